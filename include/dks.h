@@ -1,0 +1,180 @@
+/*
+ * dks.h -- C ABI of libdks, the MI355X (gfx950) hot path of LOBPCG-F for the
+ * four-component planewave Dirac-Kohn-Sham eigenproblem (Lin, Shao, E,
+ * "Efficient iterative method for solving the Dirac-Kohn-Sham density
+ * functional theory").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units are Hartree atomic units (m = 1, e = hbar = 1); every energy passed in
+ * or out is shifted by -c^2, the convention of the paper's Sec. 4, so the
+ * positive continuum starts at 0 and the negative band sits near -2c^2.
+ *
+ * A spinor block X holding nb bands is device memory laid out [nb][4][N]:
+ * band-major, then the four components (phi_up, phi_dn, chi_up, chi_dn) --
+ * the large and small two-spinors of Sec. 2.1 -- then the N planewaves of the
+ * system's sphere in the library's order (exported by dks_basis_info).  Complex
+ * numbers are interleaved (re, im): complex128 for DKS_FP64, complex64 for
+ * DKS_FP32.  Rows of one band are contiguous, so band j starts at
+ * X + j * 4 * N complex elements.
+ *
+ * Every call returns a dks_status: 0 on success, < 0 on error (outputs are then
+ * unspecified), > 0 for a warning with valid outputs.  dks_last_error() returns
+ * a message for the calling thread's last failure.  Device pointers must be
+ * allocated on the device the basis was created on; `stream` is a hipStream_t
+ * (NULL = the default stream) and every call is asynchronous on it unless
+ * stated otherwise.  Calls on one basis must not overlap on different streams.
+ */
+#ifndef DKS_H
+#define DKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int dks_status;
+#define DKS_OK          0
+#define DKS_EINVAL     (-1)   /* bad argument (null, size, grid smaller than the sphere...) */
+#define DKS_ENOMEM     (-2)   /* device or host allocation failed */
+#define DKS_EHIP       (-3)   /* a HIP runtime call failed */
+#define DKS_ECHOL      (-4)   /* Gram matrix of the start block not positive definite */
+#define DKS_ECOLLAPSE  (-5)   /* a Ritz value fell below -c^2 (variational collapse) */
+#define DKS_WNOTCONV    1     /* iteration limit reached; outputs valid, residuals reported */
+
+typedef enum { DKS_FP64 = 0, DKS_FP32 = 1 } dks_prec;
+
+typedef enum {
+  DKS_MODE_FP64 = 0,          /* every step in FP64 */
+  DKS_MODE_MIXED_FP32 = 1,    /* FP32 operator, filter, Gram and updates; FP64 Rayleigh-Ritz;
+                                 then FP64 polish iterations to the requested tolerance */
+  DKS_MODE_MIXED_BF16GRAM = 2 /* as MIXED_FP32 but the Gram products take BF16 inputs with
+                                 FP32 accumulation on the matrix cores */
+} dks_mode;
+
+/* One (atom, l) block of separable projectors of Eq. (HGH): couplings of the
+ * j = l + 1/2 channel (d_plus) and of the j = l - 1/2 channel (d_minus), each a
+ * real symmetric n_rad x n_rad matrix (row-major, Ha).  Radial functions are
+ * (q r_l)^(2(i-1)) exp(-q^2 r_l^2 / 2), i = 1..n_rad, times the complex solid
+ * harmonic |q|^l Y_lm, times exp(-i q.tau_atom); each (atom, l, i) set of 2l+1
+ * functions is scaled by one common factor so that the mean over m of their
+ * squared 2-norms over the planewave sphere is 1.  0 <= l <= 3, 1 <= n_rad <= 3. */
+typedef struct {
+  int atom;
+  int l;
+  int n_rad;
+  double r_l;
+  const double *d_plus;
+  const double *d_minus;
+} dks_proj_group;
+
+/* Physical description of one system (Sec. 2: Eq. (vDKS) at fixed potential).
+ * All pointers are host memory owned by the caller and only read during
+ * dks_init_basis.  One description with nk k-points yields nk consecutive
+ * system indices that share the sampled local potential. */
+typedef struct {
+  double lattice[9];          /* rows a1, a2, a3 (bohr), any non-singular cell */
+  int nk;                     /* number of k-points (>= 1) */
+  const double *kpts;         /* nk x 3 Cartesian (bohr^-1); {0,0,0} is Gamma */
+  double ecut;                /* Ha: basis is { G : |k + G|^2 / 2 <= ecut } (Sec. 2.3) */
+  int grid[3];                /* FFT grid N1, N2, N3; each a product of 2, 3, 5; <= 512 */
+  double c;                   /* speed of light (137.036 in a.u.) */
+  const double *v_loc;        /* N1*N2*N3 real values of the local potential at
+                                 r_j = (j1/N1) a1 + (j2/N2) a2 + (j3/N3) a3, j3 fastest */
+  int natom;
+  const double *tau;          /* natom x 3 Cartesian positions (bohr) */
+  int nproj_groups;
+  const dks_proj_group *proj; /* may be NULL when nproj_groups == 0 */
+} dks_system_desc;
+
+typedef struct dks_basis dks_basis;   /* opaque; owned by the library */
+
+/* Build the planewave basis, the projector tables, FFT plans and device copies
+ * of the potential for every (description, k-point) pair, on device `device`.
+ * The sphere is ordered by xy-column (n1, n2) lexicographically, then n3
+ * ascending.  Errors: DKS_EINVAL for a null pointer, an empty sphere, a grid that
+ * is not 2-3-5 smooth or too small to hold the sphere (N_d <= 2 max|n_d|), l or
+ * n_rad out of range; DKS_ENOMEM / DKS_EHIP from the device.  On success *out
+ * owns everything it allocated until dks_free_basis. */
+dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, dks_basis **out);
+
+/* Number of systems (sum of nk over the descriptions). */
+int dks_num_systems(const dks_basis *b);
+
+/* Sphere size N of system `sys`; optionally its FFT grid (3 ints) and the
+ * Miller index triple of every planewave in the library's order (N x 3 ints,
+ * caller-owned host buffer).  Synchronous, host only. */
+dks_status dks_basis_info(const dks_basis *b, int sys, int *npw, int *grid3, int *miller);
+
+/* HX = H X for a block of nb bands (Eq. (vDKS) with V_hxc folded into the local
+ * potential, shifted by -c^2): the per-planewave 4x4 free-Dirac block, the local
+ * potential through zero-padded 3D FFTs on the system grid, and the separable
+ * spin-orbit projectors applied identically to the large and the small
+ * two-spinor.  X and HX are device blocks [nb][4][N] of precision `prec`; they
+ * must not overlap.  The library owns its FFT scratch (grown on demand). */
+dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb,
+                       dks_prec prec, void *stream);
+
+/* FY = f(H) Y with f(E) = (E - C)^2 / Omega^2, the filter of Eq. (filter)
+ * (two applications of H).  Y and FY must not overlap. */
+dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int nb,
+                            double C, double Omega, dks_prec prec, void *stream);
+
+/* The library's default filter constants for system `sys`: C at the middle of
+ * the free negative band moved by the mean local potential, Omega = (an upper
+ * bound of the positive band) - C, so that f <= 1 on the positive band (the
+ * paper asks for C in the negative continuum and f = 1 at the top of the
+ * positive band, Sec. 3.1, without giving values).  Host only. */
+dks_status dks_filter_constants(const dks_basis *b, int sys, double *C, double *Omega);
+
+typedef struct {
+  double C, Omega;      /* filter constants; NaN selects dks_filter_constants */
+  int n_init;           /* initial filter applications (Alg. 1 lines 1-3); paper: 3 then 1 */
+  int n_iter;           /* maximum iterations of the main loop */
+  double tol;           /* convergence: 2-norm of every residual column < tol (Ha) */
+  int mode;             /* dks_mode */
+  double mixed_tol;     /* mixed modes: residual at which the reduced-precision stage stops */
+  int mixed_iter;       /* mixed modes: cap on reduced-precision iterations */
+  int kinetic_balance;  /* 1: rebuild the small components of X0 from the large ones,
+                           chi = c sigma.q phi / (E_q + c^2) (Eq. (RKB)) */
+  int use_filter;       /* 1: LOBPCG-F; 0: standard LOBPCG (the paper's comparison) */
+} dks_solve_opts;
+
+typedef struct {
+  int iterations;       /* main-loop iterations, all stages */
+  int iters_reduced;    /* of which in the reduced-precision stage */
+  int converged;        /* 1 if every residual < tol */
+  int n_converged;
+  int h_applies;        /* band-applications of H (one per band per apply) */
+  int basis_drops;      /* Y/P directions removed as numerically dependent */
+  int p_restarts;       /* iterations whose P block was dropped */
+  double min_ritz;      /* smallest Ritz value seen (collapse monitor) */
+  double max_resnorm;   /* largest final residual norm */
+  double C, Omega;      /* filter constants used */
+} dks_solve_info;
+
+void dks_default_opts(dks_solve_opts *o);
+
+/* Algorithm 1 (LOBPCG-F) for the n lowest positive-band eigenpairs of system
+ * `sys`.  X: device complex128 block [n][4][N]; in: the start block X0, out: the
+ * eigenvectors (unit 2-norm).  lambda: host array of n eigenvalues (ascending,
+ * shifted by -c^2).  resnorms: optional host array of n final residual norms.
+ * info: optional.  Synchronous on `stream`.  The library allocates its workspace
+ * (about 13 blocks of n bands) on first use and keeps it for reuse.
+ * Returns DKS_WNOTCONV if n_iter was reached, DKS_ECOLLAPSE if a Ritz value fell
+ * below -c^2, DKS_ECHOL if the start block is numerically rank deficient. */
+dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lambda,
+                             double *resnorms, const dks_solve_opts *opts,
+                             dks_solve_info *info, void *stream);
+
+/* Release everything owned by the basis (after synchronising its device). */
+void dks_free_basis(dks_basis *b);
+
+/* Message describing the calling thread's last error ("" if none). */
+const char *dks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DKS_H */

@@ -36,8 +36,13 @@ lexicographic Miller order.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft as sfft
+
+# FFTs use every host core (a library primitive; the arithmetic is unchanged)
+_WORKERS = os.cpu_count() or 1
 
 def reciprocal_lattice(lattice: np.ndarray) -> np.ndarray:
     """Rows b_i with a_i . b_j = 2 pi delta_ij."""
@@ -284,15 +289,17 @@ class DKSOperator:
         out[:, 1] = c * (sp * cu - qz * cd)
         out[:, 2] = c * (qz * pu + sm * pd) - 2.0 * c * c * cu
         out[:, 3] = c * (sp * pu - qz * pd) - 2.0 * c * c * cd
-        F = np.zeros(self.grid, dtype=np.complex128)
+        F = np.zeros((4,) + self.grid, dtype=np.complex128)
         for b in range(X.shape[0]):
+            F[...] = 0.0
             for s in range(4):
-                F[...] = 0.0
-                F[self.slot] = X[b, s]
-                f = np.fft.ifftn(F) * self.ng          # psi(r_j) = sum_G psi(G) e^{i G.r_j}
-                f *= self.v
-                G = np.fft.fftn(f) / self.ng
-                out[b, s] += G[self.slot]
+                F[s][self.slot] = X[b, s]
+            # psi(r_j) = sum_G psi(G) e^{i G.r_j}  (inverse DFT without the 1/N_g)
+            f = sfft.ifftn(F, axes=(1, 2, 3), norm="forward", workers=_WORKERS)
+            f *= self.v[None]
+            G = sfft.fftn(f, axes=(1, 2, 3), norm="forward", workers=_WORKERS)   # includes 1/N_g
+            for s in range(4):
+                out[b, s] += G[s][self.slot]
         for g, bm, w in self.groups:
             np_ = bm.shape[1]
             coef = np.einsum("gp,bsg->bsp", bm.conj(), X)        # (n, 4, np)

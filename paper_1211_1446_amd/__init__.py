@@ -1,0 +1,12 @@
+"""MI355X (gfx950) hot path of LOBPCG-F for the four-component planewave
+Dirac-Kohn-Sham eigenproblem.
+
+The work runs in ``libdks.so`` (hand-written HIP kernels behind the C ABI of
+``include/dks.h``); this package only marshals arguments.  Importing it loads
+the library and raises if it has not been built: there is no fallback.
+"""
+from ._lib import (  # noqa: F401
+    DKS_FP32, DKS_FP64, MODE_FP64, MODE_MIXED_BF16GRAM, MODE_MIXED_FP32, Basis, DksError,
+    apply_filter, apply_H, basis_info, default_opts, filter_constants, free_basis, init_basis,
+    library_path, lobpcgf_solve, num_systems,
+)

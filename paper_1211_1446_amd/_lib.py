@@ -1,0 +1,261 @@
+"""ctypes binding of libdks (include/dks.h).  Argument marshalling only.
+
+Device blocks are torch tensors on the GPU ([n][4][N] complex128 or complex64,
+contiguous); the stream is torch's current stream unless one is passed.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libdks.so")
+
+DKS_FP64, DKS_FP32 = 0, 1
+MODE_FP64, MODE_MIXED_FP32, MODE_MIXED_BF16GRAM = 0, 1, 2
+
+_STATUS = {0: "DKS_OK", -1: "DKS_EINVAL", -2: "DKS_ENOMEM", -3: "DKS_EHIP", -4: "DKS_ECHOL",
+           -5: "DKS_ECOLLAPSE", 1: "DKS_WNOTCONV"}
+
+
+class DksError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _ProjGroup(ct.Structure):
+    _fields_ = [("atom", ct.c_int), ("l", ct.c_int), ("n_rad", ct.c_int), ("r_l", ct.c_double),
+                ("d_plus", ct.POINTER(ct.c_double)), ("d_minus", ct.POINTER(ct.c_double))]
+
+
+class _SystemDesc(ct.Structure):
+    _fields_ = [("lattice", ct.c_double * 9), ("nk", ct.c_int), ("kpts", ct.POINTER(ct.c_double)),
+                ("ecut", ct.c_double), ("grid", ct.c_int * 3), ("c", ct.c_double),
+                ("v_loc", ct.POINTER(ct.c_double)), ("natom", ct.c_int),
+                ("tau", ct.POINTER(ct.c_double)), ("nproj_groups", ct.c_int),
+                ("proj", ct.POINTER(_ProjGroup))]
+
+
+class SolveOpts(ct.Structure):
+    _fields_ = [("C", ct.c_double), ("Omega", ct.c_double), ("n_init", ct.c_int),
+                ("n_iter", ct.c_int), ("tol", ct.c_double), ("mode", ct.c_int),
+                ("mixed_tol", ct.c_double), ("mixed_iter", ct.c_int),
+                ("kinetic_balance", ct.c_int), ("use_filter", ct.c_int)]
+
+
+class SolveInfo(ct.Structure):
+    _fields_ = [("iterations", ct.c_int), ("iters_reduced", ct.c_int), ("converged", ct.c_int),
+                ("n_converged", ct.c_int), ("h_applies", ct.c_int), ("basis_drops", ct.c_int),
+                ("p_restarts", ct.c_int), ("min_ritz", ct.c_double), ("max_resnorm", ct.c_double),
+                ("C", ct.c_double), ("Omega", ct.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def library_path() -> str:
+    return _LIBPATH
+
+
+def _load():
+    if not os.path.exists(_LIBPATH):
+        raise ImportError(f"libdks.so not built at {_LIBPATH}; run __graft_entry__.build()")
+    lib = ct.CDLL(_LIBPATH)
+    vp, i, d = ct.c_void_p, ct.c_int, ct.c_double
+    lib.dks_init_basis.argtypes = [ct.POINTER(_SystemDesc), i, i, ct.POINTER(vp)]
+    lib.dks_num_systems.argtypes = [vp]
+    lib.dks_basis_info.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
+    lib.dks_apply_H.argtypes = [vp, i, vp, vp, i, i, vp]
+    lib.dks_apply_filter.argtypes = [vp, i, vp, vp, i, d, d, i, vp]
+    lib.dks_filter_constants.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(d)]
+    lib.dks_default_opts.argtypes = [ct.POINTER(SolveOpts)]
+    lib.dks_default_opts.restype = None
+    lib.dks_lobpcgf_solve.argtypes = [vp, i, i, vp, ct.POINTER(d), ct.POINTER(d),
+                                      ct.POINTER(SolveOpts), ct.POINTER(SolveInfo), vp]
+    lib.dks_free_basis.argtypes = [vp]
+    lib.dks_free_basis.restype = None
+    lib.dks_last_error.restype = ct.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int, allow_warning: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_warning):
+        raise DksError(rc, _lib.dks_last_error().decode(errors="replace"))
+    return rc
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+class Basis:
+    """Owns a dks_basis handle and the host arrays it was built from."""
+
+    def __init__(self, handle: int, keep):
+        self.handle = ct.c_void_p(handle)
+        self._keep = keep
+
+    def close(self):
+        if self.handle:
+            _lib.dks_free_basis(self.handle)
+            self.handle = ct.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def init_basis(systems: Sequence, device: int = 0) -> Basis:
+    """dks_init_basis over objects with the fields of dks_system_desc
+    (lattice, kpts, ecut, grid, c, v_loc, tau, proj[atom, l, n_rad, r_l, d_plus, d_minus])."""
+    keep = []
+    descs = (_SystemDesc * len(systems))()
+    for di, s in enumerate(systems):
+        D = descs[di]
+        lat = np.ascontiguousarray(s.lattice, dtype=np.float64).reshape(9)
+        for j in range(9):
+            D.lattice[j] = float(lat[j])
+        k = np.ascontiguousarray(s.kpts, dtype=np.float64).reshape(-1, 3)
+        v = np.ascontiguousarray(s.v_loc, dtype=np.float64)
+        tau = np.ascontiguousarray(s.tau, dtype=np.float64).reshape(-1, 3)
+        keep += [k, v, tau]
+        D.nk = k.shape[0]
+        D.kpts = _dptr(k)
+        D.ecut = float(s.ecut)
+        for j in range(3):
+            D.grid[j] = int(s.grid[j])
+        D.c = float(s.c)
+        D.v_loc = _dptr(v)
+        D.natom = tau.shape[0]
+        D.tau = _dptr(tau)
+        groups = (_ProjGroup * max(1, len(s.proj)))()
+        for gi, g in enumerate(s.proj):
+            dp = np.ascontiguousarray(g.d_plus, dtype=np.float64)
+            dm = np.ascontiguousarray(g.d_minus, dtype=np.float64)
+            keep += [dp, dm]
+            groups[gi].atom, groups[gi].l, groups[gi].n_rad = int(g.atom), int(g.l), int(g.n_rad)
+            groups[gi].r_l = float(g.r_l)
+            groups[gi].d_plus, groups[gi].d_minus = _dptr(dp), _dptr(dm)
+        keep.append(groups)
+        D.nproj_groups = len(s.proj)
+        D.proj = ct.cast(groups, ct.POINTER(_ProjGroup))
+    keep.append(descs)
+    h = ct.c_void_p()
+    _check(_lib.dks_init_basis(descs, len(systems), device, ct.byref(h)))
+    return Basis(h.value, keep)
+
+
+def free_basis(b: Basis) -> None:
+    b.close()
+
+
+def num_systems(b: Basis) -> int:
+    return int(_lib.dks_num_systems(b.handle))
+
+
+def basis_info(b: Basis, sys: int = 0, miller: bool = True):
+    """(N, grid, miller (N x 3) or None)."""
+    n = ct.c_int()
+    grid = (ct.c_int * 3)()
+    _check(_lib.dks_basis_info(b.handle, sys, ct.byref(n), grid, None))
+    mil = None
+    if miller:
+        mil = np.zeros((n.value, 3), dtype=np.int32)
+        _check(_lib.dks_basis_info(b.handle, sys, ct.byref(n), grid,
+                                   mil.ctypes.data_as(ct.POINTER(ct.c_int))))
+    return n.value, tuple(grid), mil
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ct.c_void_p(stream.cuda_stream)
+    return ct.c_void_p(stream)
+
+
+def _prec_of(t) -> int:
+    import torch
+    if t.dtype == torch.complex128:
+        return DKS_FP64
+    if t.dtype == torch.complex64:
+        return DKS_FP32
+    raise TypeError("blocks must be complex128 or complex64")
+
+
+def _check_block(t, nb, N):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("blocks must be contiguous device tensors")
+    if t.numel() < nb * 4 * N:
+        raise ValueError("block smaller than nb x 4 x N")
+
+
+def apply_H(b: Basis, sys: int, X, HX, nb: Optional[int] = None, stream=None) -> None:
+    """HX = H X (dks_apply_H); X, HX torch tensors [nb][4][N]."""
+    N, _, _ = basis_info(b, sys, miller=False)
+    nb = X.shape[0] if nb is None else nb
+    _check_block(X, nb, N)
+    _check_block(HX, nb, N)
+    if HX.dtype != X.dtype:
+        raise TypeError("X and HX precision differ")
+    _check(_lib.dks_apply_H(b.handle, sys, ct.c_void_p(X.data_ptr()), ct.c_void_p(HX.data_ptr()),
+                            nb, _prec_of(X), _stream(stream)))
+
+
+def apply_filter(b: Basis, sys: int, Y, FY, C: float, Omega: float, nb: Optional[int] = None,
+                 stream=None) -> None:
+    """FY = (H - C)^2 Y / Omega^2 (dks_apply_filter)."""
+    N, _, _ = basis_info(b, sys, miller=False)
+    nb = Y.shape[0] if nb is None else nb
+    _check_block(Y, nb, N)
+    _check_block(FY, nb, N)
+    _check(_lib.dks_apply_filter(b.handle, sys, ct.c_void_p(Y.data_ptr()),
+                                 ct.c_void_p(FY.data_ptr()), nb, float(C), float(Omega),
+                                 _prec_of(Y), _stream(stream)))
+
+
+def filter_constants(b: Basis, sys: int = 0):
+    C, Om = ct.c_double(), ct.c_double()
+    _check(_lib.dks_filter_constants(b.handle, sys, ct.byref(C), ct.byref(Om)))
+    return C.value, Om.value
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    _lib.dks_default_opts(ct.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def lobpcgf_solve(b: Basis, sys: int, n: int, X, opts: Optional[SolveOpts] = None, stream=None,
+                  allow_notconv: bool = True):
+    """Algorithm 1 on the complex128 device block X (in: X0, out: eigenvectors).
+
+    Returns (eigenvalues (n,), residual norms (n,), info dict, status)."""
+    import torch
+    if X.dtype != torch.complex128:
+        raise TypeError("X must be complex128")
+    N, _, _ = basis_info(b, sys, miller=False)
+    _check_block(X, n, N)
+    lam = np.zeros(n)
+    res = np.zeros(n)
+    info = SolveInfo()
+    o = opts if opts is not None else default_opts()
+    rc = _lib.dks_lobpcgf_solve(b.handle, sys, n, ct.c_void_p(X.data_ptr()), _dptr(lam), _dptr(res),
+                                ct.byref(o), ct.byref(info), _stream(stream))
+    _check(rc, allow_warning=allow_notconv)
+    return lam, res, info.as_dict(), rc

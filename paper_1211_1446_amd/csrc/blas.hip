@@ -1,0 +1,418 @@
+// Block linear algebra on tall spinor blocks (rows of length K = 4N):
+//  gemm_ip   small Gram-type products  out[i][j] = sum_k conj(A_i[k]) B_j[k]
+//            on the matrix cores (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32),
+//            split along k over many workgroups, partial sums reduced in FP64;
+//  gemm_up   block updates  out_j[k] = sum_i V[i][j] A_i[k] (+ beta out_j[k]);
+//  residuals, column norms, gathers and conversions.
+#include "dks_internal.h"
+#include "fft_device.h"
+
+namespace dks {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using acc = d4;
+  __device__ static acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // lane l, slot v holds D[4 v + l / 16][l % 16]
+  __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  using acc = f4;
+  __device__ static acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // lane l, slot v holds D[4 (l / 16) + v][l % 16]
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int kIpTile = 64;   // output tile per workgroup (4 waves of 32 x 32)
+constexpr int kIpKT = 16;     // complex k values staged per step
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__restrict__ A,
+                                                 const int64_t *__restrict__ aoff, int M,
+                                                 const typename CT<T>::c *__restrict__ B,
+                                                 const int64_t *__restrict__ boff, int Nn,
+                                                 const typename CT<T>::c *__restrict__ B2,
+                                                 int64_t K, int64_t kchunk,
+                                                 double2 *__restrict__ part,
+                                                 double2 *__restrict__ part2) {
+  using C = typename CT<T>::c;
+  using MF = Mfma<T>;
+  using acc_t = typename MF::acc;
+  constexpr int LD = kIpKT + 1;
+  __shared__ C As[kIpTile * LD];
+  __shared__ C Bs[kIpTile * LD];
+  __shared__ C B2s[kIpTile * LD];
+  const bool two = (B2 != nullptr);
+  const int tm = blockIdx.x * kIpTile, tn = blockIdx.y * kIpTile;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  // loader mapping: 4 threads per row, 4 consecutive complex each
+  const int lrow = tid >> 2, lk = (tid & 3) * 4;
+  const C *arow = nullptr, *brow = nullptr, *b2row = nullptr;
+  if (tm + lrow < M) arow = A + (aoff ? aoff[tm + lrow] : (int64_t)(tm + lrow) * K);
+  if (tn + lrow < Nn) {
+    int64_t o = boff ? boff[tn + lrow] : (int64_t)(tn + lrow) * K;
+    brow = B + o;
+    if (two) b2row = B2 + o;
+  }
+  acc_t re[2][2], im[2][2], re2[2][2], im2[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = acc_t{0, 0, 0, 0};
+      im[i][j] = acc_t{0, 0, 0, 0};
+      re2[i][j] = acc_t{0, 0, 0, 0};
+      im2[i][j] = acc_t{0, 0, 0, 0};
+    }
+  for (int64_t k0 = kb; k0 < ke; k0 += kIpKT) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int64_t k = k0 + lk + u;
+      bool ok = k < ke;
+      As[lrow * LD + lk + u] = (arow && ok) ? arow[k] : C{0, 0};
+      Bs[lrow * LD + lk + u] = (brow && ok) ? brow[k] : C{0, 0};
+      if (two) B2s[lrow * LD + lk + u] = (b2row && ok) ? b2row[k] : C{0, 0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kIpKT / 4; ++s) {
+      const int kk = s * 4 + (lane >> 4);
+      C a[2], bb[2], b2[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = As[(wm + i * 16 + (lane & 15)) * LD + kk];
+        bb[i] = Bs[(wn + i * 16 + (lane & 15)) * LD + kk];
+        if (two) b2[i] = B2s[(wn + i * 16 + (lane & 15)) * LD + kk];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          // conj(a) b: re += ar br + ai bi, im += ar bi - ai br
+          re[i][j] = MF::mma(a[i].x, bb[j].x, re[i][j]);
+          re[i][j] = MF::mma(a[i].y, bb[j].y, re[i][j]);
+          im[i][j] = MF::mma(a[i].x, bb[j].y, im[i][j]);
+          im[i][j] = MF::mma(-a[i].y, bb[j].x, im[i][j]);
+          if (two) {
+            re2[i][j] = MF::mma(a[i].x, b2[j].x, re2[i][j]);
+            re2[i][j] = MF::mma(a[i].y, b2[j].y, re2[i][j]);
+            im2[i][j] = MF::mma(a[i].x, b2[j].y, im2[i][j]);
+            im2[i][j] = MF::mma(-a[i].y, b2[j].x, im2[i][j]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  double2 *p1 = part + (size_t)blockIdx.z * M * Nn;
+  double2 *p2 = two ? part2 + (size_t)blockIdx.z * M * Nn : nullptr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r = tm + wm + i * 16 + MF::row(lane, v);
+        int c = tn + wn + j * 16 + (lane & 15);
+        if (r < M && c < Nn) {
+          p1[(size_t)r * Nn + c] = make_double2((double)re[i][j][v], (double)im[i][j][v]);
+          if (two) p2[(size_t)r * Nn + c] = make_double2((double)re2[i][j][v], (double)im2[i][j][v]);
+        }
+      }
+}
+
+__global__ void k_reduce_part(const double2 *__restrict__ part, int nsplit, int M, int Nn,
+                              double2 *__restrict__ out, int ldo) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * Nn) return;
+  double re = 0, im = 0;
+  for (int z = 0; z < nsplit; ++z) {
+    double2 v = part[(size_t)z * M * Nn + e];
+    re += v.x;
+    im += v.y;
+  }
+  int i = e / Nn, j = e - (e / Nn) * Nn;
+  out[(size_t)i * ldo + j] = make_double2(re, im);
+}
+
+template <typename T>
+void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
+             int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
+             DevBuf &part, hipStream_t st) {
+  if (M <= 0 || Nn <= 0) return;
+  const int tm = (M + kIpTile - 1) / kIpTile, tn = (Nn + kIpTile - 1) / kIpTile;
+  const int tiles = tm * tn;
+  int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
+  int64_t nsplit = (1024 + tiles - 1) / tiles;
+  nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
+  int64_t kchunk = (K + nsplit - 1) / nsplit;
+  kchunk = (kchunk + kIpKT - 1) / kIpKT * kIpKT;
+  nsplit = (K + kchunk - 1) / kchunk;
+  if (nsplit < 1) nsplit = 1;
+  const int nmat = B2 ? 2 : 1;
+  part.ensure(sizeof(double2) * (size_t)nsplit * M * Nn * nmat);
+  double2 *p1 = part.as<double2>();
+  double2 *p2 = B2 ? p1 + (size_t)nsplit * M * Nn : nullptr;
+  dim3 grid(tm, tn, (unsigned)nsplit);
+  hipLaunchKernelGGL(k_gemm_ip<T>, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk,
+                     p1, p2);
+  DKS_HIP(hipGetLastError());
+  int nel = M * Nn;
+  hipLaunchKernelGGL(k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p1, (int)nsplit, M,
+                     Nn, out, ldo);
+  DKS_HIP(hipGetLastError());
+  if (B2) {
+    hipLaunchKernelGGL(k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p2, (int)nsplit,
+                       M, Nn, out2, ldo);
+    DKS_HIP(hipGetLastError());
+  }
+}
+
+template void gemm_ip<double>(const double2 *, const int64_t *, int, const double2 *,
+                              const int64_t *, int, const double2 *, int64_t, double2 *,
+                              double2 *, int, DevBuf &, hipStream_t);
+template void gemm_ip<float>(const float2 *, const int64_t *, int, const float2 *,
+                             const int64_t *, int, const float2 *, int64_t, double2 *, double2 *,
+                             int, DevBuf &, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// block update
+// ---------------------------------------------------------------------------
+constexpr int kUpJT = 16;
+constexpr int kUpICH = 64;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gemm_up(const typename CT<T>::c *__restrict__ A,
+                                                 const int64_t *__restrict__ aoff, int m,
+                                                 const double2 *__restrict__ V, int ldv, int n,
+                                                 int64_t K, typename CT<T>::c *__restrict__ out,
+                                                 int64_t ldo, T beta) {
+  using C = typename CT<T>::c;
+  __shared__ C Vs[kUpICH * kUpJT];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = blockIdx.y * kUpJT;
+  C acc[kUpJT];
+#pragma unroll
+  for (int j = 0; j < kUpJT; ++j) acc[j] = C{0, 0};
+  for (int i0 = 0; i0 < m; i0 += kUpICH) {
+    const int ic = min(kUpICH, m - i0);
+    for (int e = threadIdx.x; e < kUpICH * kUpJT; e += blockDim.x) {
+      int ii = e / kUpJT, jj = e - (e / kUpJT) * kUpJT;
+      double2 v = (ii < ic && j0 + jj < n) ? V[(size_t)(i0 + ii) * ldv + j0 + jj] : make_double2(0, 0);
+      Vs[e] = C{(T)v.x, (T)v.y};
+    }
+    __syncthreads();
+    if (k < K) {
+      for (int ii = 0; ii < ic; ++ii) {
+        const int i = i0 + ii;
+        C a = A[(aoff ? aoff[i] : (int64_t)i * K) + k];
+#pragma unroll
+        for (int jj = 0; jj < kUpJT; ++jj) {
+          C v = Vs[ii * kUpJT + jj];
+          acc[jj].x += v.x * a.x - v.y * a.y;
+          acc[jj].y += v.x * a.y + v.y * a.x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (k >= K) return;
+#pragma unroll
+  for (int jj = 0; jj < kUpJT; ++jj) {
+    if (j0 + jj < n) {
+      C *o = out + (size_t)(j0 + jj) * ldo + k;
+      C r = acc[jj];
+      if (beta != T(0)) {
+        C ov = *o;
+        r.x += beta * ov.x;
+        r.y += beta * ov.y;
+      }
+      *o = r;
+    }
+  }
+}
+
+template <typename T>
+void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int ldv, int n,
+             int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st) {
+  if (n <= 0 || K <= 0) return;
+  dim3 grid((unsigned)((K + 255) / 256), (n + kUpJT - 1) / kUpJT);
+  hipLaunchKernelGGL(k_gemm_up<T>, grid, dim3(256), 0, st, A, aoff, m, V, ldv, n, K, out, ldo,
+                     (T)beta);
+  DKS_HIP(hipGetLastError());
+}
+template void gemm_up<double>(const double2 *, const int64_t *, int, const double2 *, int, int,
+                              int64_t, double2 *, int64_t, double, hipStream_t);
+template void gemm_up<float>(const float2 *, const int64_t *, int, const double2 *, int, int,
+                             int64_t, float2 *, int64_t, double, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// residuals and norms
+// ---------------------------------------------------------------------------
+__device__ double block_sum(double v) {
+  __shared__ double red[16];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+constexpr int kRedChunk = 8192;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_residual(const typename CT<T>::c *__restrict__ X,
+                                                  const typename CT<T>::c *__restrict__ HX,
+                                                  const double *__restrict__ lam, int64_t K,
+                                                  typename CT<T>::c *__restrict__ R,
+                                                  double *__restrict__ part, int nchunk) {
+  using C = typename CT<T>::c;
+  const int j = blockIdx.y;
+  const T l = (T)lam[j];
+  const int64_t b = (int64_t)blockIdx.x * kRedChunk;
+  const int64_t e = min(K, b + kRedChunk);
+  const C *x = X + (size_t)j * K;
+  const C *hx = HX + (size_t)j * K;
+  C *r = R + (size_t)j * K;
+  double s = 0;
+  for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+    C xv = x[k], hv = hx[k];
+    C rv = C{hv.x - l * xv.x, hv.y - l * xv.y};
+    r[k] = rv;
+    s += (double)rv.x * rv.x + (double)rv.y * rv.y;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[(size_t)j * nchunk + blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_norm2(const typename CT<T>::c *__restrict__ X, int64_t K,
+                                               double *__restrict__ part, int nchunk) {
+  using C = typename CT<T>::c;
+  const int j = blockIdx.y;
+  const int64_t b = (int64_t)blockIdx.x * kRedChunk;
+  const int64_t e = min(K, b + kRedChunk);
+  const C *x = X + (size_t)j * K;
+  double s = 0;
+  for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+    C v = x[k];
+    s += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[(size_t)j * nchunk + blockIdx.x] = s;
+}
+
+__global__ void k_sum_rows(const double *__restrict__ part, int n, int nchunk,
+                           double *__restrict__ out) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0;
+  for (int c = 0; c < nchunk; ++c) s += part[(size_t)j * nchunk + c];
+  out[j] = s;
+}
+
+template <typename T>
+void residual(const cplx<T> *X, const cplx<T> *HX, const double *lam, int n, int64_t K,
+              cplx<T> *R, double *norm2, DevBuf &part, hipStream_t st) {
+  if (n <= 0) return;
+  int nchunk = (int)((K + kRedChunk - 1) / kRedChunk);
+  part.ensure(sizeof(double) * (size_t)n * nchunk);
+  hipLaunchKernelGGL(k_residual<T>, dim3(nchunk, n), dim3(256), 0, st, X, HX, lam, K, R,
+                     part.as<double>(), nchunk);
+  DKS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_rows, dim3((n + 63) / 64), dim3(64), 0, st, part.as<double>(), n,
+                     nchunk, norm2);
+  DKS_HIP(hipGetLastError());
+}
+template void residual<double>(const double2 *, const double2 *, const double *, int, int64_t,
+                               double2 *, double *, DevBuf &, hipStream_t);
+template void residual<float>(const float2 *, const float2 *, const double *, int, int64_t,
+                              float2 *, double *, DevBuf &, hipStream_t);
+
+template <typename T>
+void col_norm2(const cplx<T> *X, int n, int64_t K, double *norm2, DevBuf &part, hipStream_t st) {
+  if (n <= 0) return;
+  int nchunk = (int)((K + kRedChunk - 1) / kRedChunk);
+  part.ensure(sizeof(double) * (size_t)n * nchunk);
+  hipLaunchKernelGGL(k_norm2<T>, dim3(nchunk, n), dim3(256), 0, st, X, K, part.as<double>(),
+                     nchunk);
+  DKS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_rows, dim3((n + 63) / 64), dim3(64), 0, st, part.as<double>(), n,
+                     nchunk, norm2);
+  DKS_HIP(hipGetLastError());
+}
+template void col_norm2<double>(const double2 *, int, int64_t, double *, DevBuf &, hipStream_t);
+template void col_norm2<float>(const float2 *, int, int64_t, double *, DevBuf &, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// gathers, conversions, scaling
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_gather(const typename CT<T>::c *__restrict__ src, const int *__restrict__ idx,
+                         int64_t K, typename CT<T>::c *__restrict__ dst) {
+  const int i = blockIdx.y;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  dst[(size_t)i * K + k] = src[(size_t)idx[i] * K + k];
+}
+template <typename T>
+void gather_rows(const cplx<T> *src, const int *idx, int m, int64_t K, cplx<T> *dst,
+                 hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((K + 255) / 256), m), dim3(256), 0, st, src, idx,
+                     K, dst);
+  DKS_HIP(hipGetLastError());
+}
+template void gather_rows<double>(const double2 *, const int *, int, int64_t, double2 *, hipStream_t);
+template void gather_rows<float>(const float2 *, const int *, int, int64_t, float2 *, hipStream_t);
+
+template <typename Ts, typename Td>
+__global__ void k_convert(const typename CT<Ts>::c *__restrict__ s, typename CT<Td>::c *__restrict__ d,
+                          int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) d[i] = typename CT<Td>::c{(Td)s[i].x, (Td)s[i].y};
+}
+template <typename Ts, typename Td>
+void convert(const cplx<Ts> *src, cplx<Td> *dst, int64_t count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL((k_convert<Ts, Td>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                     src, dst, count);
+  DKS_HIP(hipGetLastError());
+}
+template void convert<double, float>(const double2 *, float2 *, int64_t, hipStream_t);
+template void convert<float, double>(const float2 *, double2 *, int64_t, hipStream_t);
+
+template <typename T>
+__global__ void k_scale_rows(typename CT<T>::c *X, const double *s, int64_t K) {
+  const int i = blockIdx.y;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  T f = (T)s[i];
+  typename CT<T>::c v = X[(size_t)i * K + k];
+  X[(size_t)i * K + k] = typename CT<T>::c{v.x * f, v.y * f};
+}
+template <typename T>
+void scale_rows(cplx<T> *X, const double *s, int n, int64_t K, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale_rows<T>, dim3((unsigned)((K + 255) / 256), n), dim3(256), 0, st, X, s, K);
+  DKS_HIP(hipGetLastError());
+}
+template void scale_rows<double>(double2 *, const double *, int, int64_t, hipStream_t);
+template void scale_rows<float>(float2 *, const double *, int, int64_t, hipStream_t);
+
+}  // namespace dks

@@ -1,0 +1,201 @@
+// Internal declarations of libdks: device-side tables of one system, scratch
+// management and the kernel launchers shared by the operator, the dense
+// linear algebra and the LOBPCG-F driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dks.h"
+
+namespace dks {
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+const char *get_error();
+
+struct Error {
+  dks_status code;
+  std::string msg;
+};
+
+#define DKS_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      throw ::dks::Error{DKS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define DKS_REQUIRE(cond, code, msg)                          \
+  do {                                                        \
+    if (!(cond)) throw ::dks::Error{(code), std::string(msg)}; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <typename T> using cplx = typename cvec<T>::type;
+
+// ---------------------------------------------------------------------------
+// FFT plan of one axis
+// ---------------------------------------------------------------------------
+constexpr int kMaxPass = 8;
+struct FftPlan {
+  int n;
+  int npass;
+  int radix[kMaxPass];
+};
+FftPlan make_plan(int n);   // radices from {8, 6, 5, 4, 3, 2}; n must be 2-3-5 smooth
+
+// ---------------------------------------------------------------------------
+// device buffer (owned)
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t nbytes) {  // grow-only
+    if (nbytes <= bytes) return;
+    release();
+    if (nbytes == 0) return;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{DKS_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed"};
+    }
+    bytes = nbytes;
+  }
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+void upload(DevBuf &b, const void *host, size_t bytes);
+
+// ---------------------------------------------------------------------------
+// one system (one description at one k-point)
+// ---------------------------------------------------------------------------
+struct ProjGroupHost {
+  int atom, l, n_rad, p0, dim;   // dim = n_rad (2l+1) scalar projectors starting at p0
+  int woff;                      // offset (complex elements) of W (2 dim x 2 dim, row-major)
+};
+
+struct System {
+  // geometry
+  double lattice[9];
+  double kpt[3];
+  double ecut, c;
+  int grid[3];
+  int ng;
+  int N;              // planewaves
+  int ncol;           // xy-columns (n1, n2) of the sphere
+  int nrows;          // distinct n1 values among the columns
+  int vsrc;           // index of the shared local potential
+  // host copies
+  std::vector<int> miller;        // N x 3, library order
+  std::vector<double> q;          // N x 3
+  std::vector<int> col_off;       // ncol + 1
+  std::vector<int4> col_info;     // {n1 slot, n2 slot, n3 start, len}
+  std::vector<int> rows;          // the nrows distinct n1 slots
+  std::vector<ProjGroupHost> groups;
+  int nproj = 0;                  // scalar projectors
+  int wtotal = 0;                 // complex elements of all W blocks
+  double qmax2 = 0;
+  double nl_bound = 0;
+  // device tables
+  DevBuf d_col_off, d_col_info, d_rows, d_gmap;   // gmap: per G {local column, z slot}
+  DevBuf d_q64, d_q32;                            // SoA qx | qy | qz
+  DevBuf d_B64, d_B32;                            // [nproj][N] complex
+  DevBuf d_W64;                                   // all W blocks, complex double
+  DevBuf d_Winfo;                                 // per (group): int4 {p0, dim, woff, 0}
+  FftPlan plan[3];
+  int tile_z;                                     // xy-columns per z-FFT workgroup
+};
+
+struct Potential {
+  int grid[3];
+  double vmin, vmax, vmean;
+  DevBuf d_v64, d_v32;            // plane layout [N3][N1][N2]
+  DevBuf d_tw64[3], d_tw32[3];    // exp(-2 pi i t / n_d), t < n_d
+};
+
+}  // namespace dks
+
+struct dks_basis {
+  int device = 0;
+  std::vector<dks::System *> sys;
+  std::vector<dks::Potential *> pot;
+  // apply_H / apply_filter scratch
+  dks::DevBuf t1, nlc, nlc2, part, ftmp64, ftmp32;
+  // solver workspace (created on first solve)
+  void *solver = nullptr;
+  ~dks_basis();
+};
+
+namespace dks {
+
+// ---------------------------------------------------------------------------
+// launchers (all asynchronous on `st`)
+// ---------------------------------------------------------------------------
+// HX = scale * ((H - shift) X) for nb bands, precision T.
+template <typename T>
+void apply_h(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
+             double scale, hipStream_t st);
+
+// out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
+// rows addressed by element offsets.  M, Nn <= 512.
+template <typename T>
+void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
+             int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
+             DevBuf &part, hipStream_t st);
+
+// out_j[k] = alpha * sum_i V[i][j] A_i[k] (+ beta out_j[k]); V FP64 m x n (ld ldv).
+template <typename T>
+void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int ldv, int n,
+             int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st);
+
+// R_j = HX_j - lambda_j X_j and ||R_j||^2 (FP64) for n columns of length K.
+template <typename T>
+void residual(const cplx<T> *X, const cplx<T> *HX, const double *lam, int n, int64_t K,
+              cplx<T> *R, double *norm2, DevBuf &part, hipStream_t st);
+
+// column squared norms of n rows of length K
+template <typename T>
+void col_norm2(const cplx<T> *X, int n, int64_t K, double *norm2, DevBuf &part, hipStream_t st);
+
+// dst row i = src row idx[i] (scaled by s[i] if s != null)
+template <typename T>
+void gather_rows(const cplx<T> *src, const int *idx, int m, int64_t K, cplx<T> *dst,
+                 hipStream_t st);
+
+template <typename Ts, typename Td>
+void convert(const cplx<Ts> *src, cplx<Td> *dst, int64_t count, hipStream_t st);
+
+template <typename T>
+void scale_rows(cplx<T> *X, const double *s, int n, int64_t K, hipStream_t st);
+
+// small component from the large one by kinetic balance, in place on [n][4][N]
+void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st);
+
+// Rayleigh-Ritz on (A, S) of size nz: V (nz x nkeep, row-major ld nkeep), theta (nkeep),
+// info[0] = kept count, info[1] = status (0 ok, 1 too few kept), info[2] = dropped;
+// dinfo[0] = smallest Ritz value.  `forced_drop` (nz ints or null): 1 marks a column to skip.
+void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
+                   const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
+                   DevBuf &scratch, hipStream_t st);
+
+}  // namespace dks

@@ -1,0 +1,331 @@
+// The block DKS operator H X (shifted by -c^2) on gfx950.
+//
+// For every band and component the local potential goes through the grid in
+// three passes over a column-pruned layout T1[column][z][xy-column] that holds
+// only the xy-columns (n1, n2) crossing the planewave sphere:
+//   zfft_inv   sphere -> z lines (inverse FFT along a3)       -> T1
+//   plane      per z plane: inverse FFT along a2 (sphere rows only), inverse
+//              FFT along a1, x V(r), forward FFT along a1, forward FFT along a2
+//              (sphere rows only); the whole plane stays in LDS
+//   zfft_fwd   T1 -> forward FFT along a3 -> sphere, / N_g, added to HX
+// The projectors and the free-Dirac block are done first:
+//   C = B^H X (matrix-core inner products), C' = W C per (atom, l) and
+//   two-spinor, HX = B C' + kinetic(X) - shift X.
+#include "dks_internal.h"
+#include "fft_device.h"
+
+namespace dks {
+
+// ---------------------------------------------------------------------------
+// z transforms of the sphere columns
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__restrict__ X, int N,
+                                                  const int *__restrict__ col_off,
+                                                  const int2 *__restrict__ gmap, int ncol,
+                                                  int tile, FftPlan pz,
+                                                  const typename CT<T>::c *__restrict__ twz,
+                                                  typename CT<T>::c *__restrict__ T1) {
+  using C = typename CT<T>::c;
+  extern __shared__ unsigned char smem_raw[];
+  C *lines = reinterpret_cast<C *>(smem_raw);
+  const int n3 = pz.n;
+  const int ld = n3 + 1;
+  const int c0 = blockIdx.x * tile;
+  const int w = min(tile, ncol - c0);
+  const int cc = blockIdx.y;
+  for (int e = threadIdx.x; e < w * ld; e += blockDim.x) lines[e] = C{0, 0};
+  __syncthreads();
+  const C *x = X + (size_t)cc * N;
+  const int g0 = col_off[c0], g1 = col_off[c0 + w];
+  for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+    int2 m = gmap[g];
+    lines[(m.x - c0) * ld + m.y] = x[g];
+  }
+  __syncthreads();
+  fft_lines<+1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  C *t = T1 + (size_t)cc * n3 * ncol;
+  for (int e = threadIdx.x; e < w * n3; e += blockDim.x) {
+    int z = e / w, ci = e - (e / w) * w;
+    t[(size_t)z * ncol + c0 + ci] = lines[ci * ld + z];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__restrict__ T1,
+                                                  typename CT<T>::c *__restrict__ HX, int N,
+                                                  const int *__restrict__ col_off,
+                                                  const int2 *__restrict__ gmap, int ncol,
+                                                  int tile, FftPlan pz,
+                                                  const typename CT<T>::c *__restrict__ twz,
+                                                  T inv_ng, T scale) {
+  using C = typename CT<T>::c;
+  extern __shared__ unsigned char smem_raw[];
+  C *lines = reinterpret_cast<C *>(smem_raw);
+  const int n3 = pz.n;
+  const int ld = n3 + 1;
+  const int c0 = blockIdx.x * tile;
+  const int w = min(tile, ncol - c0);
+  const int cc = blockIdx.y;
+  const C *t = T1 + (size_t)cc * n3 * ncol;
+  for (int e = threadIdx.x; e < w * n3; e += blockDim.x) {
+    int z = e / w, ci = e - (e / w) * w;
+    lines[ci * ld + z] = t[(size_t)z * ncol + c0 + ci];
+  }
+  __syncthreads();
+  fft_lines<-1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  C *hx = HX + (size_t)cc * N;
+  const int g0 = col_off[c0], g1 = col_off[c0 + w];
+  for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+    int2 m = gmap[g];
+    C v = lines[(m.x - c0) * ld + m.y];
+    C h = hx[g];
+    hx[g] = C{scale * (h.x + inv_ng * v.x), scale * (h.y + inv_ng * v.y)};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one z plane: 2D inverse FFT, x V, 2D forward FFT, all in LDS
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
+                                                const int4 *__restrict__ col_info,
+                                                const int *__restrict__ rows, int nrows,
+                                                FftPlan px, FftPlan py,
+                                                const typename CT<T>::c *__restrict__ twx,
+                                                const typename CT<T>::c *__restrict__ twy,
+                                                const T *__restrict__ V) {
+  using C = typename CT<T>::c;
+  extern __shared__ unsigned char smem_raw[];
+  C *pl = reinterpret_cast<C *>(smem_raw);
+  const int n1 = px.n, n2 = py.n;
+  const int ld = n2 + 1;
+  const int z = blockIdx.x;
+  const int cc = blockIdx.y;
+  const int n3 = gridDim.x;
+  for (int e = threadIdx.x; e < n1 * ld; e += blockDim.x) pl[e] = C{0, 0};
+  __syncthreads();
+  C *t = T1 + ((size_t)cc * n3 + z) * ncol;
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    int4 ci = col_info[c];
+    pl[ci.x * ld + ci.y] = t[c];
+  }
+  __syncthreads();
+  // along a2 (contiguous), only rows that hold sphere columns
+  fft_lines<+1, T>(pl, nrows, rows, ld, 1, py, twy);
+  // along a1 (stride ld), every a2 position
+  fft_lines<+1, T>(pl, n2, nullptr, 1, ld, px, twx);
+  const T *v = V + (size_t)z * n1 * n2;
+  for (int e = threadIdx.x; e < n1 * n2; e += blockDim.x) {
+    int i = e / n2, j = e - (e / n2) * n2;
+    T s = v[e];
+    C a = pl[i * ld + j];
+    pl[i * ld + j] = C{a.x * s, a.y * s};
+  }
+  __syncthreads();
+  fft_lines<-1, T>(pl, n2, nullptr, 1, ld, px, twx);
+  fft_lines<-1, T>(pl, nrows, rows, ld, 1, py, twy);
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    int4 ci = col_info[c];
+    t[c] = pl[ci.x * ld + ci.y];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projectors: C' = W C, per band, two-spinor and (atom, l) group
+// C is [nproj][4 nb] (FP64); W blocks are (2 dim)^2, index (i m, s).
+// ---------------------------------------------------------------------------
+__global__ void k_apply_w(const double2 *__restrict__ Cin, double2 *__restrict__ Cout, int ldc,
+                          int nb, const int4 *__restrict__ winfo, int ngroups,
+                          const double2 *__restrict__ W) {
+  // grid: x -> band * 2 + pair, y -> group; threads -> output index (2 dim)
+  const int bp = blockIdx.x;
+  const int band = bp >> 1, pair = bp & 1;
+  const int4 gi = winfo[blockIdx.y];
+  const int p0 = gi.x, dim = gi.y;
+  const double2 *w = W + gi.z;
+  const int nd = 2 * dim;
+  for (int o = threadIdx.x; o < nd; o += blockDim.x) {
+    double re = 0, im = 0;
+    for (int k = 0; k < nd; ++k) {
+      double2 wv = w[o * nd + k];
+      int p = p0 + (k >> 1), s = k & 1;
+      double2 cv = Cin[(size_t)p * ldc + band * 4 + pair * 2 + s];
+      re += wv.x * cv.x - wv.y * cv.y;
+      im += wv.x * cv.y + wv.y * cv.x;
+    }
+    int p = p0 + (o >> 1), s = o & 1;
+    Cout[(size_t)p * ldc + band * 4 + pair * 2 + s] = make_double2(re, im);
+  }
+}
+
+// HX = B C' + kinetic(X) - shift X, for a tile of kBT bands per workgroup.
+constexpr int kBT = 4;
+template <typename T>
+__global__ void __launch_bounds__(256) k_nl_kin(const typename CT<T>::c *__restrict__ X,
+                                                typename CT<T>::c *__restrict__ HX, int N, int nb,
+                                                const typename CT<T>::c *__restrict__ B, int nproj,
+                                                const double2 *__restrict__ Cp, int ldc,
+                                                const T *__restrict__ q, T c, T shift) {
+  using C = typename CT<T>::c;
+  extern __shared__ unsigned char smem_raw[];
+  C *cs = reinterpret_cast<C *>(smem_raw);  // [nproj][4 kBT]
+  const int b0 = blockIdx.y * kBT;
+  const int bw = min(kBT, nb - b0);
+  for (int e = threadIdx.x; e < nproj * 4 * kBT; e += blockDim.x) {
+    int p = e / (4 * kBT), j = e - (e / (4 * kBT)) * (4 * kBT);
+    double2 v = (j < 4 * bw) ? Cp[(size_t)p * ldc + b0 * 4 + j] : make_double2(0, 0);
+    cs[e] = C{(T)v.x, (T)v.y};
+  }
+  __syncthreads();
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  C acc[4 * kBT];
+#pragma unroll
+  for (int j = 0; j < 4 * kBT; ++j) acc[j] = C{0, 0};
+  for (int p = 0; p < nproj; ++p) {
+    C bv = B[(size_t)p * N + g];
+#pragma unroll
+    for (int j = 0; j < 4 * kBT; ++j) {
+      C cv = cs[p * 4 * kBT + j];
+      acc[j].x += cv.x * bv.x - cv.y * bv.y;
+      acc[j].y += cv.x * bv.y + cv.y * bv.x;
+    }
+  }
+  const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
+  const T twoc2 = T(2) * c * c;
+#pragma unroll
+  for (int bb = 0; bb < kBT; ++bb) {
+    if (bb < bw) {
+      const C *x = X + (size_t)(b0 + bb) * 4 * N;
+      C *hx = HX + (size_t)(b0 + bb) * 4 * N;
+      C pu = x[g], pd = x[N + g], cu = x[2 * N + g], cd = x[3 * N + g];
+      // sigma.q = [[qz, qx - i qy], [qx + i qy, -qz]]
+      C s0 = C{qz * cu.x + qx * cd.x + qy * cd.y, qz * cu.y + qx * cd.y - qy * cd.x};   // (sigma.q chi)_up
+      C s1 = C{qx * cu.x - qy * cu.y - qz * cd.x, qx * cu.y + qy * cu.x - qz * cd.y};   // (sigma.q chi)_dn
+      C t0 = C{qz * pu.x + qx * pd.x + qy * pd.y, qz * pu.y + qx * pd.y - qy * pd.x};   // (sigma.q phi)_up
+      C t1 = C{qx * pu.x - qy * pu.y - qz * pd.x, qx * pu.y + qy * pu.x - qz * pd.y};   // (sigma.q phi)_dn
+      C o0 = acc[bb * 4 + 0], o1 = acc[bb * 4 + 1], o2 = acc[bb * 4 + 2], o3 = acc[bb * 4 + 3];
+      hx[g] = C{o0.x + c * s0.x - shift * pu.x, o0.y + c * s0.y - shift * pu.y};
+      hx[N + g] = C{o1.x + c * s1.x - shift * pd.x, o1.y + c * s1.y - shift * pd.y};
+      hx[2 * N + g] = C{o2.x + c * t0.x - (twoc2 + shift) * cu.x, o2.y + c * t0.y - (twoc2 + shift) * cu.y};
+      hx[3 * N + g] = C{o3.x + c * t1.x - (twoc2 + shift) * cd.x, o3.y + c * t1.y - (twoc2 + shift) * cd.y};
+    }
+  }
+}
+
+// small component from the large one: chi = c sigma.q phi / (E_q + c^2)  (FP64)
+__global__ void k_kinetic_balance(double2 *X, int N, int n, const double *q, double c) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = blockIdx.y;
+  if (g >= N || b >= n) return;
+  double qx = q[g], qy = q[N + g], qz = q[2 * N + g];
+  double q2 = qx * qx + qy * qy + qz * qz;
+  double e = sqrt(c * c * q2 + c * c * c * c);
+  double f = c / (e + c * c);
+  double2 *x = X + (size_t)b * 4 * N;
+  double2 pu = x[g], pd = x[N + g];
+  double2 t0 = make_double2(qz * pu.x + qx * pd.x + qy * pd.y, qz * pu.y + qx * pd.y - qy * pd.x);
+  double2 t1 = make_double2(qx * pu.x - qy * pu.y - qz * pd.x, qx * pu.y + qy * pu.x - qz * pd.y);
+  x[2 * N + g] = make_double2(f * t0.x, f * t0.y);
+  x[3 * N + g] = make_double2(f * t1.x, f * t1.y);
+}
+
+void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st) {
+  System &s = *b->sys[sys];
+  dim3 grid((s.N + 255) / 256, n);
+  hipLaunchKernelGGL(k_kinetic_balance, grid, dim3(256), 0, st, X, s.N, n, s.d_q64.as<double>(),
+                     s.c);
+  DKS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// launcher
+// ---------------------------------------------------------------------------
+template <typename T> static const typename CT<T>::c *Btab(const System &s);
+template <> const double2 *Btab<double>(const System &s) { return s.d_B64.as<double2>(); }
+template <> const float2 *Btab<float>(const System &s) { return s.d_B32.as<float2>(); }
+template <typename T> static const T *Qtab(const System &s);
+template <> const double *Qtab<double>(const System &s) { return s.d_q64.as<double>(); }
+template <> const float *Qtab<float>(const System &s) { return s.d_q32.as<float>(); }
+template <typename T> static const T *Vtab(const Potential &p);
+template <> const double *Vtab<double>(const Potential &p) { return p.d_v64.as<double>(); }
+template <> const float *Vtab<float>(const Potential &p) { return p.d_v32.as<float>(); }
+template <typename T> static const typename CT<T>::c *Tw(const Potential &p, int d);
+template <> const double2 *Tw<double>(const Potential &p, int d) { return p.d_tw64[d].as<double2>(); }
+template <> const float2 *Tw<float>(const Potential &p, int d) { return p.d_tw32[d].as<float2>(); }
+
+void init_kernel_attributes() {
+  static bool done = false;
+  if (done) return;
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_zfft_inv<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_zfft_inv<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_zfft_fwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_zfft_fwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  done = true;
+}
+
+template <typename T>
+void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
+             double scale, hipStream_t st) {
+  using C = cplx<T>;
+  System &s = *b->sys[sysi];
+  Potential &pot = *b->pot[s.vsrc];
+  if (nb <= 0) return;
+  const int N = s.N;
+  const int ncols = 4 * nb;
+  // --- projectors and kinetic block: HX = B C' + kin X - shift X
+  double2 *Cp = nullptr;
+  if (s.nproj > 0) {
+    size_t cbytes = sizeof(double2) * (size_t)s.nproj * ncols;
+    b->nlc.ensure(cbytes);
+    b->nlc2.ensure(cbytes);
+    std::vector<int64_t> dummy;
+    // row offsets: B rows p*N, X rows cc*N (contiguous), passed as null -> stride N
+    gemm_ip<T>(Btab<T>(s), nullptr, s.nproj, X, nullptr, ncols, nullptr, (int64_t)N,
+               b->nlc.as<double2>(), nullptr, ncols, b->part, st);
+    dim3 gw(nb * 2, (unsigned)s.groups.size());
+    hipLaunchKernelGGL(k_apply_w, gw, dim3(64), 0, st, b->nlc.as<double2>(), b->nlc2.as<double2>(),
+                       ncols, nb, s.d_Winfo.as<int4>(), (int)s.groups.size(), s.d_W64.as<double2>());
+    DKS_HIP(hipGetLastError());
+    Cp = b->nlc2.as<double2>();
+  }
+  {
+    dim3 grid((N + 255) / 256, (nb + kBT - 1) / kBT);
+    size_t sm = sizeof(C) * (size_t)s.nproj * 4 * kBT;
+    hipLaunchKernelGGL(k_nl_kin<T>, grid, dim3(256), sm, st, X, HX, N, nb, Btab<T>(s), s.nproj, Cp,
+                       ncols, Qtab<T>(s), (T)s.c, (T)shift);
+    DKS_HIP(hipGetLastError());
+  }
+  // --- local potential through the grid
+  const int n3 = s.grid[2];
+  b->t1.ensure(sizeof(C) * (size_t)ncols * n3 * s.ncol);
+  C *t1 = b->t1.as<C>();
+  const int tile = s.tile_z;
+  dim3 gz((s.ncol + tile - 1) / tile, ncols);
+  size_t smz = sizeof(C) * (size_t)tile * (n3 + 1);
+  hipLaunchKernelGGL(k_zfft_inv<T>, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
+                     s.d_gmap.as<int2>(), s.ncol, tile, s.plan[2], Tw<T>(pot, 2), t1);
+  DKS_HIP(hipGetLastError());
+  dim3 gp(n3, ncols);
+  size_t smp = sizeof(C) * (size_t)s.grid[0] * (s.grid[1] + 1);
+  hipLaunchKernelGGL(k_plane<T>, gp, dim3(1024), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
+                     s.d_rows.as<int>(), s.nrows, s.plan[0], s.plan[1], Tw<T>(pot, 0),
+                     Tw<T>(pot, 1), Vtab<T>(pot));
+  DKS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_zfft_fwd<T>, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
+                     s.d_gmap.as<int2>(), s.ncol, tile, s.plan[2], Tw<T>(pot, 2),
+                     (T)(1.0 / s.ng), (T)scale);
+  DKS_HIP(hipGetLastError());
+}
+
+template void apply_h<double>(dks_basis *, int, const double2 *, double2 *, int, double, double,
+                              hipStream_t);
+template void apply_h<float>(dks_basis *, int, const float2 *, float2 *, int, double, double,
+                             hipStream_t);
+
+}  // namespace dks

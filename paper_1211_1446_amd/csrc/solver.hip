@@ -1,0 +1,426 @@
+// Algorithm 1 (LOBPCG-F) driven from the host: every step on the block runs in
+// the library's kernels on one stream; the host reads back only the small
+// Rayleigh-Ritz results and the residual norms once per iteration to decide
+// convergence and the active (unlocked) columns (Alg. 1 lines 17-21).
+//
+// Workspace per precision: two copies of the subspace Z = [X | Y | P] and of
+// HZ = [HX | HY | HP] (3n rows each, K = 4N complex per row), a residual block
+// and a filter temporary.  Iteration k reads Z_cur and writes the new X and P
+// into Z_nxt, then the two swap.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+
+#include "dks_internal.h"
+
+namespace dks {
+
+template <typename T> struct Blocks {
+  int n = 0;
+  int64_t K = 0;
+  DevBuf Z[2], HZ[2], R, W;
+  void ensure(int n_, int64_t K_) {
+    size_t rowb = sizeof(cplx<T>) * (size_t)K_;
+    for (int i = 0; i < 2; ++i) {
+      Z[i].ensure(rowb * 3 * n_);
+      HZ[i].ensure(rowb * 3 * n_);
+    }
+    R.ensure(rowb * n_);
+    W.ensure(rowb * n_);
+    n = n_;
+    K = K_;
+  }
+  cplx<T> *z(int i, int row) { return Z[i].as<cplx<T>>() + (size_t)row * K; }
+  cplx<T> *hz(int i, int row) { return HZ[i].as<cplx<T>>() + (size_t)row * K; }
+};
+
+struct Solver {
+  Blocks<double> b64;
+  Blocks<float> b32;
+  DevBuf gS, gA, Vz, Vp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2;
+};
+
+static Solver *solver_of(dks_basis *b) {
+  if (!b->solver) b->solver = new Solver();
+  return static_cast<Solver *>(b->solver);
+}
+
+// DKS_LOG=1 in the environment prints one JSON line per Rayleigh-Ritz step to stderr.
+static bool log_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("DKS_LOG");
+    v = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+struct Ctx {
+  dks_basis *b;
+  int sys;
+  hipStream_t st;
+  Solver *sv;
+  const dks_solve_opts *o;
+  dks_solve_info *info;
+  double C, Om, c2;
+  int64_t K;
+  int N;
+};
+
+// Row offsets of Z = [rows 0..n) U [n, n+m) U [2n, 2n+mp) of a 3n-row block.
+__global__ void k_offsets(int64_t *off, int n, int m, int mp, int64_t K) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int nz = n + m + mp;
+  if (i >= nz) return;
+  int row = (i < n + m) ? i : (2 * n + (i - n - m));
+  off[i] = (int64_t)row * K;
+}
+
+template <typename T>
+static void filter_inplace(Ctx &x, cplx<T> *Y, cplx<T> *W, int m) {
+  // W = (H - C) Y ; Y = (H - C) W / Omega^2   (Eq. filter)
+  apply_h<T>(x.b, x.sys, Y, W, m, x.C, 1.0, x.st);
+  apply_h<T>(x.b, x.sys, W, Y, m, x.C, 1.0 / (x.Om * x.Om), x.st);
+  if (x.info) x.info->h_applies += 2 * m;
+}
+
+template <typename T> struct LoopState {
+  int cur = 0;
+  int m = 0;       // active columns (rows of Y)
+  int mp = 0;      // rows of P
+  std::vector<int> act;
+  std::vector<double> lam, res;
+  bool converged = false;
+  int iters = 0;
+};
+
+// Rayleigh-Ritz on Z_cur rows described by (n, m, mp); returns false when
+// fewer than n directions survive even without P.
+template <typename T>
+static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
+                 std::vector<double2> &hV) {
+  Solver &sv = *x.sv;
+  int mp = s.mp;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const int nz = n + s.m + mp;
+    sv.off.ensure(sizeof(int64_t) * 3 * n);
+    hipLaunchKernelGGL(k_offsets, dim3((nz + 255) / 256), dim3(256), 0, x.st, sv.off.as<int64_t>(),
+                       n, s.m, mp, bk.K);
+    DKS_HIP(hipGetLastError());
+    sv.gS.ensure(sizeof(double2) * nz * nz);
+    sv.gA.ensure(sizeof(double2) * nz * nz);
+    gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+               bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+               bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(), sv.gA.as<double2>(),
+               nz, sv.part, x.st);
+    sv.Vz.ensure(sizeof(double2) * nz * n);
+    sv.theta.ensure(sizeof(double) * n);
+    sv.rinfo.ensure(sizeof(int) * 4);
+    sv.rdinfo.ensure(sizeof(double) * 2);
+    rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, drop_tol, nullptr,
+                  sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
+                  sv.rdinfo.as<double>(), sv.rrs, x.st);
+    int info[4];
+    double dinfo[2];
+    DKS_HIP(hipMemcpyAsync(info, sv.rinfo.p, sizeof(int) * 4, hipMemcpyDeviceToHost, x.st));
+    DKS_HIP(hipMemcpyAsync(dinfo, sv.rdinfo.p, sizeof(double) * 2, hipMemcpyDeviceToHost, x.st));
+    DKS_HIP(hipStreamSynchronize(x.st));
+    if (log_enabled())
+      std::fprintf(stderr,
+                   "{\"prec\": %d, \"nz\": %d, \"n\": %d, \"m\": %d, \"mp\": %d, \"kept\": %d, "
+                   "\"status\": %d, \"min_ritz\": %.12g}\n",
+                   (int)sizeof(T), nz, n, s.m, mp, info[0], info[1], dinfo[0]);
+    if (info[1] == 0) {
+      if (x.info) {
+        x.info->basis_drops += info[2];
+        x.info->min_ritz = std::min(x.info->min_ritz, dinfo[0]);
+      }
+      s.mp = mp;
+      hV.resize((size_t)nz * n);
+      DKS_HIP(hipMemcpyAsync(hV.data(), sv.Vz.p, sizeof(double2) * nz * n, hipMemcpyDeviceToHost, x.st));
+      s.lam.resize(n);
+      DKS_HIP(hipMemcpyAsync(s.lam.data(), sv.theta.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
+      DKS_HIP(hipStreamSynchronize(x.st));
+      return true;
+    }
+    if (mp == 0) return false;
+    mp = 0;   // retry without P
+    if (x.info) x.info->p_restarts += 1;
+  }
+  return false;
+}
+
+// X_new = Z V[:, :n], HX_new = HZ V; residual and norms; active set; P, HP.
+template <typename T>
+static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vector<double2> &hV,
+                   double tol) {
+  Solver &sv = *x.sv;
+  const int nz = n + s.m + s.mp;
+  const int nxt = 1 - s.cur;
+  gemm_up<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, sv.Vz.as<double2>(), n, n,
+             bk.K, bk.z(nxt, 0), bk.K, 0.0, x.st);
+  gemm_up<T>(bk.HZ[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, sv.Vz.as<double2>(), n, n,
+             bk.K, bk.hz(nxt, 0), bk.K, 0.0, x.st);
+  sv.lam.ensure(sizeof(double) * n);
+  DKS_HIP(hipMemcpyAsync(sv.lam.p, s.lam.data(), sizeof(double) * n, hipMemcpyHostToDevice, x.st));
+  sv.norms.ensure(sizeof(double) * n);
+  residual<T>(bk.z(nxt, 0), bk.hz(nxt, 0), sv.lam.as<double>(), n, bk.K, bk.R.template as<cplx<T>>(),
+              sv.norms.as<double>(), sv.part2, x.st);
+  s.res.resize(n);
+  DKS_HIP(hipMemcpyAsync(s.res.data(), sv.norms.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
+  DKS_HIP(hipStreamSynchronize(x.st));
+  for (auto &r : s.res) r = std::sqrt(std::max(r, 0.0));
+  if (log_enabled()) {
+    std::fprintf(stderr, "{\"prec\": %d, \"lam\": [", (int)sizeof(T));
+    for (int j = 0; j < n; ++j) std::fprintf(stderr, "%s%.12g", j ? ", " : "", s.lam[j]);
+    std::fprintf(stderr, "], \"res\": [");
+    for (int j = 0; j < n; ++j) std::fprintf(stderr, "%s%.3e", j ? ", " : "", s.res[j]);
+    std::fprintf(stderr, "]}\n");
+  }
+  std::vector<int> act;
+  for (int j = 0; j < n; ++j)
+    if (!(s.res[j] < tol)) act.push_back(j);
+  const int mnew = (int)act.size();
+  if (mnew == 0) {
+    s.converged = true;
+  } else if (s.m + s.mp > 0) {
+    // P = [0, Y, P] V[:, act]  (Alg. 1 line 22), HP alike
+    const int nyp = s.m + s.mp;
+    std::vector<double2> vp((size_t)nyp * mnew);
+    for (int i = 0; i < nyp; ++i)
+      for (int a = 0; a < mnew; ++a) vp[(size_t)i * mnew + a] = hV[(size_t)(n + i) * n + act[a]];
+    sv.Vp.ensure(sizeof(double2) * vp.size());
+    DKS_HIP(hipMemcpyAsync(sv.Vp.p, vp.data(), sizeof(double2) * vp.size(), hipMemcpyHostToDevice, x.st));
+    const int64_t *offyp = sv.off.as<int64_t>() + n;
+    gemm_up<T>(bk.Z[s.cur].template as<cplx<T>>(), offyp, nyp, sv.Vp.as<double2>(), mnew, mnew,
+               bk.K, bk.z(nxt, 2 * n), bk.K, 0.0, x.st);
+    gemm_up<T>(bk.HZ[s.cur].template as<cplx<T>>(), offyp, nyp, sv.Vp.as<double2>(), mnew, mnew,
+               bk.K, bk.hz(nxt, 2 * n), bk.K, 0.0, x.st);
+    DKS_HIP(hipStreamSynchronize(x.st));   // vp must outlive the copy
+  }
+  s.mp = (mnew > 0 && s.m + s.mp > 0) ? mnew : 0;
+  s.m = mnew;
+  s.act = act;
+  s.cur = nxt;
+}
+
+// One precision stage of Algorithm 1 on the block already in Z[cur] rows [0, n).
+// `first`: apply the initial filtering (lines 1-3) before the first Rayleigh-Ritz.
+template <typename T>
+static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n_init,
+                            double tol, int max_iter, double drop_tol, bool stagnation_exit) {
+  Solver &sv = *x.sv;
+  const bool filt = x.o->use_filter != 0;
+  s.cur = 0;
+  s.m = 0;
+  s.mp = 0;
+  s.converged = false;
+  // lines 1-3
+  if (filt)
+    for (int k = 0; k < n_init; ++k) filter_inplace<T>(x, bk.z(0, 0), bk.W.template as<cplx<T>>(), n);
+  // lines 4-6: Rayleigh-Ritz on X0
+  apply_h<T>(x.b, x.sys, bk.z(0, 0), bk.hz(0, 0), n, 0.0, 1.0, x.st);
+  if (x.info) x.info->h_applies += n;
+  std::vector<double2> hV;
+  if (!ritz<T>(x, bk, s, n, drop_tol, hV))
+    throw Error{DKS_ECHOL, "the start block is numerically rank deficient"};
+  update<T>(x, bk, s, n, hV, tol);
+  double best = *std::max_element(s.res.begin(), s.res.end());
+  int stall = 0;
+  // lines 8-23
+  while (!s.converged && s.iters < max_iter) {
+    s.iters++;
+    if (x.info) x.info->iterations++;
+    const int m = s.m;
+    // line 9 (T = I) : Y = R[:, active]
+    sv.idx.ensure(sizeof(int) * n);
+    DKS_HIP(hipMemcpyAsync(sv.idx.p, s.act.data(), sizeof(int) * m, hipMemcpyHostToDevice, x.st));
+    gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
+    // line 10 : Y = f(H) Y
+    if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
+    apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st);
+    if (x.info) x.info->h_applies += m;
+    // lines 11-14
+    if (!ritz<T>(x, bk, s, n, drop_tol, hV))
+      throw Error{DKS_ECHOL, "Rayleigh-Ritz lost the X block"};
+    // lines 15-22
+    update<T>(x, bk, s, n, hV, tol);
+    double worst = *std::max_element(s.res.begin(), s.res.end());
+    if (stagnation_exit) {
+      if (worst < 0.7 * best) {
+        best = worst;
+        stall = 0;
+      } else if (++stall >= 3) {
+        break;
+      }
+    }
+  }
+  return s.converged ? DKS_OK : DKS_WNOTCONV;
+}
+
+}  // namespace dks
+
+using namespace dks;
+
+extern "C" {
+
+void dks_free_solver(dks_basis *b) {
+  if (b && b->solver) {
+    delete static_cast<Solver *>(b->solver);
+    b->solver = nullptr;
+  }
+}
+
+void dks_default_opts(dks_solve_opts *o) {
+  if (!o) return;
+  o->C = std::numeric_limits<double>::quiet_NaN();
+  o->Omega = std::numeric_limits<double>::quiet_NaN();
+  o->n_init = 3;
+  o->n_iter = 200;
+  o->tol = 1e-8;
+  o->mode = DKS_MODE_FP64;
+  o->mixed_tol = 1e-4;
+  o->mixed_iter = 200;
+  o->kinetic_balance = 0;
+  o->use_filter = 1;
+}
+
+dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb, dks_prec prec,
+                       void *stream) {
+  try {
+    DKS_REQUIRE(b && X && HX && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
+                "bad argument");
+    DKS_REQUIRE(X != HX, DKS_EINVAL, "X and HX must not overlap");
+    DKS_HIP(hipSetDevice(b->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == DKS_FP64)
+      apply_h<double>(b, sys, (const double2 *)X, (double2 *)HX, nb, 0.0, 1.0, st);
+    else
+      apply_h<float>(b, sys, (const float2 *)X, (float2 *)HX, nb, 0.0, 1.0, st);
+    return DKS_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int nb, double C,
+                            double Omega, dks_prec prec, void *stream) {
+  try {
+    DKS_REQUIRE(b && Y && FY && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
+                "bad argument");
+    DKS_REQUIRE(Y != FY, DKS_EINVAL, "Y and FY must not overlap");
+    DKS_REQUIRE(std::isfinite(C) && std::isfinite(Omega) && Omega != 0.0, DKS_EINVAL,
+                "C and Omega must be finite, Omega nonzero");
+    DKS_HIP(hipSetDevice(b->device));
+    hipStream_t st = (hipStream_t)stream;
+    const System &s = *b->sys[sys];
+    const size_t K = 4 * (size_t)s.N;
+    if (prec == DKS_FP64) {
+      b->ftmp64.ensure(sizeof(double2) * K * nb);
+      apply_h<double>(b, sys, (const double2 *)Y, b->ftmp64.as<double2>(), nb, C, 1.0, st);
+      apply_h<double>(b, sys, b->ftmp64.as<double2>(), (double2 *)FY, nb, C, 1.0 / (Omega * Omega), st);
+    } else {
+      b->ftmp32.ensure(sizeof(float2) * K * nb);
+      apply_h<float>(b, sys, (const float2 *)Y, b->ftmp32.as<float2>(), nb, C, 1.0, st);
+      apply_h<float>(b, sys, b->ftmp32.as<float2>(), (float2 *)FY, nb, C, 1.0 / (Omega * Omega), st);
+    }
+    return DKS_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lambda,
+                             double *resnorms, const dks_solve_opts *opts, dks_solve_info *info,
+                             void *stream) {
+  try {
+    DKS_REQUIRE(b && X && lambda && sys >= 0 && sys < (int)b->sys.size(), DKS_EINVAL, "bad argument");
+    dks_solve_opts o;
+    if (opts) o = *opts; else dks_default_opts(&o);
+    const System &s = *b->sys[sys];
+    DKS_REQUIRE(n >= 1 && n <= 170 && n <= 4 * s.N, DKS_EINVAL,
+                "n must be in [1, min(170, 4N)] (subspace dimension 3n <= 512)");
+    DKS_REQUIRE(o.n_init >= 0 && o.n_iter >= 0 && o.tol > 0, DKS_EINVAL, "bad options");
+    DKS_REQUIRE(o.mode >= 0 && o.mode <= 2, DKS_EINVAL, "bad mode");
+    DKS_HIP(hipSetDevice(b->device));
+    hipStream_t st = (hipStream_t)stream;
+    dks_solve_info inf{};
+    inf.min_ritz = std::numeric_limits<double>::infinity();
+    Ctx x;
+    x.b = b;
+    x.sys = sys;
+    x.st = st;
+    x.sv = solver_of(b);
+    x.o = &o;
+    x.info = &inf;
+    x.N = s.N;
+    x.K = 4 * (int64_t)s.N;
+    x.c2 = s.c * s.c;
+    double C0, O0;
+    dks_filter_constants(b, sys, &C0, &O0);
+    x.C = std::isnan(o.C) ? C0 : o.C;
+    x.Om = std::isnan(o.Omega) ? O0 : o.Omega;
+    DKS_REQUIRE(std::isfinite(x.C) && std::isfinite(x.Om) && x.Om != 0.0, DKS_EINVAL, "bad C or Omega");
+    inf.C = x.C;
+    inf.Omega = x.Om;
+    double2 *Xu = (double2 *)X;
+    if (o.kinetic_balance) kinetic_balance(b, sys, Xu, n, st);
+    dks_status rc = DKS_OK;
+    LoopState<double> s64;
+    if (o.mode == DKS_MODE_FP64) {
+      x.sv->b64.ensure(n, x.K);
+      DKS_HIP(hipMemcpyAsync(x.sv->b64.z(0, 0), Xu, sizeof(double2) * x.K * n, hipMemcpyDeviceToDevice, st));
+      rc = run_stage<double>(x, x.sv->b64, s64, n, o.n_init, o.tol, o.n_iter, 1e-10, false);
+    } else {
+      // reduced-precision stage
+      x.sv->b32.ensure(n, x.K);
+      LoopState<float> s32;
+      convert<double, float>(Xu, x.sv->b32.z(0, 0), x.K * n, st);
+      run_stage<float>(x, x.sv->b32, s32, n, o.n_init, o.mixed_tol, o.mixed_iter, 1e-5, true);
+      inf.iters_reduced = s32.iters;
+      // FP64 polish.  The reduced-precision block carries rounding noise of
+      // relative size ~1e-8 in every direction, including the negative band,
+      // where the residual amplifies it by ~2c^2 (the gamma_LOBPCG ~ Delta/w of
+      // Sec. 3.1); one filter application in FP64 (N_init = 1, the paper's
+      // choice for a warm start) damps it below the FP64 tolerance.
+      x.sv->b64.ensure(n, x.K);
+      convert<float, double>(x.sv->b32.z(s32.cur, 0), x.sv->b64.z(0, 0), x.K * n, st);
+      s64.iters = 0;
+      rc = run_stage<double>(x, x.sv->b64, s64, n, 1, o.tol, o.n_iter, 1e-10, false);
+    }
+    Blocks<double> &bk = x.sv->b64;
+    DKS_HIP(hipMemcpyAsync(Xu, bk.z(s64.cur, 0), sizeof(double2) * x.K * n, hipMemcpyDeviceToDevice, st));
+    DKS_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < n; ++j) lambda[j] = s64.lam[j];
+    double mx = 0;
+    int nconv = 0;
+    for (int j = 0; j < n; ++j) {
+      if (resnorms) resnorms[j] = s64.res[j];
+      mx = std::max(mx, s64.res[j]);
+      if (s64.res[j] < o.tol) ++nconv;
+    }
+    inf.converged = (nconv == n);
+    inf.n_converged = nconv;
+    inf.max_resnorm = mx;
+    if (info) *info = inf;
+    for (int j = 0; j < n; ++j)
+      if (lambda[j] < -x.c2) {
+        set_error("a Ritz value fell below -c^2 (variational collapse)");
+        return DKS_ECOLLAPSE;
+      }
+    if (rc != DKS_OK) set_error("iteration limit reached before every residual fell below tol");
+    return rc;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+}  // extern "C"
