@@ -134,11 +134,16 @@ typedef struct {
   int n_iter;           /* maximum iterations of the main loop */
   double tol;           /* convergence: 2-norm of every residual column < tol (Ha) */
   int mode;             /* dks_mode */
-  double mixed_tol;     /* mixed modes: residual at which the reduced-precision stage stops */
+  double mixed_tol;     /* mixed modes: residual at which the reduced-precision stage stops
+                           (it also stops when its residual stagnates); <= 0 runs exactly
+                           mixed_iter reduced-precision iterations */
   int mixed_iter;       /* mixed modes: cap on reduced-precision iterations */
   int kinetic_balance;  /* 1: rebuild the small components of X0 from the large ones,
                            chi = c sigma.q phi / (E_q + c^2) (Eq. (RKB)) */
   int use_filter;       /* 1: LOBPCG-F; 0: standard LOBPCG (the paper's comparison) */
+  double *iter_ms;      /* optional caller-owned host array of n_iter (+ mixed_iter in the
+                           mixed modes) entries: wall time of each main-loop iteration in
+                           ms, in execution order (each iteration ends with a stream sync) */
 } dks_solve_opts;
 
 typedef struct {
@@ -149,6 +154,7 @@ typedef struct {
   int h_applies;        /* band-applications of H (one per band per apply) */
   int basis_drops;      /* Y/P directions removed as numerically dependent */
   int p_restarts;       /* iterations whose P block was dropped */
+  int neg_ritz_discarded; /* Ritz values below -c^2 left out of X (LOBPCG-F only) */
   double min_ritz;      /* smallest Ritz value seen (collapse monitor) */
   double max_resnorm;   /* largest final residual norm */
   double C, Omega;      /* filter constants used */
@@ -167,6 +173,15 @@ void dks_default_opts(dks_solve_opts *o);
 dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lambda,
                              double *resnorms, const dks_solve_opts *opts,
                              dks_solve_info *info, void *stream);
+
+/* Kernel timing (a diagnostic for roofline accounting).  When enabled, every
+ * kernel the library launches on the calling thread is bracketed by a pair of
+ * HIP events on its stream.  dks_profile_report synchronises the device, writes
+ * a JSON object {"kernel": {"count": c, "total_ms": t}, ...} into buf (always
+ * NUL-terminated, truncated to len) and clears the records.  Disabled by
+ * default; enabling costs two event records per launch. */
+void dks_profile_enable(int on);
+dks_status dks_profile_report(char *buf, size_t len);
 
 /* Release everything owned by the basis (after synchronising its device). */
 void dks_free_basis(dks_basis *b);

@@ -41,8 +41,9 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-# FFTs use every host core (a library primitive; the arithmetic is unchanged)
-_WORKERS = os.cpu_count() or 1
+# FFT worker threads: OMP_NUM_THREADS if set, else every host core (a library
+# primitive; the arithmetic is unchanged)
+_WORKERS = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
 
 def reciprocal_lattice(lattice: np.ndarray) -> np.ndarray:
     """Rows b_i with a_i . b_j = 2 pi delta_ij."""

@@ -45,13 +45,15 @@ class SolveOpts(ct.Structure):
     _fields_ = [("C", ct.c_double), ("Omega", ct.c_double), ("n_init", ct.c_int),
                 ("n_iter", ct.c_int), ("tol", ct.c_double), ("mode", ct.c_int),
                 ("mixed_tol", ct.c_double), ("mixed_iter", ct.c_int),
-                ("kinetic_balance", ct.c_int), ("use_filter", ct.c_int)]
+                ("kinetic_balance", ct.c_int), ("use_filter", ct.c_int),
+                ("iter_ms", ct.POINTER(ct.c_double))]
 
 
 class SolveInfo(ct.Structure):
     _fields_ = [("iterations", ct.c_int), ("iters_reduced", ct.c_int), ("converged", ct.c_int),
                 ("n_converged", ct.c_int), ("h_applies", ct.c_int), ("basis_drops", ct.c_int),
-                ("p_restarts", ct.c_int), ("min_ritz", ct.c_double), ("max_resnorm", ct.c_double),
+                ("p_restarts", ct.c_int), ("neg_ritz_discarded", ct.c_int),
+                ("min_ritz", ct.c_double), ("max_resnorm", ct.c_double),
                 ("C", ct.c_double), ("Omega", ct.c_double)]
 
     def as_dict(self):
@@ -80,6 +82,9 @@ def _load():
     lib.dks_free_basis.argtypes = [vp]
     lib.dks_free_basis.restype = None
     lib.dks_last_error.restype = ct.c_char_p
+    lib.dks_profile_enable.argtypes = [i]
+    lib.dks_profile_enable.restype = None
+    lib.dks_profile_report.argtypes = [ct.c_char_p, ct.c_size_t]
     return lib
 
 
@@ -241,11 +246,26 @@ def default_opts(**kw) -> SolveOpts:
     return o
 
 
+def profile_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch of this thread with HIP events."""
+    _lib.dks_profile_enable(1 if on else 0)
+
+
+def profile_report() -> dict:
+    """{kernel: {"count", "total_ms"}} since the last report (synchronises the device)."""
+    import json
+    buf = ct.create_string_buffer(1 << 16)
+    _check(_lib.dks_profile_report(buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
 def lobpcgf_solve(b: Basis, sys: int, n: int, X, opts: Optional[SolveOpts] = None, stream=None,
-                  allow_notconv: bool = True):
+                  allow_notconv: bool = True, iter_ms: Optional[np.ndarray] = None):
     """Algorithm 1 on the complex128 device block X (in: X0, out: eigenvectors).
 
-    Returns (eigenvalues (n,), residual norms (n,), info dict, status)."""
+    ``iter_ms``: optional float64 array receiving the wall time of each
+    main-loop iteration.  Returns (eigenvalues (n,), residual norms (n,), info
+    dict, status)."""
     import torch
     if X.dtype != torch.complex128:
         raise TypeError("X must be complex128")
@@ -255,6 +275,11 @@ def lobpcgf_solve(b: Basis, sys: int, n: int, X, opts: Optional[SolveOpts] = Non
     res = np.zeros(n)
     info = SolveInfo()
     o = opts if opts is not None else default_opts()
+    if iter_ms is not None:
+        need = o.n_iter + (o.mixed_iter if o.mode != MODE_FP64 else 0)
+        if iter_ms.dtype != np.float64 or iter_ms.size < need or not iter_ms.flags.c_contiguous:
+            raise ValueError(f"iter_ms must be a contiguous float64 array of >= {need} entries")
+        o.iter_ms = _dptr(iter_ms)
     rc = _lib.dks_lobpcgf_solve(b.handle, sys, n, ct.c_void_p(X.data_ptr()), _dptr(lam), _dptr(res),
                                 ct.byref(o), ct.byref(info), _stream(stream))
     _check(rc, allow_warning=allow_notconv)

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["basis.cpp", "operator.hip", "blas.hip", "rr.hip", "solver.hip"]
+SRC = ["basis.cpp", "profile.cpp", "operator.hip", "blas.hip", "rr.hip", "solver.hip"]
 LIB = os.path.join(HERE, "libdks.so")
 
 
@@ -13,7 +13,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     csrc = os.path.join(HERE, "csrc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    flags = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
     procs, objs = [], []

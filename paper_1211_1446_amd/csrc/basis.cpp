@@ -9,6 +9,7 @@
 #include <map>
 
 #include "dks_internal.h"
+#include "fft_split.h"
 
 namespace dks {
 
@@ -184,20 +185,33 @@ dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, d
       const size_t ng = (size_t)n1 * n2 * n3;
       for (int d = 0; d < 3; ++d) P->grid[d] = D.grid[d];
       {
+        // plane layout [p3][p1][p2] in the real-space order the transforms
+        // leave behind: position p of axis d holds natural index nat[d][p]
+        std::vector<int> nat[3];
+        for (int d = 0; d < 3; ++d) {
+          const int n = D.grid[d];
+          nat[d].resize(n);
+          int A = 1, Bq = n;
+          bool fast = (d == 2) ? fft2::split_z(n, &A, &Bq) : fft2::split_plane(n, &A, &Bq);
+          for (int p = 0; p < n; ++p) nat[d][p] = fast ? fft2::scrambled_to_natural(p, A, Bq) : p;
+        }
         std::vector<double> v64(ng);
         std::vector<float> v32(ng);
         double vmin = 1e300, vmax = -1e300, vs = 0;
-        for (int i = 0; i < n1; ++i)
-          for (int j = 0; j < n2; ++j)
-            for (int k = 0; k < n3; ++k) {
-              double v = D.v_loc[((size_t)i * n2 + j) * n3 + k];
-              DKS_REQUIRE(std::isfinite(v), DKS_EINVAL, "v_loc has a non-finite value");
-              size_t o = ((size_t)k * n1 + i) * n2 + j;
+        for (size_t e = 0; e < ng; ++e) {
+          double v = D.v_loc[e];
+          DKS_REQUIRE(std::isfinite(v), DKS_EINVAL, "v_loc has a non-finite value");
+          vmin = std::min(vmin, v);
+          vmax = std::max(vmax, v);
+          vs += v;
+        }
+        for (int p3 = 0; p3 < n3; ++p3)
+          for (int p1 = 0; p1 < n1; ++p1)
+            for (int p2 = 0; p2 < n2; ++p2) {
+              double v = D.v_loc[((size_t)nat[0][p1] * n2 + nat[1][p2]) * n3 + nat[2][p3]];
+              size_t o = ((size_t)p3 * n1 + p1) * n2 + p2;
               v64[o] = v;
               v32[o] = (float)v;
-              vmin = std::min(vmin, v);
-              vmax = std::max(vmax, v);
-              vs += v;
             }
         P->vmin = vmin;
         P->vmax = vmax;
@@ -372,6 +386,7 @@ dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, d
           }
         }
         for (int d = 0; d < 3; ++d) S->plan[d] = make_plan(D.grid[d]);
+        upload(S->d_plan, S->plan, sizeof(S->plan));
         S->tile_z = std::max(1, std::min(32, 4096 / n3));
       }
     }

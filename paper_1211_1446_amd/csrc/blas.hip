@@ -164,15 +164,15 @@ void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, con
   double2 *p1 = part.as<double2>();
   double2 *p2 = B2 ? p1 + (size_t)nsplit * M * Nn : nullptr;
   dim3 grid(tm, tn, (unsigned)nsplit);
-  hipLaunchKernelGGL(k_gemm_ip<T>, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk,
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_gemm_ip.f64" : "k_gemm_ip.f32"), k_gemm_ip<T>, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk,
                      p1, p2);
   DKS_HIP(hipGetLastError());
   int nel = M * Nn;
-  hipLaunchKernelGGL(k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p1, (int)nsplit, M,
+  DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p1, (int)nsplit, M,
                      Nn, out, ldo);
   DKS_HIP(hipGetLastError());
   if (B2) {
-    hipLaunchKernelGGL(k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p2, (int)nsplit,
+    DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p2, (int)nsplit,
                        M, Nn, out2, ldo);
     DKS_HIP(hipGetLastError());
   }
@@ -247,7 +247,7 @@ void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int
              int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st) {
   if (n <= 0 || K <= 0) return;
   dim3 grid((unsigned)((K + 255) / 256), (n + kUpJT - 1) / kUpJT);
-  hipLaunchKernelGGL(k_gemm_up<T>, grid, dim3(256), 0, st, A, aoff, m, V, ldv, n, K, out, ldo,
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32"), k_gemm_up<T>, grid, dim3(256), 0, st, A, aoff, m, V, ldv, n, K, out, ldo,
                      (T)beta);
   DKS_HIP(hipGetLastError());
 }
@@ -332,10 +332,10 @@ void residual(const cplx<T> *X, const cplx<T> *HX, const double *lam, int n, int
   if (n <= 0) return;
   int nchunk = (int)((K + kRedChunk - 1) / kRedChunk);
   part.ensure(sizeof(double) * (size_t)n * nchunk);
-  hipLaunchKernelGGL(k_residual<T>, dim3(nchunk, n), dim3(256), 0, st, X, HX, lam, K, R,
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_residual.f64" : "k_residual.f32"), k_residual<T>, dim3(nchunk, n), dim3(256), 0, st, X, HX, lam, K, R,
                      part.as<double>(), nchunk);
   DKS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sum_rows, dim3((n + 63) / 64), dim3(64), 0, st, part.as<double>(), n,
+  DKS_LAUNCH("k_sum_rows", k_sum_rows, dim3((n + 63) / 64), dim3(64), 0, st, part.as<double>(), n,
                      nchunk, norm2);
   DKS_HIP(hipGetLastError());
 }
@@ -349,10 +349,10 @@ void col_norm2(const cplx<T> *X, int n, int64_t K, double *norm2, DevBuf &part, 
   if (n <= 0) return;
   int nchunk = (int)((K + kRedChunk - 1) / kRedChunk);
   part.ensure(sizeof(double) * (size_t)n * nchunk);
-  hipLaunchKernelGGL(k_norm2<T>, dim3(nchunk, n), dim3(256), 0, st, X, K, part.as<double>(),
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_norm2.f64" : "k_norm2.f32"), k_norm2<T>, dim3(nchunk, n), dim3(256), 0, st, X, K, part.as<double>(),
                      nchunk);
   DKS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sum_rows, dim3((n + 63) / 64), dim3(64), 0, st, part.as<double>(), n,
+  DKS_LAUNCH("k_sum_rows", k_sum_rows, dim3((n + 63) / 64), dim3(64), 0, st, part.as<double>(), n,
                      nchunk, norm2);
   DKS_HIP(hipGetLastError());
 }
@@ -374,7 +374,7 @@ template <typename T>
 void gather_rows(const cplx<T> *src, const int *idx, int m, int64_t K, cplx<T> *dst,
                  hipStream_t st) {
   if (m <= 0) return;
-  hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((K + 255) / 256), m), dim3(256), 0, st, src, idx,
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_gather.f64" : "k_gather.f32"), k_gather<T>, dim3((unsigned)((K + 255) / 256), m), dim3(256), 0, st, src, idx,
                      K, dst);
   DKS_HIP(hipGetLastError());
 }
@@ -390,7 +390,7 @@ __global__ void k_convert(const typename CT<Ts>::c *__restrict__ s, typename CT<
 template <typename Ts, typename Td>
 void convert(const cplx<Ts> *src, cplx<Td> *dst, int64_t count, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_convert<Ts, Td>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+  DKS_LAUNCH((sizeof(Ts) == 8 ? "k_convert.f64_f32" : "k_convert.f32_f64"), (k_convert<Ts, Td>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
                      src, dst, count);
   DKS_HIP(hipGetLastError());
 }
@@ -409,7 +409,7 @@ __global__ void k_scale_rows(typename CT<T>::c *X, const double *s, int64_t K) {
 template <typename T>
 void scale_rows(cplx<T> *X, const double *s, int n, int64_t K, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_scale_rows<T>, dim3((unsigned)((K + 255) / 256), n), dim3(256), 0, st, X, s, K);
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_scale_rows.f64" : "k_scale_rows.f32"), k_scale_rows<T>, dim3((unsigned)((K + 255) / 256), n), dim3(256), 0, st, X, s, K);
   DKS_HIP(hipGetLastError());
 }
 template void scale_rows<double>(double2 *, const double *, int, int64_t, hipStream_t);

@@ -86,6 +86,25 @@ struct DevBuf {
 
 void upload(DevBuf &b, const void *host, size_t bytes);
 
+// Launch a kernel, bracketed by profiling events when profiling is enabled.
+#define DKS_LAUNCH(name, kern, grid, block, smem, st, ...)        \
+  do {                                                            \
+    ::dks::ProfScope ps_((name), (st));                           \
+    hipLaunchKernelGGL(kern, grid, block, smem, st, __VA_ARGS__); \
+  } while (0)
+
+// Brackets one kernel launch with HIP events when profiling is enabled.
+struct ProfScope {
+  ProfScope(const char *name, hipStream_t st);
+  ~ProfScope();
+  ProfScope(const ProfScope &) = delete;
+  ProfScope &operator=(const ProfScope &) = delete;
+
+ private:
+  hipStream_t st_;
+  int idx_ = -1;
+};
+
 // ---------------------------------------------------------------------------
 // one system (one description at one k-point)
 // ---------------------------------------------------------------------------
@@ -123,6 +142,7 @@ struct System {
   DevBuf d_W64;                                   // all W blocks, complex double
   DevBuf d_Winfo;                                 // per (group): int4 {p0, dim, woff, 0}
   FftPlan plan[3];
+  DevBuf d_plan;                                  // the three plans, for the kernels
   int tile_z;                                     // xy-columns per z-FFT workgroup
 };
 
@@ -191,11 +211,13 @@ void scale_rows(cplx<T> *X, const double *s, int n, int64_t K, hipStream_t st);
 // small component from the large one by kinetic balance, in place on [n][4][N]
 void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st);
 
-// Rayleigh-Ritz on (A, S) of size nz: V (nz x nkeep, row-major ld nkeep), theta (nkeep),
-// info[0] = kept count, info[1] = status (0 ok, 1 too few kept), info[2] = dropped;
-// dinfo[0] = smallest Ritz value.  `forced_drop` (nz ints or null): 1 marks a column to skip.
+// Rayleigh-Ritz on (A, S) of size nz: V (nz x nkeep, row-major ld nkeep), theta (nkeep) are
+// the nkeep lowest Ritz pairs above floor_val.  info[0] = kept basis columns, info[1] =
+// status (0 ok, 1 too few independent columns, 2 too few Ritz values above floor_val),
+// info[2] = dropped columns, info[3] = Ritz values below floor_val; dinfo[0] = smallest
+// Ritz value.  `forced_drop` (nz ints or null): 1 marks a column to skip.
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
-                   const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
+                   double floor_val, const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
                    DevBuf &scratch, hipStream_t st);
 
 }  // namespace dks

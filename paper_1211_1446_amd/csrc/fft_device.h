@@ -173,22 +173,30 @@ __device__ void fft_pass(typename CT<T>::c *buf, int nlines, const int *rowlist,
   __syncthreads();
 }
 
-// Full 1D transform of length plan.n on every line.  Caller synchronises before.
+// Full 1D transform of length plan.n on every line (natural order in and
+// out), lines processed in chunks that fit kMaxElems per thread.  Caller
+// synchronises before.
 template <int S, typename T>
 __device__ void fft_lines(typename CT<T>::c *buf, int nlines, const int *rowlist, int ld,
                           int stride, const FftPlan &plan, const typename CT<T>::c *tw) {
-  int Ns = 1;
-  for (int p = 0; p < plan.npass; ++p) {
-    int R = plan.radix[p];
-    switch (R) {
-      case 8: fft_pass<8, S, T>(buf, nlines, rowlist, ld, stride, plan.n, Ns, tw); break;
-      case 6: fft_pass<6, S, T>(buf, nlines, rowlist, ld, stride, plan.n, Ns, tw); break;
-      case 5: fft_pass<5, S, T>(buf, nlines, rowlist, ld, stride, plan.n, Ns, tw); break;
-      case 4: fft_pass<4, S, T>(buf, nlines, rowlist, ld, stride, plan.n, Ns, tw); break;
-      case 3: fft_pass<3, S, T>(buf, nlines, rowlist, ld, stride, plan.n, Ns, tw); break;
-      default: fft_pass<2, S, T>(buf, nlines, rowlist, ld, stride, plan.n, Ns, tw); break;
+  const int chunk = max(1, (int)(kMaxElems * blockDim.x) / plan.n);
+  for (int l0 = 0; l0 < nlines; l0 += chunk) {
+    const int nl = min(chunk, nlines - l0);
+    const int *rl = rowlist ? rowlist + l0 : nullptr;
+    typename CT<T>::c *bb = rowlist ? buf : buf + (size_t)l0 * ld;
+    int Ns = 1;
+    for (int p = 0; p < plan.npass; ++p) {
+      int R = plan.radix[p];
+      switch (R) {
+        case 8: fft_pass<8, S, T>(bb, nl, rl, ld, stride, plan.n, Ns, tw); break;
+        case 6: fft_pass<6, S, T>(bb, nl, rl, ld, stride, plan.n, Ns, tw); break;
+        case 5: fft_pass<5, S, T>(bb, nl, rl, ld, stride, plan.n, Ns, tw); break;
+        case 4: fft_pass<4, S, T>(bb, nl, rl, ld, stride, plan.n, Ns, tw); break;
+        case 3: fft_pass<3, S, T>(bb, nl, rl, ld, stride, plan.n, Ns, tw); break;
+        default: fft_pass<2, S, T>(bb, nl, rl, ld, stride, plan.n, Ns, tw); break;
+      }
+      Ns *= R;
     }
-    Ns *= R;
   }
 }
 

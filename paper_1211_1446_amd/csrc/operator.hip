@@ -12,6 +12,7 @@
 //   C = B^H X (matrix-core inner products), C' = W C per (atom, l) and
 //   two-spinor, HX = B C' + kinetic(X) - shift X.
 #include "dks_internal.h"
+#include "fft2.h"
 #include "fft_device.h"
 
 namespace dks {
@@ -23,12 +24,13 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__restrict__ X, int N,
                                                   const int *__restrict__ col_off,
                                                   const int2 *__restrict__ gmap, int ncol,
-                                                  int tile, FftPlan pz,
+                                                  int tile, const FftPlan *__restrict__ pzp,
                                                   const typename CT<T>::c *__restrict__ twz,
                                                   typename CT<T>::c *__restrict__ T1) {
   using C = typename CT<T>::c;
   extern __shared__ unsigned char smem_raw[];
   C *lines = reinterpret_cast<C *>(smem_raw);
+  const FftPlan &pz = *pzp;
   const int n3 = pz.n;
   const int ld = n3 + 1;
   const int c0 = blockIdx.x * tile;
@@ -43,7 +45,14 @@ __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__res
     lines[(m.x - c0) * ld + m.y] = x[g];
   }
   __syncthreads();
-  fft_lines<+1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  const fft2::Lines Lz{nullptr, ld, 1};
+  bool fast = fft2::dispatch_z(n3, [&]<int A, int B>() {
+    fft2::inv_step1<A, B, T>(lines, w, Lz, twz);
+    __syncthreads();
+    fft2::inv_step2<A, B, T>(lines, w, Lz);
+  });
+  if (!fast) fft_lines<+1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  __syncthreads();
   C *t = T1 + (size_t)cc * n3 * ncol;
   for (int e = threadIdx.x; e < w * n3; e += blockDim.x) {
     int z = e / w, ci = e - (e / w) * w;
@@ -56,12 +65,13 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
                                                   typename CT<T>::c *__restrict__ HX, int N,
                                                   const int *__restrict__ col_off,
                                                   const int2 *__restrict__ gmap, int ncol,
-                                                  int tile, FftPlan pz,
+                                                  int tile, const FftPlan *__restrict__ pzp,
                                                   const typename CT<T>::c *__restrict__ twz,
                                                   T inv_ng, T scale) {
   using C = typename CT<T>::c;
   extern __shared__ unsigned char smem_raw[];
   C *lines = reinterpret_cast<C *>(smem_raw);
+  const FftPlan &pz = *pzp;
   const int n3 = pz.n;
   const int ld = n3 + 1;
   const int c0 = blockIdx.x * tile;
@@ -73,7 +83,14 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
     lines[ci * ld + z] = t[(size_t)z * ncol + c0 + ci];
   }
   __syncthreads();
-  fft_lines<-1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  const fft2::Lines Lz{nullptr, ld, 1};
+  bool fast = fft2::dispatch_z(n3, [&]<int A, int B>() {
+    fft2::fwd_step2<A, B, T>(lines, w, Lz, twz);
+    __syncthreads();
+    fft2::fwd_step1<A, B, T>(lines, w, Lz, twz);
+  });
+  if (!fast) fft_lines<-1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  __syncthreads();
   C *hx = HX + (size_t)cc * N;
   const int g0 = col_off[c0], g1 = col_off[c0 + w];
   for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
@@ -88,16 +105,17 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
 // one z plane: 2D inverse FFT, x V, 2D forward FFT, all in LDS
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(1024) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
+__global__ void __launch_bounds__(512) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
                                                 const int4 *__restrict__ col_info,
                                                 const int *__restrict__ rows, int nrows,
-                                                FftPlan px, FftPlan py,
+                                                const FftPlan *__restrict__ pxy,
                                                 const typename CT<T>::c *__restrict__ twx,
                                                 const typename CT<T>::c *__restrict__ twy,
                                                 const T *__restrict__ V) {
   using C = typename CT<T>::c;
   extern __shared__ unsigned char smem_raw[];
   C *pl = reinterpret_cast<C *>(smem_raw);
+  const FftPlan &px = pxy[0], &py = pxy[1];
   const int n1 = px.n, n2 = py.n;
   const int ld = n2 + 1;
   const int z = blockIdx.x;
@@ -111,20 +129,45 @@ __global__ void __launch_bounds__(1024) k_plane(typename CT<T>::c *__restrict__ 
     pl[ci.x * ld + ci.y] = t[c];
   }
   __syncthreads();
-  // along a2 (contiguous), only rows that hold sphere columns
-  fft_lines<+1, T>(pl, nrows, rows, ld, 1, py, twy);
-  // along a1 (stride ld), every a2 position
-  fft_lines<+1, T>(pl, n2, nullptr, 1, ld, px, twx);
-  const T *v = V + (size_t)z * n1 * n2;
-  for (int e = threadIdx.x; e < n1 * n2; e += blockDim.x) {
-    int i = e / n2, j = e - (e / n2) * n2;
-    T s = v[e];
-    C a = pl[i * ld + j];
-    pl[i * ld + j] = C{a.x * s, a.y * s};
+  const T *v = V + (size_t)z * n1 * n2;   // potential of this plane, [p1][p2] scrambled
+  const fft2::Lines Ly{rows, ld, 1};       // rows holding sphere columns, along a2
+  const fft2::Lines Lx{nullptr, 1, ld};    // every a2 position, along a1
+  // inverse along a2
+  bool fy = fft2::dispatch_plane(n2, [&]<int A, int B>() {
+    fft2::inv_step1<A, B, T>(pl, nrows, Ly, twy);
+    __syncthreads();
+    fft2::inv_step2<A, B, T>(pl, nrows, Ly);
+  });
+  if (!fy) fft_lines<+1, T>(pl, nrows, rows, ld, 1, py, twy);
+  __syncthreads();
+  // inverse along a1, x V, forward along a1
+  bool fx = fft2::dispatch_plane(n1, [&]<int A, int B>() {
+    fft2::inv_step1<A, B, T>(pl, n2, Lx, twx);
+    __syncthreads();
+    fft2::inv2_mul_fwd2<A, B, T>(pl, n2, Lx, twx, v, 1, n2);
+    __syncthreads();
+    fft2::fwd_step1<A, B, T>(pl, n2, Lx, twx);
+  });
+  if (!fx) {
+    fft_lines<+1, T>(pl, n2, nullptr, 1, ld, px, twx);
+    for (int e = threadIdx.x; e < n1 * n2; e += blockDim.x) {
+      int i = e / n2, j = e - (e / n2) * n2;
+      T s = v[e];
+      C a = pl[i * ld + j];
+      pl[i * ld + j] = C{a.x * s, a.y * s};
+    }
+    __syncthreads();
+    fft_lines<-1, T>(pl, n2, nullptr, 1, ld, px, twx);
   }
   __syncthreads();
-  fft_lines<-1, T>(pl, n2, nullptr, 1, ld, px, twx);
-  fft_lines<-1, T>(pl, nrows, rows, ld, 1, py, twy);
+  // forward along a2
+  fy = fft2::dispatch_plane(n2, [&]<int A, int B>() {
+    fft2::fwd_step2<A, B, T>(pl, nrows, Ly, twy);
+    __syncthreads();
+    fft2::fwd_step1<A, B, T>(pl, nrows, Ly, twy);
+  });
+  if (!fy) fft_lines<-1, T>(pl, nrows, rows, ld, 1, py, twy);
+  __syncthreads();
   for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
     int4 ci = col_info[c];
     t[c] = pl[ci.x * ld + ci.y];
@@ -234,7 +277,7 @@ __global__ void k_kinetic_balance(double2 *X, int N, int n, const double *q, dou
 void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st) {
   System &s = *b->sys[sys];
   dim3 grid((s.N + 255) / 256, n);
-  hipLaunchKernelGGL(k_kinetic_balance, grid, dim3(256), 0, st, X, s.N, n, s.d_q64.as<double>(),
+  DKS_LAUNCH("k_kinetic_balance", k_kinetic_balance, grid, dim3(256), 0, st, X, s.N, n, s.d_q64.as<double>(),
                      s.c);
   DKS_HIP(hipGetLastError());
 }
@@ -289,7 +332,7 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
     gemm_ip<T>(Btab<T>(s), nullptr, s.nproj, X, nullptr, ncols, nullptr, (int64_t)N,
                b->nlc.as<double2>(), nullptr, ncols, b->part, st);
     dim3 gw(nb * 2, (unsigned)s.groups.size());
-    hipLaunchKernelGGL(k_apply_w, gw, dim3(64), 0, st, b->nlc.as<double2>(), b->nlc2.as<double2>(),
+    DKS_LAUNCH("k_apply_w", k_apply_w, gw, dim3(64), 0, st, b->nlc.as<double2>(), b->nlc2.as<double2>(),
                        ncols, nb, s.d_Winfo.as<int4>(), (int)s.groups.size(), s.d_W64.as<double2>());
     DKS_HIP(hipGetLastError());
     Cp = b->nlc2.as<double2>();
@@ -297,7 +340,7 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   {
     dim3 grid((N + 255) / 256, (nb + kBT - 1) / kBT);
     size_t sm = sizeof(C) * (size_t)s.nproj * 4 * kBT;
-    hipLaunchKernelGGL(k_nl_kin<T>, grid, dim3(256), sm, st, X, HX, N, nb, Btab<T>(s), s.nproj, Cp,
+    DKS_LAUNCH((sizeof(T) == 8 ? "k_nl_kin.f64" : "k_nl_kin.f32"), k_nl_kin<T>, grid, dim3(256), sm, st, X, HX, N, nb, Btab<T>(s), s.nproj, Cp,
                        ncols, Qtab<T>(s), (T)s.c, (T)shift);
     DKS_HIP(hipGetLastError());
   }
@@ -308,17 +351,17 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   const int tile = s.tile_z;
   dim3 gz((s.ncol + tile - 1) / tile, ncols);
   size_t smz = sizeof(C) * (size_t)tile * (n3 + 1);
-  hipLaunchKernelGGL(k_zfft_inv<T>, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
-                     s.d_gmap.as<int2>(), s.ncol, tile, s.plan[2], Tw<T>(pot, 2), t1);
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_inv.f64" : "k_zfft_inv.f32"), k_zfft_inv<T>, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
+                     s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2), t1);
   DKS_HIP(hipGetLastError());
   dim3 gp(n3, ncols);
   size_t smp = sizeof(C) * (size_t)s.grid[0] * (s.grid[1] + 1);
-  hipLaunchKernelGGL(k_plane<T>, gp, dim3(1024), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
-                     s.d_rows.as<int>(), s.nrows, s.plan[0], s.plan[1], Tw<T>(pot, 0),
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), k_plane<T>, gp, dim3(512), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
+                     s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(), Tw<T>(pot, 0),
                      Tw<T>(pot, 1), Vtab<T>(pot));
   DKS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_zfft_fwd<T>, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
-                     s.d_gmap.as<int2>(), s.ncol, tile, s.plan[2], Tw<T>(pot, 2),
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_fwd.f64" : "k_zfft_fwd.f32"), k_zfft_fwd<T>, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
+                     s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2),
                      (T)(1.0 / s.ng), (T)scale);
   DKS_HIP(hipGetLastError());
 }

@@ -8,7 +8,9 @@
 //      earlier columns) is removed from the subspace instead of failing;
 //   3. C = L^-1 (D A D) L^-H on the kept columns;
 //   4. Householder reduction C = Q T Q^H to a real symmetric tridiagonal T;
-//   5. the nkeep smallest eigenvalues of T by bisection on Sturm counts;
+//   5. the nkeep smallest eigenvalues of T above `floor_val` by bisection on
+//      Sturm counts (floor_val = -c^2 discards Ritz values that belong to the
+//      negative band; -inf keeps the plain lowest nkeep);
 //   6. their eigenvectors by inverse iteration, re-orthogonalised inside
 //      clusters of (nearly) equal eigenvalues such as Kramers pairs;
 //   7. back-transformation v = D L^-H Q y.
@@ -71,7 +73,7 @@ __device__ double start_entry(int i, int j) {
 
 __global__ void __launch_bounds__(kRRThreads) k_rayleigh_ritz(
     const double2 *__restrict__ Ain, const double2 *__restrict__ Sin, int nz, int nkeep,
-    double drop_tol, const int *__restrict__ forced, double2 *__restrict__ Vout,
+    double drop_tol, double floor_val, const int *__restrict__ forced, double2 *__restrict__ Vout,
     double *__restrict__ theta, int *__restrict__ info, double *__restrict__ dinfo,
     double2 *__restrict__ ws) {
   __shared__ double dsc[kRRMax];
@@ -79,7 +81,8 @@ __global__ void __launch_bounds__(kRRThreads) k_rayleigh_ritz(
   __shared__ double dd[kRRMax], ee[kRRMax], e2[kRRMax], lam[kRRMax];
   __shared__ double2 tauv[kRRMax], vv[kRRMax], wv[kRRMax];
   __shared__ double red[32];
-  __shared__ int s_r, s_flag;
+  __shared__ int s_r, s_flag, s_k0;
+  __shared__ double s_lmin;
   __shared__ double s_ljj;
   __shared__ double2 s_tau, s_alpha2;
 
@@ -293,15 +296,31 @@ __global__ void __launch_bounds__(kRRThreads) k_rayleigh_ritz(
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
   glo -= 2.0 * DBL_EPSILON * tnorm + 2 * pivmin;
   ghi += 2.0 * DBL_EPSILON * tnorm + 2 * pivmin;
-  for (int t = tid; t < nkeep; t += nt) {
+  // Ritz values below floor_val (the mid-gap -c^2) belong to the negative band;
+  // the kept pairs are the nkeep lowest above it.
+  if (tid == 0) {
+    int k0 = (floor_val > glo) ? sturm_count(dd, e2, r, floor_val, pivmin) : 0;
+    s_k0 = k0;
+    info[3] = k0;
+    if (r - k0 < nkeep) {
+      s_flag = 2;
+      info[1] = 2;
+    }
+  }
+  __syncthreads();
+  if (s_flag) return;
+  const int k0 = s_k0;
+  for (int t = tid; t <= nkeep; t += nt) {
+    // t < nkeep: kept eigenvalue k0 + t; t == nkeep: the smallest (index 0), for monitoring
+    const int idx = (t < nkeep) ? k0 + t : 0;
     double lo = glo, hi = ghi;
     for (int it = 0; it < 200; ++it) {
       double mid = 0.5 * (lo + hi);
       if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
       if (mid <= lo || mid >= hi) break;
-      if (sturm_count(dd, e2, r, mid, pivmin) <= t) lo = mid; else hi = mid;
+      if (sturm_count(dd, e2, r, mid, pivmin) <= idx) lo = mid; else hi = mid;
     }
-    lam[t] = 0.5 * (lo + hi);
+    if (t < nkeep) lam[t] = 0.5 * (lo + hi); else s_lmin = 0.5 * (lo + hi);
   }
   __syncthreads();
 
@@ -411,11 +430,11 @@ __global__ void __launch_bounds__(kRRThreads) k_rayleigh_ritz(
     Vout[(size_t)kb * nkeep + j] = make_double2(f * s.x, f * s.y);
   }
   for (int t = tid; t < nkeep; t += nt) theta[t] = lam[t];
-  if (tid == 0) dinfo[0] = lam[0];
+  if (tid == 0) dinfo[0] = s_lmin;
 }
 
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
-                   const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
+                   double floor_val, const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
                    DevBuf &scratch, hipStream_t st) {
   DKS_REQUIRE(nz > 0 && nz <= kRRMax && nkeep > 0 && nkeep <= nz, DKS_EINVAL,
               "Rayleigh-Ritz size out of range (subspace dimension must be <= 512)");
@@ -423,8 +442,8 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
   size_t bytes = sizeof(double2) * (5 * nn + (size_t)nz * nkeep) + sizeof(double) * (size_t)nz * nkeep +
                  sizeof(double) * 5 * (size_t)nz * nkeep;
   scratch.ensure(bytes);
-  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(kRRThreads), 0, st, A, S, nz, nkeep, drop_tol,
-                     forced_drop, V, theta, info, dinfo, scratch.as<double2>());
+  DKS_LAUNCH("k_rayleigh_ritz", k_rayleigh_ritz, dim3(1), dim3(kRRThreads), 0, st, A, S, nz, nkeep, drop_tol,
+                     floor_val, forced_drop, V, theta, info, dinfo, scratch.as<double2>());
   DKS_HIP(hipGetLastError());
 }
 

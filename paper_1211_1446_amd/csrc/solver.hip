@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -70,6 +71,8 @@ struct Ctx {
   double C, Om, c2;
   int64_t K;
   int N;
+  int iter_slot = 0, iter_cap = 0;   // entries written to / capacity of opts.iter_ms
+  double floor = -1e300;              // Ritz values below are discarded (mid-gap -c^2 with F)
 };
 
 // Row offsets of Z = [rows 0..n) U [n, n+m) U [2n, 2n+mp) of a 3n-row block.
@@ -88,6 +91,15 @@ static void filter_inplace(Ctx &x, cplx<T> *Y, cplx<T> *W, int m) {
   apply_h<T>(x.b, x.sys, W, Y, m, x.C, 1.0 / (x.Om * x.Om), x.st);
   if (x.info) x.info->h_applies += 2 * m;
 }
+
+static double residual_level(std::vector<double> r) {
+  std::nth_element(r.begin(), r.begin() + r.size() / 2, r.end());
+  return r[r.size() / 2];
+}
+
+constexpr int kStallFp64 = 10;     // iterations without a new best residual before stopping
+constexpr int kStallFp32 = 4;
+constexpr int kPolishFilters = 2;  // filter applications on the block entering the FP64 polish
 
 template <typename T> struct LoopState {
   int cur = 0;
@@ -109,7 +121,7 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int nz = n + s.m + mp;
     sv.off.ensure(sizeof(int64_t) * 3 * n);
-    hipLaunchKernelGGL(k_offsets, dim3((nz + 255) / 256), dim3(256), 0, x.st, sv.off.as<int64_t>(),
+    DKS_LAUNCH("k_offsets", k_offsets, dim3((nz + 255) / 256), dim3(256), 0, x.st, sv.off.as<int64_t>(),
                        n, s.m, mp, bk.K);
     DKS_HIP(hipGetLastError());
     sv.gS.ensure(sizeof(double2) * nz * nz);
@@ -122,7 +134,7 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
     sv.theta.ensure(sizeof(double) * n);
     sv.rinfo.ensure(sizeof(int) * 4);
     sv.rdinfo.ensure(sizeof(double) * 2);
-    rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, drop_tol, nullptr,
+    rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, drop_tol, x.floor, nullptr,
                   sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
                   sv.rdinfo.as<double>(), sv.rrs, x.st);
     int info[4];
@@ -138,6 +150,7 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
     if (info[1] == 0) {
       if (x.info) {
         x.info->basis_drops += info[2];
+        x.info->neg_ritz_discarded += info[3];
         x.info->min_ritz = std::min(x.info->min_ritz, dinfo[0]);
       }
       s.mp = mp;
@@ -213,7 +226,7 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
 // `first`: apply the initial filtering (lines 1-3) before the first Rayleigh-Ritz.
 template <typename T>
 static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n_init,
-                            double tol, int max_iter, double drop_tol, bool stagnation_exit) {
+                            double tol, int max_iter, double drop_tol, int stall_window) {
   Solver &sv = *x.sv;
   const bool filt = x.o->use_filter != 0;
   s.cur = 0;
@@ -230,10 +243,11 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   if (!ritz<T>(x, bk, s, n, drop_tol, hV))
     throw Error{DKS_ECHOL, "the start block is numerically rank deficient"};
   update<T>(x, bk, s, n, hV, tol);
-  double best = *std::max_element(s.res.begin(), s.res.end());
+  double best = residual_level(s.res);
   int stall = 0;
   // lines 8-23
   while (!s.converged && s.iters < max_iter) {
+    const auto t0 = std::chrono::steady_clock::now();
     s.iters++;
     if (x.info) x.info->iterations++;
     const int m = s.m;
@@ -250,14 +264,19 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
       throw Error{DKS_ECHOL, "Rayleigh-Ritz lost the X block"};
     // lines 15-22
     update<T>(x, bk, s, n, hV, tol);
-    double worst = *std::max_element(s.res.begin(), s.res.end());
-    if (stagnation_exit) {
-      if (worst < 0.7 * best) {
-        best = worst;
-        stall = 0;
-      } else if (++stall >= 3) {
-        break;
-      }
+    if (x.o->iter_ms && x.iter_slot < x.iter_cap)
+      x.o->iter_ms[x.iter_slot++] =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // stagnation: no new best residual level for `stall_window` iterations means
+    // the iteration sits on its rounding floor; stop instead of iterating on
+    // noise.  The level is the median residual (the worst one is gap-limited and
+    // not monotone in the first iterations).
+    double level = residual_level(s.res);
+    if (level < 0.9 * best) {
+      best = level;
+      stall = 0;
+    } else if (stall_window > 0 && ++stall >= stall_window) {
+      break;
     }
   }
   return s.converged ? DKS_OK : DKS_WNOTCONV;
@@ -370,6 +389,8 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
     DKS_REQUIRE(std::isfinite(x.C) && std::isfinite(x.Om) && x.Om != 0.0, DKS_EINVAL, "bad C or Omega");
     inf.C = x.C;
     inf.Omega = x.Om;
+    x.iter_cap = o.n_iter + (o.mode != DKS_MODE_FP64 ? o.mixed_iter : 0);
+    x.floor = o.use_filter ? -x.c2 : -std::numeric_limits<double>::infinity();
     double2 *Xu = (double2 *)X;
     if (o.kinetic_balance) kinetic_balance(b, sys, Xu, n, st);
     dks_status rc = DKS_OK;
@@ -377,23 +398,26 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
     if (o.mode == DKS_MODE_FP64) {
       x.sv->b64.ensure(n, x.K);
       DKS_HIP(hipMemcpyAsync(x.sv->b64.z(0, 0), Xu, sizeof(double2) * x.K * n, hipMemcpyDeviceToDevice, st));
-      rc = run_stage<double>(x, x.sv->b64, s64, n, o.n_init, o.tol, o.n_iter, 1e-10, false);
+      rc = run_stage<double>(x, x.sv->b64, s64, n, o.n_init, o.tol, o.n_iter, 1e-10, kStallFp64);
     } else {
       // reduced-precision stage
       x.sv->b32.ensure(n, x.K);
       LoopState<float> s32;
       convert<double, float>(Xu, x.sv->b32.z(0, 0), x.K * n, st);
-      run_stage<float>(x, x.sv->b32, s32, n, o.n_init, o.mixed_tol, o.mixed_iter, 1e-5, true);
+      const bool fixed = !(o.mixed_tol > 0);   // mixed_tol <= 0: exactly mixed_iter iterations
+      run_stage<float>(x, x.sv->b32, s32, n, o.n_init, fixed ? 0.0 : o.mixed_tol, o.mixed_iter, 1e-5,
+                       fixed ? 0 : kStallFp32);
       inf.iters_reduced = s32.iters;
       // FP64 polish.  The reduced-precision block carries rounding noise of
-      // relative size ~1e-8 in every direction, including the negative band,
-      // where the residual amplifies it by ~2c^2 (the gamma_LOBPCG ~ Delta/w of
-      // Sec. 3.1); one filter application in FP64 (N_init = 1, the paper's
-      // choice for a warm start) damps it below the FP64 tolerance.
+      // relative size up to ~1e-7 in every direction, including the negative
+      // band, where the residual amplifies it by ~2c^2 (the gamma_LOBPCG ~ Delta/w
+      // of Sec. 3.1) and where Y and P, being filtered, cannot remove it.  Two
+      // filter applications in FP64 (each damping the negative band by
+      // ~(w/2c^2)^2) push it far below the FP64 tolerance.
       x.sv->b64.ensure(n, x.K);
       convert<float, double>(x.sv->b32.z(s32.cur, 0), x.sv->b64.z(0, 0), x.K * n, st);
       s64.iters = 0;
-      rc = run_stage<double>(x, x.sv->b64, s64, n, 1, o.tol, o.n_iter, 1e-10, false);
+      rc = run_stage<double>(x, x.sv->b64, s64, n, kPolishFilters, o.tol, o.n_iter, 1e-10, kStallFp64);
     }
     Blocks<double> &bk = x.sv->b64;
     DKS_HIP(hipMemcpyAsync(Xu, bk.z(s64.cur, 0), sizeof(double2) * x.K * n, hipMemcpyDeviceToDevice, st));
