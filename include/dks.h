@@ -130,7 +130,9 @@ dks_status dks_filter_constants(const dks_basis *b, int sys, double *C, double *
 
 typedef struct {
   double C, Omega;      /* filter constants; NaN selects dks_filter_constants */
-  int n_init;           /* initial filter applications (Alg. 1 lines 1-3); paper: 3 then 1 */
+  int n_init;           /* filter applications on X0 before the first Rayleigh-Ritz (the
+                           initial filtering of Algorithm 1; the paper uses 3, then 1 for a
+                           warm start) */
   int n_iter;           /* maximum iterations of the main loop */
   double tol;           /* convergence: 2-norm of every residual column < tol (Ha) */
   int mode;             /* dks_mode */

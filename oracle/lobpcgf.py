@@ -87,7 +87,7 @@ class LobpcgResult:
 
 
 def _ritz(A: np.ndarray, S: np.ndarray):
-    """Generalized Hermitian eigenproblem A V = S V Lambda, ascending (Alg. 1 lines 4, 12)."""
+    """Generalized Hermitian eigenproblem A V = S V Lambda, ascending (the Rayleigh-Ritz steps of Algorithm 1)."""
     A = 0.5 * (A + A.conj().T)
     S = 0.5 * (S + S.conj().T)
     return sla.eigh(A, S)
@@ -112,19 +112,19 @@ def lobpcgf(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,
         return apply_filter(apply_h, Y, C, Omega)
 
     X = np.array(X0, dtype=np.complex128, copy=True)
-    # lines 1-3: initial filtering
+    # initial filtering of the start block
     if use_filter:
         for _ in range(n_init):
             X = f_of_h(X)
             X, _ = _unit_columns(X)
-    # line 4: Rayleigh-Ritz on X0
+    # Rayleigh-Ritz on the filtered start block
     HX = apply_h(X)
     lam, V = _ritz(X.conj().T @ HX, X.conj().T @ X)
     lam, V = lam[:n], V[:, :n]
-    # line 5
+    # rotate the block onto the Ritz vectors
     X = X @ V
     HX = HX @ V
-    # line 6
+    # first residual
     R = HX - X * lam[None, :]
     P = HP = None
     hist_min: List[float] = [float(lam.min())]
@@ -136,16 +136,16 @@ def lobpcgf(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,
     converged = bool(active.size == 0)
     while not converged and it < n_iter:
         it += 1
-        # line 9: T Y = R on the active columns
+        # preconditioned residual: T Y = R on the active columns
         Y = R[:, active]
         if precond is not None:
             Y = precond(Y)
-        # line 10: Y <- f(H) Y
+        # the filtering step: Y <- f(H) Y
         if use_filter:
             Y = f_of_h(Y)
         Y, _ = _unit_columns(Y)
         HY = apply_h(Y)
-        # line 11: Z = [X, Y, P]
+        # subspace Z = [X, Y, P]
         blocks = [X, Y] + ([P] if P is not None else [])
         hblocks = [HX, HY] + ([HP] if P is not None else [])
         try:
@@ -160,26 +160,26 @@ def lobpcgf(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,
             HZ = np.concatenate([HX, HY], axis=1)
             P = HP = None
             theta, Vz = _ritz(Z.conj().T @ HZ, Z.conj().T @ Z)
-        # lines 13-14
+        # keep the first n Ritz pairs
         V = Vz[:, :n]
         lam = theta[:n]
         hist_min.append(float(theta.min()))
         if max_history:
             hist.append(theta.copy())
-        # line 15 (and the same combination of HZ)
+        # new block X = Z V (and the same combination of HZ)
         X = Z @ V
         HX = HZ @ V
-        # line 16
+        # residual
         R = HX - X * lam[None, :]
         norms = np.linalg.norm(R, axis=0)
-        # lines 17-19
+        # convergence test on every column
         if np.all(norms < tol):
             converged = True
             break
-        # lines 20-21
+        # soft locking: keep the unconverged columns
         active = np.nonzero(norms >= tol)[0]
         Va = V[:, active]
-        # line 22: P <- [0, Y, P] V   (HP alike)
+        # conjugate directions P <- [0, Y, P] V   (HP alike)
         nx = X.shape[1]
         P = Z[:, nx:] @ Va[nx:, :]
         HP = HZ[:, nx:] @ Va[nx:, :]

@@ -218,6 +218,6 @@ void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st);
 // Ritz value.  `forced_drop` (nz ints or null): 1 marks a column to skip.
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
-                   DevBuf &scratch, hipStream_t st);
+                   DevBuf &scratch, hipStream_t st, long long *tstamp = nullptr);
 
 }  // namespace dks

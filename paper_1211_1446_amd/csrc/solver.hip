@@ -1,7 +1,7 @@
 // Algorithm 1 (LOBPCG-F) driven from the host: every step on the block runs in
 // the library's kernels on one stream; the host reads back only the small
 // Rayleigh-Ritz results and the residual norms once per iteration to decide
-// convergence and the active (unlocked) columns (Alg. 1 lines 17-21).
+// convergence and the active (unlocked) columns of Algorithm 1.
 //
 // Workspace per precision: two copies of the subspace Z = [X | Y | P] and of
 // HZ = [HX | HY | HP] (3n rows each, K = 4N complex per row), a residual block
@@ -43,7 +43,7 @@ template <typename T> struct Blocks {
 struct Solver {
   Blocks<double> b64;
   Blocks<float> b32;
-  DevBuf gS, gA, Vz, Vp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2;
+  DevBuf gS, gA, Vz, Vp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2, tst;
 };
 
 static Solver *solver_of(dks_basis *b) {
@@ -134,9 +134,19 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
     sv.theta.ensure(sizeof(double) * n);
     sv.rinfo.ensure(sizeof(int) * 4);
     sv.rdinfo.ensure(sizeof(double) * 2);
+    const bool stamps = log_enabled();
+    if (stamps) sv.tst.ensure(sizeof(long long) * 16);
     rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, drop_tol, x.floor, nullptr,
                   sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
-                  sv.rdinfo.as<double>(), sv.rrs, x.st);
+                  sv.rdinfo.as<double>(), sv.rrs, x.st, stamps ? sv.tst.as<long long>() : nullptr);
+    if (stamps) {
+      long long ts[9];
+      DKS_HIP(hipMemcpyAsync(ts, sv.tst.p, sizeof(ts), hipMemcpyDeviceToHost, x.st));
+      DKS_HIP(hipStreamSynchronize(x.st));
+      std::fprintf(stderr, "{\"rr_phase_us\": [");
+      for (int k = 1; k < 9; ++k) std::fprintf(stderr, "%s%.1f", k > 1 ? ", " : "", (ts[k] - ts[k - 1]) / 100.0);
+      std::fprintf(stderr, "]}\n");
+    }
     int info[4];
     double dinfo[2];
     DKS_HIP(hipMemcpyAsync(info, sv.rinfo.p, sizeof(int) * 4, hipMemcpyDeviceToHost, x.st));
@@ -202,7 +212,7 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
   if (mnew == 0) {
     s.converged = true;
   } else if (s.m + s.mp > 0) {
-    // P = [0, Y, P] V[:, act]  (Alg. 1 line 22), HP alike
+    // conjugate directions P = [0, Y, P] V[:, act] (Algorithm 1), HP alike
     const int nyp = s.m + s.mp;
     std::vector<double2> vp((size_t)nyp * mnew);
     for (int i = 0; i < nyp; ++i)
@@ -223,7 +233,7 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
 }
 
 // One precision stage of Algorithm 1 on the block already in Z[cur] rows [0, n).
-// `first`: apply the initial filtering (lines 1-3) before the first Rayleigh-Ritz.
+// n_init: filter applications on the start block before the first Rayleigh-Ritz.
 template <typename T>
 static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n_init,
                             double tol, int max_iter, double drop_tol, int stall_window) {
@@ -233,10 +243,10 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   s.m = 0;
   s.mp = 0;
   s.converged = false;
-  // lines 1-3
+  // initial filtering of the start block
   if (filt)
     for (int k = 0; k < n_init; ++k) filter_inplace<T>(x, bk.z(0, 0), bk.W.template as<cplx<T>>(), n);
-  // lines 4-6: Rayleigh-Ritz on X0
+  // Rayleigh-Ritz on the start block, first residual
   apply_h<T>(x.b, x.sys, bk.z(0, 0), bk.hz(0, 0), n, 0.0, 1.0, x.st);
   if (x.info) x.info->h_applies += n;
   std::vector<double2> hV;
@@ -245,24 +255,24 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   update<T>(x, bk, s, n, hV, tol);
   double best = residual_level(s.res);
   int stall = 0;
-  // lines 8-23
+  // main loop
   while (!s.converged && s.iters < max_iter) {
     const auto t0 = std::chrono::steady_clock::now();
     s.iters++;
     if (x.info) x.info->iterations++;
     const int m = s.m;
-    // line 9 (T = I) : Y = R[:, active]
+    // preconditioned residual (T = I): Y = R[:, active]
     sv.idx.ensure(sizeof(int) * n);
     DKS_HIP(hipMemcpyAsync(sv.idx.p, s.act.data(), sizeof(int) * m, hipMemcpyHostToDevice, x.st));
     gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
-    // line 10 : Y = f(H) Y
+    // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
     apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st);
     if (x.info) x.info->h_applies += m;
-    // lines 11-14
+    // Rayleigh-Ritz on Z = [X, Y, P]
     if (!ritz<T>(x, bk, s, n, drop_tol, hV))
       throw Error{DKS_ECHOL, "Rayleigh-Ritz lost the X block"};
-    // lines 15-22
+    // new X, residuals, soft locking, new P
     update<T>(x, bk, s, n, hV, tol);
     if (x.o->iter_ms && x.iter_slot < x.iter_cap)
       x.o->iter_ms[x.iter_slot++] =
