@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__res
                                                   const typename CT<T>::c *__restrict__ twz,
                                                   typename CT<T>::c *__restrict__ T1) {
   using C = typename CT<T>::c;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   C *lines = reinterpret_cast<C *>(smem_raw);
   const FftPlan &pz = *pzp;
   const int n3 = pz.n;
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
                                                   const typename CT<T>::c *__restrict__ twz,
                                                   T inv_ng, T scale) {
   using C = typename CT<T>::c;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   C *lines = reinterpret_cast<C *>(smem_raw);
   const FftPlan &pz = *pzp;
   const int n3 = pz.n;
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(512) k_plane(typename CT<T>::c *__restrict__ T
                                                 const typename CT<T>::c *__restrict__ twy,
                                                 const T *__restrict__ V) {
   using C = typename CT<T>::c;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   C *pl = reinterpret_cast<C *>(smem_raw);
   const FftPlan &px = pxy[0], &py = pxy[1];
   const int n1 = px.n, n2 = py.n;
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(256) k_nl_kin(const typename CT<T>::c *__restr
                                                 const double2 *__restrict__ Cp, int ldc,
                                                 const T *__restrict__ q, T c, T shift) {
   using C = typename CT<T>::c;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   C *cs = reinterpret_cast<C *>(smem_raw);  // [nproj][4 kBT]
   const int b0 = blockIdx.y * kBT;
   const int bw = min(kBT, nb - b0);
