@@ -33,13 +33,29 @@ template <> struct Mfma<float> {
 constexpr int kIpTile = 64;   // output tile per workgroup (4 waves of 32 x 32)
 constexpr int kIpKT = 16;     // complex k values staged per step
 
+// Output tile (ti, tj) of workgroup x: row-major over all tiles, or over the
+// tiles on and above the diagonal when only the upper triangle is wanted.
+__device__ __forceinline__ void ip_tile(int x, int tm, bool upper, int &ti, int &tj) {
+  if (!upper) {
+    ti = x % tm;
+    tj = x / tm;
+    return;
+  }
+  ti = 0;
+  while (x >= tm - ti) {
+    x -= tm - ti;
+    ++ti;
+  }
+  tj = ti + x;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__restrict__ A,
                                                  const int64_t *__restrict__ aoff, int M,
                                                  const typename CT<T>::c *__restrict__ B,
                                                  const int64_t *__restrict__ boff, int Nn,
                                                  const typename CT<T>::c *__restrict__ B2,
-                                                 int64_t K, int64_t kchunk,
+                                                 int64_t K, int64_t kchunk, int tm, int upper,
                                                  double2 *__restrict__ part,
                                                  double2 *__restrict__ part2) {
   using C = typename CT<T>::c;
@@ -50,7 +66,9 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
   __shared__ C Bs[kIpTile * LD];
   __shared__ C B2s[kIpTile * LD];
   const bool two = (B2 != nullptr);
-  const int tm = blockIdx.x * kIpTile, tn = blockIdx.y * kIpTile;
+  int ti, tj;
+  ip_tile(blockIdx.x, tm, upper != 0, ti, tj);
+  const int tm0 = ti * kIpTile, tn0 = tj * kIpTile;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = min(K, kb + kchunk);
   const int tid = threadIdx.x;
@@ -59,9 +77,9 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
   // loader mapping: 4 threads per row, 4 consecutive complex each
   const int lrow = tid >> 2, lk = (tid & 3) * 4;
   const C *arow = nullptr, *brow = nullptr, *b2row = nullptr;
-  if (tm + lrow < M) arow = A + (aoff ? aoff[tm + lrow] : (int64_t)(tm + lrow) * K);
-  if (tn + lrow < Nn) {
-    int64_t o = boff ? boff[tn + lrow] : (int64_t)(tn + lrow) * K;
+  if (tm0 + lrow < M) arow = A + (aoff ? aoff[tm0 + lrow] : (int64_t)(tm0 + lrow) * K);
+  if (tn0 + lrow < Nn) {
+    int64_t o = boff ? boff[tn0 + lrow] : (int64_t)(tn0 + lrow) * K;
     brow = B + o;
     if (two) b2row = B2 + o;
   }
@@ -75,16 +93,28 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
       re2[i][j] = acc_t{0, 0, 0, 0};
       im2[i][j] = acc_t{0, 0, 0, 0};
     }
+  // the next k step is fetched into registers while the current one is multiplied
+  C ra[4], rb[4], rb2[4];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + lk + u;
+      const bool ok = k < ke;
+      ra[u] = (arow && ok) ? arow[k] : C{0, 0};
+      rb[u] = (brow && ok) ? brow[k] : C{0, 0};
+      if (two) rb2[u] = (b2row && ok) ? b2row[k] : C{0, 0};
+    }
+  };
+  if (kb < ke) fetch(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += kIpKT) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      int64_t k = k0 + lk + u;
-      bool ok = k < ke;
-      As[lrow * LD + lk + u] = (arow && ok) ? arow[k] : C{0, 0};
-      Bs[lrow * LD + lk + u] = (brow && ok) ? brow[k] : C{0, 0};
-      if (two) B2s[lrow * LD + lk + u] = (b2row && ok) ? b2row[k] : C{0, 0};
+      As[lrow * LD + lk + u] = ra[u];
+      Bs[lrow * LD + lk + u] = rb[u];
+      if (two) B2s[lrow * LD + lk + u] = rb2[u];
     }
     __syncthreads();
+    if (k0 + kIpKT < ke) fetch(k0 + kIpKT);
 #pragma unroll
     for (int s = 0; s < kIpKT / 4; ++s) {
       const int kk = s * 4 + (lane >> 4);
@@ -101,13 +131,20 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
         for (int j = 0; j < 2; ++j) {
           // conj(a) b: re += ar br + ai bi, im += ar bi - ai br
           re[i][j] = MF::mma(a[i].x, bb[j].x, re[i][j]);
-          re[i][j] = MF::mma(a[i].y, bb[j].y, re[i][j]);
           im[i][j] = MF::mma(a[i].x, bb[j].y, im[i][j]);
-          im[i][j] = MF::mma(-a[i].y, bb[j].x, im[i][j]);
           if (two) {
             re2[i][j] = MF::mma(a[i].x, b2[j].x, re2[i][j]);
-            re2[i][j] = MF::mma(a[i].y, b2[j].y, re2[i][j]);
             im2[i][j] = MF::mma(a[i].x, b2[j].y, im2[i][j]);
+          }
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          re[i][j] = MF::mma(a[i].y, bb[j].y, re[i][j]);
+          im[i][j] = MF::mma(-a[i].y, bb[j].x, im[i][j]);
+          if (two) {
+            re2[i][j] = MF::mma(a[i].y, b2[j].y, re2[i][j]);
             im2[i][j] = MF::mma(-a[i].y, b2[j].x, im2[i][j]);
           }
         }
@@ -122,8 +159,8 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int r = tm + wm + i * 16 + MF::row(lane, v);
-        int c = tn + wn + j * 16 + (lane & 15);
+        int r = tm0 + wm + i * 16 + MF::row(lane, v);
+        int c = tn0 + wn + j * 16 + (lane & 15);
         if (r < M && c < Nn) {
           p1[(size_t)r * Nn + c] = make_double2((double)re[i][j][v], (double)im[i][j][v]);
           if (two) p2[(size_t)r * Nn + c] = make_double2((double)re2[i][j][v], (double)im2[i][j][v]);
@@ -131,27 +168,38 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
       }
 }
 
-__global__ void k_reduce_part(const double2 *__restrict__ part, int nsplit, int M, int Nn,
-                              double2 *__restrict__ out, int ldo) {
+// out[i][j] = sum over splits; with `upper`, entries of tiles below the
+// diagonal were not computed and are the conjugates of their mirror images.
+// Both products (part -> out, part2 -> out2) in one launch.
+__global__ void k_reduce_part(const double2 *__restrict__ part, const double2 *__restrict__ part2,
+                              int nsplit, int M, int Nn, int upper, double2 *__restrict__ out,
+                              double2 *__restrict__ out2, int ldo) {
+  const int nel = M * Nn;
   int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M * Nn) return;
+  const bool second = e >= nel;
+  if (second) e -= nel;
+  if (e >= nel || (second && !part2)) return;
+  const double2 *p = second ? part2 : part;
+  const int i = e / Nn, j = e - (e / Nn) * Nn;
+  const bool mirror = upper && (i / kIpTile) > (j / kIpTile);
+  const int src = mirror ? j * Nn + i : e;
   double re = 0, im = 0;
   for (int z = 0; z < nsplit; ++z) {
-    double2 v = part[(size_t)z * M * Nn + e];
+    double2 v = p[(size_t)z * nel + src];
     re += v.x;
     im += v.y;
   }
-  int i = e / Nn, j = e - (e / Nn) * Nn;
-  out[(size_t)i * ldo + j] = make_double2(re, im);
+  (second ? out2 : out)[(size_t)i * ldo + j] = make_double2(re, mirror ? -im : im);
 }
 
 template <typename T>
 void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
              int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
-             DevBuf &part, hipStream_t st) {
+             DevBuf &part, hipStream_t st, bool hermitian) {
   if (M <= 0 || Nn <= 0) return;
   const int tm = (M + kIpTile - 1) / kIpTile, tn = (Nn + kIpTile - 1) / kIpTile;
-  const int tiles = tm * tn;
+  const bool upper = hermitian && M == Nn;
+  const int tiles = upper ? tm * (tm + 1) / 2 : tm * tn;
   int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
   int64_t nsplit = (1024 + tiles - 1) / tiles;
   nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
@@ -163,27 +211,24 @@ void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, con
   part.ensure(sizeof(double2) * (size_t)nsplit * M * Nn * nmat);
   double2 *p1 = part.as<double2>();
   double2 *p2 = B2 ? p1 + (size_t)nsplit * M * Nn : nullptr;
-  dim3 grid(tm, tn, (unsigned)nsplit);
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_gemm_ip.f64" : "k_gemm_ip.f32"), k_gemm_ip<T>, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk,
-                     p1, p2);
+  dim3 grid(tiles, 1, (unsigned)nsplit);
+  const char *name = upper ? (sizeof(T) == 8 ? "k_gemm_ip.gram.f64" : "k_gemm_ip.gram.f32")
+                           : (sizeof(T) == 8 ? "k_gemm_ip.f64" : "k_gemm_ip.f32");
+  DKS_LAUNCH(name, k_gemm_ip<T>, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk, tm,
+             (int)upper, p1, p2);
   DKS_HIP(hipGetLastError());
-  int nel = M * Nn;
-  DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p1, (int)nsplit, M,
-                     Nn, out, ldo);
+  int nel = M * Nn * nmat;
+  DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p1, p2,
+             (int)nsplit, M, Nn, (int)upper, out, out2, ldo);
   DKS_HIP(hipGetLastError());
-  if (B2) {
-    DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p2, (int)nsplit,
-                       M, Nn, out2, ldo);
-    DKS_HIP(hipGetLastError());
-  }
 }
 
 template void gemm_ip<double>(const double2 *, const int64_t *, int, const double2 *,
                               const int64_t *, int, const double2 *, int64_t, double2 *,
-                              double2 *, int, DevBuf &, hipStream_t);
+                              double2 *, int, DevBuf &, hipStream_t, bool);
 template void gemm_ip<float>(const float2 *, const int64_t *, int, const float2 *,
                              const int64_t *, int, const float2 *, int64_t, double2 *, double2 *,
-                             int, DevBuf &, hipStream_t);
+                             int, DevBuf &, hipStream_t, bool);
 
 // ---------------------------------------------------------------------------
 // block update

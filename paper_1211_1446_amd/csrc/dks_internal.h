@@ -177,11 +177,13 @@ void apply_h(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, doubl
              double scale, hipStream_t st);
 
 // out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
-// rows addressed by element offsets.  M, Nn <= 512.
+// rows addressed by element offsets.  M, Nn <= 512.  `hermitian` (A and B the same
+// rows, both products Hermitian): only the tiles on and above the diagonal are
+// multiplied, the rest are mirrored.
 template <typename T>
 void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
              int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
-             DevBuf &part, hipStream_t st);
+             DevBuf &part, hipStream_t st, bool hermitian = false);
 
 // out_j[k] = alpha * sum_i V[i][j] A_i[k] (+ beta out_j[k]); V FP64 m x n (ld ldv).
 template <typename T>

@@ -129,7 +129,7 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
     gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
                bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
                bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(), sv.gA.as<double2>(),
-               nz, sv.part, x.st);
+               nz, sv.part, x.st, /*hermitian=*/true);
     sv.Vz.ensure(sizeof(double2) * nz * n);
     sv.theta.ensure(sizeof(double) * n);
     sv.rinfo.ensure(sizeof(int) * 4);
