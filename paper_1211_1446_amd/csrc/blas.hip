@@ -233,37 +233,57 @@ template void gemm_ip<float>(const float2 *, const int64_t *, int, const float2 
 // ---------------------------------------------------------------------------
 // block update
 // ---------------------------------------------------------------------------
-constexpr int kUpJT = 16;
-constexpr int kUpICH = 64;
+constexpr int kUpICH = 64;   // rows of V staged in LDS at a time
+constexpr int kUpIU = 4;     // input rows whose loads are issued together
 
-template <typename T>
+// out_j[k] = sum_i V[i][j] A_i[k] (+ beta out_j[k]) for j in [j0, j0 + JT): one
+// thread per k holds all JT outputs, so each A element is read once per
+// column block; V rows are LDS broadcasts.
+template <typename T, int JT>
 __global__ void __launch_bounds__(256) k_gemm_up(const typename CT<T>::c *__restrict__ A,
                                                  const int64_t *__restrict__ aoff, int m,
                                                  const double2 *__restrict__ V, int ldv, int n,
                                                  int64_t K, typename CT<T>::c *__restrict__ out,
                                                  int64_t ldo, T beta) {
   using C = typename CT<T>::c;
-  __shared__ C Vs[kUpICH * kUpJT];
+  __shared__ C Vs[kUpICH * JT];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j0 = blockIdx.y * kUpJT;
-  C acc[kUpJT];
+  const int j0 = blockIdx.y * JT;
+  C acc[JT];
 #pragma unroll
-  for (int j = 0; j < kUpJT; ++j) acc[j] = C{0, 0};
+  for (int j = 0; j < JT; ++j) acc[j] = C{0, 0};
   for (int i0 = 0; i0 < m; i0 += kUpICH) {
     const int ic = min(kUpICH, m - i0);
-    for (int e = threadIdx.x; e < kUpICH * kUpJT; e += blockDim.x) {
-      int ii = e / kUpJT, jj = e - (e / kUpJT) * kUpJT;
-      double2 v = (ii < ic && j0 + jj < n) ? V[(size_t)(i0 + ii) * ldv + j0 + jj] : make_double2(0, 0);
+    for (int e = threadIdx.x; e < kUpICH * JT; e += blockDim.x) {
+      const int ii = e / JT, jj = e - (e / JT) * JT;
+      const double2 v = (ii < ic && j0 + jj < n) ? V[(size_t)(i0 + ii) * ldv + j0 + jj] : make_double2(0, 0);
       Vs[e] = C{(T)v.x, (T)v.y};
     }
     __syncthreads();
     if (k < K) {
-      for (int ii = 0; ii < ic; ++ii) {
-        const int i = i0 + ii;
-        C a = A[(aoff ? aoff[i] : (int64_t)i * K) + k];
+      int ii = 0;
+      for (; ii + kUpIU <= ic; ii += kUpIU) {
+        C a[kUpIU];
 #pragma unroll
-        for (int jj = 0; jj < kUpJT; ++jj) {
-          C v = Vs[ii * kUpJT + jj];
+        for (int u = 0; u < kUpIU; ++u) {
+          const int i = i0 + ii + u;
+          a[u] = A[(aoff ? aoff[i] : (int64_t)i * K) + k];
+        }
+#pragma unroll
+        for (int u = 0; u < kUpIU; ++u)
+#pragma unroll
+          for (int jj = 0; jj < JT; ++jj) {
+            const C v = Vs[(ii + u) * JT + jj];
+            acc[jj].x += v.x * a[u].x - v.y * a[u].y;
+            acc[jj].y += v.x * a[u].y + v.y * a[u].x;
+          }
+      }
+      for (; ii < ic; ++ii) {
+        const int i = i0 + ii;
+        const C a = A[(aoff ? aoff[i] : (int64_t)i * K) + k];
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj) {
+          const C v = Vs[ii * JT + jj];
           acc[jj].x += v.x * a.x - v.y * a.y;
           acc[jj].y += v.x * a.y + v.y * a.x;
         }
@@ -273,7 +293,7 @@ __global__ void __launch_bounds__(256) k_gemm_up(const typename CT<T>::c *__rest
   }
   if (k >= K) return;
 #pragma unroll
-  for (int jj = 0; jj < kUpJT; ++jj) {
+  for (int jj = 0; jj < JT; ++jj) {
     if (j0 + jj < n) {
       C *o = out + (size_t)(j0 + jj) * ldo + k;
       C r = acc[jj];
@@ -291,9 +311,17 @@ template <typename T>
 void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int ldv, int n,
              int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st) {
   if (n <= 0 || K <= 0) return;
-  dim3 grid((unsigned)((K + 255) / 256), (n + kUpJT - 1) / kUpJT);
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32"), k_gemm_up<T>, grid, dim3(256), 0, st, A, aoff, m, V, ldv, n, K, out, ldo,
-                     (T)beta);
+  const char *name = sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32";
+  const unsigned gx = (unsigned)((K + 255) / 256);
+#define DKS_UP(JT_)                                                                            \
+  DKS_LAUNCH(name, (k_gemm_up<T, JT_>), dim3(gx, (n + JT_ - 1) / JT_), dim3(256), 0, st, A,    \
+             aoff, m, V, ldv, n, K, out, ldo, (T)beta)
+  if (n <= 8) DKS_UP(8);
+  else if (n <= 16) DKS_UP(16);
+  else if (n <= 24) DKS_UP(24);
+  else if (n <= 32) DKS_UP(32);
+  else DKS_UP(40);
+#undef DKS_UP
   DKS_HIP(hipGetLastError());
 }
 template void gemm_up<double>(const double2 *, const int64_t *, int, const double2 *, int, int,
