@@ -49,8 +49,10 @@ typedef enum {
   DKS_MODE_FP64 = 0,          /* every step in FP64 */
   DKS_MODE_MIXED_FP32 = 1,    /* FP32 operator, filter, Gram and updates; FP64 Rayleigh-Ritz;
                                  then FP64 polish iterations to the requested tolerance */
-  DKS_MODE_MIXED_BF16GRAM = 2 /* as MIXED_FP32 but the Gram products take BF16 inputs with
-                                 FP32 accumulation on the matrix cores */
+  DKS_MODE_MIXED_BF16GRAM = 2 /* as MIXED_FP32 but, while the median residual of the FP32
+                                 stage exceeds 10 * mixed_tol, the Gram products take BF16
+                                 inputs (rounded to nearest even) with FP32 accumulation on
+                                 the matrix cores */
 } dks_mode;
 
 /* One (atom, l) block of separable projectors of Eq. (HGH): couplings of the

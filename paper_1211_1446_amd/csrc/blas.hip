@@ -223,6 +223,188 @@ void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, con
   DKS_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Gram products on the BF16 matrix cores with FP32 accumulation
+// (v_mfma_f32_16x16x16_bf16).  Each FP32 input is split into two BF16 numbers,
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to nearest even),
+// and a b is taken as hi_a hi_b + hi_a lo_b + lo_a hi_b: about 16 significant
+// bits per factor instead of 8, at three BF16 products per real product.
+// Same tiling, splitting and reduction as k_gemm_ip.
+// ---------------------------------------------------------------------------
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short f32_to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (inputs are finite)
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(short h) {
+  return __uint_as_float((unsigned)(unsigned short)h << 16);
+}
+
+// hi / lo BF16 fragments of one real component
+struct Split4 {
+  s4 hi, lo;
+};
+__device__ __forceinline__ void split_bf16(float v, short &hi, short &lo) {
+  hi = f32_to_bf16(v);
+  lo = f32_to_bf16(v - bf16_to_f32(hi));
+}
+__device__ __forceinline__ f4 mfma_split(const Split4 &a, const Split4 &b, f4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, c, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) k_gemm_ip_bf16(const float2 *__restrict__ A,
+                                                      const int64_t *__restrict__ aoff, int M,
+                                                      const float2 *__restrict__ B,
+                                                      const int64_t *__restrict__ boff, int Nn,
+                                                      const float2 *__restrict__ B2, int64_t K,
+                                                      int64_t kchunk, int tm, int upper,
+                                                      double2 *__restrict__ part,
+                                                      double2 *__restrict__ part2) {
+  using C = float2;
+  constexpr int LD = kIpKT + 1;
+  __shared__ C As[kIpTile * LD];
+  __shared__ C Bs[kIpTile * LD];
+  __shared__ C B2s[kIpTile * LD];
+  const bool two = (B2 != nullptr);
+  int ti, tj;
+  ip_tile(blockIdx.x, tm, upper != 0, ti, tj);
+  const int tm0 = ti * kIpTile, tn0 = tj * kIpTile;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lrow = tid >> 2, lk = (tid & 3) * 4;
+  const C *arow = nullptr, *brow = nullptr, *b2row = nullptr;
+  if (tm0 + lrow < M) arow = A + (aoff ? aoff[tm0 + lrow] : (int64_t)(tm0 + lrow) * K);
+  if (tn0 + lrow < Nn) {
+    int64_t o = boff ? boff[tn0 + lrow] : (int64_t)(tn0 + lrow) * K;
+    brow = B + o;
+    if (two) b2row = B2 + o;
+  }
+  f4 re[2][2], im[2][2], re2[2][2], im2[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = f4{0, 0, 0, 0};
+      im[i][j] = f4{0, 0, 0, 0};
+      re2[i][j] = f4{0, 0, 0, 0};
+      im2[i][j] = f4{0, 0, 0, 0};
+    }
+  C ra[4], rb[4], rb2[4];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + lk + u;
+      const bool ok = k < ke;
+      ra[u] = (arow && ok) ? arow[k] : C{0, 0};
+      rb[u] = (brow && ok) ? brow[k] : C{0, 0};
+      if (two) rb2[u] = (b2row && ok) ? b2row[k] : C{0, 0};
+    }
+  };
+  // lane l's four k values of one 16 x 16 x 16 product: 4 (l / 16) + 0..3
+  auto frag = [&](const C *T_, int row, Split4 &fr, Split4 &fi) {
+    const int kq = 4 * (lane >> 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const C v = T_[row * LD + kq + q];
+      short h, l;
+      split_bf16(v.x, h, l);
+      fr.hi[q] = h;
+      fr.lo[q] = l;
+      split_bf16(v.y, h, l);
+      fi.hi[q] = h;
+      fi.lo[q] = l;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kIpKT) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[lrow * LD + lk + u] = ra[u];
+      Bs[lrow * LD + lk + u] = rb[u];
+      if (two) B2s[lrow * LD + lk + u] = rb2[u];
+    }
+    __syncthreads();
+    if (k0 + kIpKT < ke) fetch(k0 + kIpKT);
+    Split4 ar[2], ai[2], ain[2], br[2], bi[2], cr[2], ci[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      frag(As, wm + i * 16 + (lane & 15), ar[i], ai[i]);
+      ain[i].hi = ai[i].hi ^ (short)0x8000;   // -a_i: flip the BF16 sign bits
+      ain[i].lo = ai[i].lo ^ (short)0x8000;
+      frag(Bs, wn + i * 16 + (lane & 15), br[i], bi[i]);
+      if (two) frag(B2s, wn + i * 16 + (lane & 15), cr[i], ci[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // conj(a) b: re += ar br + ai bi, im += ar bi - ai br
+        re[i][j] = mfma_split(ar[i], br[j], re[i][j]);
+        im[i][j] = mfma_split(ar[i], bi[j], im[i][j]);
+        re[i][j] = mfma_split(ai[i], bi[j], re[i][j]);
+        im[i][j] = mfma_split(ain[i], br[j], im[i][j]);
+        if (two) {
+          re2[i][j] = mfma_split(ar[i], cr[j], re2[i][j]);
+          im2[i][j] = mfma_split(ar[i], ci[j], im2[i][j]);
+          re2[i][j] = mfma_split(ai[i], ci[j], re2[i][j]);
+          im2[i][j] = mfma_split(ain[i], cr[j], im2[i][j]);
+        }
+      }
+    __syncthreads();
+  }
+  double2 *p1 = part + (size_t)blockIdx.z * M * Nn;
+  double2 *p2 = two ? part2 + (size_t)blockIdx.z * M * Nn : nullptr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // lane l, slot v holds D[4 (l / 16) + v][l % 16]
+        const int r = tm0 + wm + i * 16 + 4 * (lane >> 4) + v;
+        const int c = tn0 + wn + j * 16 + (lane & 15);
+        if (r < M && c < Nn) {
+          p1[(size_t)r * Nn + c] = make_double2((double)re[i][j][v], (double)im[i][j][v]);
+          if (two) p2[(size_t)r * Nn + c] = make_double2((double)re2[i][j][v], (double)im2[i][j][v]);
+        }
+      }
+}
+
+void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, const int64_t *boff,
+                  int Nn, const float2 *B2, int64_t K, double2 *out, double2 *out2, int ldo,
+                  DevBuf &part, hipStream_t st, bool hermitian) {
+  if (M <= 0 || Nn <= 0) return;
+  const int tm = (M + kIpTile - 1) / kIpTile, tn = (Nn + kIpTile - 1) / kIpTile;
+  const bool upper = hermitian && M == Nn;
+  const int tiles = upper ? tm * (tm + 1) / 2 : tm * tn;
+  int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
+  int64_t nsplit = (1024 + tiles - 1) / tiles;
+  nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
+  int64_t kchunk = (K + nsplit - 1) / nsplit;
+  kchunk = (kchunk + kIpKT - 1) / kIpKT * kIpKT;
+  nsplit = (K + kchunk - 1) / kchunk;
+  if (nsplit < 1) nsplit = 1;
+  const int nmat = B2 ? 2 : 1;
+  part.ensure(sizeof(double2) * (size_t)nsplit * M * Nn * nmat);
+  double2 *p1 = part.as<double2>();
+  double2 *p2 = B2 ? p1 + (size_t)nsplit * M * Nn : nullptr;
+  dim3 grid(tiles, 1, (unsigned)nsplit);
+  DKS_LAUNCH("k_gemm_ip.gram.bf16", k_gemm_ip_bf16, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn,
+             B2, K, kchunk, tm, (int)upper, p1, p2);
+  DKS_HIP(hipGetLastError());
+  int nel = M * Nn * nmat;
+  DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p1, p2,
+             (int)nsplit, M, Nn, (int)upper, out, out2, ldo);
+  DKS_HIP(hipGetLastError());
+}
+
 template void gemm_ip<double>(const double2 *, const int64_t *, int, const double2 *,
                               const int64_t *, int, const double2 *, int64_t, double2 *,
                               double2 *, int, DevBuf &, hipStream_t, bool);

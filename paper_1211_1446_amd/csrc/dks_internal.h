@@ -184,6 +184,10 @@ template <typename T>
 void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
              int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
              DevBuf &part, hipStream_t st, bool hermitian = false);
+// The same product with the FP32 inputs rounded to BF16 and FP32 accumulation.
+void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, const int64_t *boff,
+                  int Nn, const float2 *B2, int64_t K, double2 *out, double2 *out2, int ldo,
+                  DevBuf &part, hipStream_t st, bool hermitian = false);
 
 // out_j[k] = alpha * sum_i V[i][j] A_i[k] (+ beta out_j[k]); V FP64 m x n (ld ldv).
 template <typename T>

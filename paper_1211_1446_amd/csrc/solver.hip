@@ -17,6 +17,8 @@
 #include <cstring>
 #include <limits>
 
+#include <type_traits>
+
 #include "dks_internal.h"
 
 namespace dks {
@@ -73,6 +75,7 @@ struct Ctx {
   int N;
   int iter_slot = 0, iter_cap = 0;   // entries written to / capacity of opts.iter_ms
   double floor = -1e300;              // Ritz values below are discarded (mid-gap -c^2 with F)
+  bool bf16_gram = false;             // reduced-precision stage: Gram products from BF16 inputs
 };
 
 // Row offsets of Z = [rows 0..n) U [n, n+m) U [2n, 2n+mp) of a 3n-row block.
@@ -100,6 +103,12 @@ static double residual_level(std::vector<double> r) {
 constexpr int kStallFp64 = 10;     // iterations without a new best residual before stopping
 constexpr int kStallFp32 = 4;
 constexpr int kPolishFilters = 2;  // filter applications on the block entering the FP64 polish
+// MIXED_BF16GRAM: BF16-input Gram products while the median residual exceeds
+// this multiple of mixed_tol (their rounding, ~2^-9 per element and averaged
+// over K terms, stops mattering only once the residuals are that small), FP32
+// Gram products after.
+constexpr double kBf16GramExit = 10.0;
+constexpr double kBf16DropTol = 1e-3;
 
 template <typename T> struct LoopState {
   int cur = 0;
@@ -126,17 +135,34 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
     DKS_HIP(hipGetLastError());
     sv.gS.ensure(sizeof(double2) * nz * nz);
     sv.gA.ensure(sizeof(double2) * nz * nz);
-    gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
-               bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
-               bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(), sv.gA.as<double2>(),
-               nz, sv.part, x.st, /*hermitian=*/true);
+    if constexpr (std::is_same<T, float>::value) {
+      if (x.bf16_gram) {
+        gemm_ip_bf16(bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz,
+                     bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz,
+                     bk.HZ[s.cur].template as<float2>(), bk.K, sv.gS.as<double2>(),
+                     sv.gA.as<double2>(), nz, sv.part, x.st, /*hermitian=*/true);
+      } else {
+        gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+                   bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+                   bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(),
+                   sv.gA.as<double2>(), nz, sv.part, x.st, /*hermitian=*/true);
+      }
+    } else {
+      gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+                 bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+                 bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(),
+                 sv.gA.as<double2>(), nz, sv.part, x.st, /*hermitian=*/true);
+    }
     sv.Vz.ensure(sizeof(double2) * nz * n);
     sv.theta.ensure(sizeof(double) * n);
     sv.rinfo.ensure(sizeof(int) * 4);
     sv.rdinfo.ensure(sizeof(double) * 2);
     const bool stamps = log_enabled();
     if (stamps) sv.tst.ensure(sizeof(long long) * 16);
-    rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, drop_tol, x.floor, nullptr,
+    // BF16-split Gram products carry relative errors of a few 1e-6: directions
+    // whose scaled overlap pivot is not well above that are dropped
+    const double dtol = (sizeof(T) == 4 && x.bf16_gram) ? std::max(drop_tol, kBf16DropTol) : drop_tol;
+    rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, dtol, x.floor, nullptr,
                   sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
                   sv.rdinfo.as<double>(), sv.rrs, x.st, stamps ? sv.tst.as<long long>() : nullptr);
     if (stamps) {
@@ -282,6 +308,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     // noise.  The level is the median residual (the worst one is gap-limited and
     // not monotone in the first iterations).
     double level = residual_level(s.res);
+    if (x.bf16_gram && !(level > kBf16GramExit * x.o->mixed_tol)) x.bf16_gram = false;
     if (level < 0.9 * best) {
       best = level;
       stall = 0;
@@ -415,9 +442,11 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
       LoopState<float> s32;
       convert<double, float>(Xu, x.sv->b32.z(0, 0), x.K * n, st);
       const bool fixed = !(o.mixed_tol > 0);   // mixed_tol <= 0: exactly mixed_iter iterations
+      x.bf16_gram = (o.mode == DKS_MODE_MIXED_BF16GRAM);
       run_stage<float>(x, x.sv->b32, s32, n, o.n_init, fixed ? 0.0 : o.mixed_tol, o.mixed_iter, 1e-5,
                        fixed ? 0 : kStallFp32);
       inf.iters_reduced = s32.iters;
+      x.bf16_gram = false;
       // FP64 polish.  The reduced-precision block carries rounding noise of
       // relative size up to ~1e-7 in every direction, including the negative
       // band, where the residual amplifies it by ~2c^2 (the gamma_LOBPCG ~ Delta/w

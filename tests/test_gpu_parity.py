@@ -179,7 +179,7 @@ def _solve_tiny(dev, mode, seed=0, n=8, **kw):
     return lam, res, info, rc, lam_ref, vec_ref, Xo, s
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_lobpcgf_tiny_dimer_matches_dense(dev, mode):
     lam, res, info, rc, lam_ref, vec_ref, Xo, s = _solve_tiny(dev, mode)
     assert rc == 0, info
@@ -188,8 +188,22 @@ def test_lobpcgf_tiny_dimer_matches_dense(dev, mode):
     assert info["min_ritz"] > -s.c ** 2
     assert np.allclose(np.linalg.norm(Xo, axis=0), 1.0, atol=1e-10)
     assert cluster_projectors_match(lam_ref, vec_ref, Xo) < 1e-6
-    if mode == 1:
+    if mode >= 1:
         assert info["iters_reduced"] > 0
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_reduced_precision_stage_alone(dev, mode):
+    """The FP32 (mode 1) or BF16-Gram (mode 2) stage by itself, 40 iterations,
+    followed only by the FP64 polish's first Rayleigh-Ritz (n_iter = 0): its
+    eigenvalues already sit near the dense ones, far below the start block's
+    error, so the reduced-precision Gram products carry the right numbers."""
+    lam, res, info, rc, lam_ref, vec_ref, Xo, s = _solve_tiny(
+        dev, mode, n_iter=0, mixed_iter=40, mixed_tol=-1.0)
+    err = np.max(np.abs(lam - lam_ref))
+    print(f"mode {mode}: reduced stage max |lambda - dense| = {err:.3e}", flush=True)
+    assert info["iters_reduced"] == 40
+    assert err < 1e-3, err
 
 
 def test_lobpcgf_ragged_block_and_kpoint(dev):
