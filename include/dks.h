@@ -178,6 +178,24 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
                              double *resnorms, const dks_solve_opts *opts,
                              dks_solve_info *info, void *stream);
 
+/* Algorithm 1 on several systems of one basis at once: the k-points of a
+ * description, or independent systems of uneven size and band count (each k
+ * and each system is a separate eigenproblem, Sec. 2).  Item i solves system
+ * sys[i] for n[i] bands with block X[i] ([n[i]][4][N] complex128, device; in:
+ * start block, out: eigenvectors), eigenvalues into the host array lambda[i]
+ * (n[i] doubles) and, when resnorms is not NULL, residual norms into
+ * resnorms[i]; info, when not NULL, is an array of nsys records.  The same
+ * options apply to every item; opts->iter_ms is ignored.  Items run on up to 4
+ * library-owned streams (one host thread each, items i, i + 4, ... on lane
+ * i mod 4), each lane with its own workspace, kept with the basis for reuse;
+ * they start after the work queued on `stream` and `stream` waits for all of
+ * them.  Returns the most severe item status (errors before DKS_WNOTCONV), with
+ * dks_last_error naming the item; every item is attempted. */
+dks_status dks_lobpcgf_solve_batch(dks_basis *b, int nsys, const int *sys, const int *n,
+                                   void *const *X, double *const *lambda,
+                                   double *const *resnorms, const dks_solve_opts *opts,
+                                   dks_solve_info *info, void *stream);
+
 /* Kernel timing (a diagnostic for roofline accounting).  When enabled, every
  * kernel the library launches on the calling thread is bracketed by a pair of
  * HIP events on its stream.  dks_profile_report synchronises the device, writes

@@ -79,6 +79,9 @@ def _load():
     lib.dks_default_opts.restype = None
     lib.dks_lobpcgf_solve.argtypes = [vp, i, i, vp, ct.POINTER(d), ct.POINTER(d),
                                       ct.POINTER(SolveOpts), ct.POINTER(SolveInfo), vp]
+    lib.dks_lobpcgf_solve_batch.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(vp),
+                                            ct.POINTER(ct.POINTER(d)), ct.POINTER(ct.POINTER(d)),
+                                            ct.POINTER(SolveOpts), ct.POINTER(SolveInfo), vp]
     lib.dks_free_basis.argtypes = [vp]
     lib.dks_free_basis.restype = None
     lib.dks_last_error.restype = ct.c_char_p
@@ -284,3 +287,35 @@ def lobpcgf_solve(b: Basis, sys: int, n: int, X, opts: Optional[SolveOpts] = Non
                                 ct.byref(o), ct.byref(info), _stream(stream))
     _check(rc, allow_warning=allow_notconv)
     return lam, res, info.as_dict(), rc
+
+
+def lobpcgf_solve_batch(b: Basis, systems: Sequence[int], ns: Sequence[int], Xs: Sequence,
+                        opts: Optional[SolveOpts] = None, stream=None, allow_notconv: bool = True):
+    """Algorithm 1 on several systems of one basis (dks_lobpcgf_solve_batch).
+
+    ``Xs[i]``: complex128 device block [ns[i]][4][N_i] (in: start block, out:
+    eigenvectors).  Returns (list of eigenvalue arrays, list of residual arrays,
+    list of info dicts, status)."""
+    import torch
+    nsys = len(systems)
+    if not (len(ns) == nsys and len(Xs) == nsys):
+        raise ValueError("systems, ns and Xs must have the same length")
+    for s_, n_, X in zip(systems, ns, Xs):
+        if X.dtype != torch.complex128:
+            raise TypeError("every block must be complex128")
+        N, _, _ = basis_info(b, int(s_), miller=False)
+        _check_block(X, int(n_), N)
+    lams = [np.zeros(int(n_)) for n_ in ns]
+    ress = [np.zeros(int(n_)) for n_ in ns]
+    infos = (SolveInfo * max(nsys, 1))()
+    sys_a = (ct.c_int * max(nsys, 1))(*[int(v) for v in systems])
+    n_a = (ct.c_int * max(nsys, 1))(*[int(v) for v in ns])
+    x_a = (ct.c_void_p * max(nsys, 1))(*[X.data_ptr() for X in Xs])
+    dp = ct.POINTER(ct.c_double)
+    l_a = (dp * max(nsys, 1))(*[a.ctypes.data_as(dp) for a in lams])
+    r_a = (dp * max(nsys, 1))(*[a.ctypes.data_as(dp) for a in ress])
+    o = opts if opts is not None else default_opts()
+    rc = _lib.dks_lobpcgf_solve_batch(b.handle, nsys, sys_a, n_a, x_a, l_a, r_a, ct.byref(o),
+                                      infos, _stream(stream))
+    _check(rc, allow_warning=allow_notconv)
+    return lams, ress, [infos[i].as_dict() for i in range(nsys)], rc

@@ -155,12 +155,21 @@ struct Potential {
 
 }  // namespace dks
 
+namespace dks {
+// Device scratch of one H.X pipeline: column-pruned FFT intermediate, projector
+// coefficients and GEMM partial sums.  Concurrent applies need separate ones.
+struct Workspace {
+  DevBuf t1, nlc, nlc2, part;
+};
+}  // namespace dks
+
 struct dks_basis {
   int device = 0;
   std::vector<dks::System *> sys;
   std::vector<dks::Potential *> pot;
-  // apply_H / apply_filter scratch
-  dks::DevBuf t1, nlc, nlc2, part, ftmp64, ftmp32;
+  // apply_H / apply_filter scratch of the unbatched entry points
+  dks::Workspace ws;
+  dks::DevBuf ftmp64, ftmp32;
   // solver workspace (created on first solve)
   void *solver = nullptr;
   ~dks_basis();
@@ -174,7 +183,7 @@ namespace dks {
 // HX = scale * ((H - shift) X) for nb bands, precision T.
 template <typename T>
 void apply_h(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
-             double scale, hipStream_t st);
+             double scale, hipStream_t st, Workspace &ws);
 
 // out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
 // rows addressed by element offsets.  M, Nn <= 512.  `hermitian` (A and B the same

@@ -314,7 +314,7 @@ void init_kernel_attributes() {
 
 template <typename T>
 void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
-             double scale, hipStream_t st) {
+             double scale, hipStream_t st, Workspace &ws) {
   using C = cplx<T>;
   System &s = *b->sys[sysi];
   Potential &pot = *b->pot[s.vsrc];
@@ -325,17 +325,17 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   double2 *Cp = nullptr;
   if (s.nproj > 0) {
     size_t cbytes = sizeof(double2) * (size_t)s.nproj * ncols;
-    b->nlc.ensure(cbytes);
-    b->nlc2.ensure(cbytes);
+    ws.nlc.ensure(cbytes);
+    ws.nlc2.ensure(cbytes);
     std::vector<int64_t> dummy;
     // row offsets: B rows p*N, X rows cc*N (contiguous), passed as null -> stride N
     gemm_ip<T>(Btab<T>(s), nullptr, s.nproj, X, nullptr, ncols, nullptr, (int64_t)N,
-               b->nlc.as<double2>(), nullptr, ncols, b->part, st);
+               ws.nlc.as<double2>(), nullptr, ncols, ws.part, st);
     dim3 gw(nb * 2, (unsigned)s.groups.size());
-    DKS_LAUNCH("k_apply_w", k_apply_w, gw, dim3(64), 0, st, b->nlc.as<double2>(), b->nlc2.as<double2>(),
+    DKS_LAUNCH("k_apply_w", k_apply_w, gw, dim3(64), 0, st, ws.nlc.as<double2>(), ws.nlc2.as<double2>(),
                        ncols, nb, s.d_Winfo.as<int4>(), (int)s.groups.size(), s.d_W64.as<double2>());
     DKS_HIP(hipGetLastError());
-    Cp = b->nlc2.as<double2>();
+    Cp = ws.nlc2.as<double2>();
   }
   {
     dim3 grid((N + 255) / 256, (nb + kBT - 1) / kBT);
@@ -346,8 +346,8 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   }
   // --- local potential through the grid
   const int n3 = s.grid[2];
-  b->t1.ensure(sizeof(C) * (size_t)ncols * n3 * s.ncol);
-  C *t1 = b->t1.as<C>();
+  ws.t1.ensure(sizeof(C) * (size_t)ncols * n3 * s.ncol);
+  C *t1 = ws.t1.as<C>();
   const int tile = s.tile_z;
   dim3 gz((s.ncol + tile - 1) / tile, ncols);
   size_t smz = sizeof(C) * (size_t)tile * (n3 + 1);
@@ -367,8 +367,8 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
 }
 
 template void apply_h<double>(dks_basis *, int, const double2 *, double2 *, int, double, double,
-                              hipStream_t);
+                              hipStream_t, Workspace &);
 template void apply_h<float>(dks_basis *, int, const float2 *, float2 *, int, double, double,
-                             hipStream_t);
+                             hipStream_t, Workspace &);
 
 }  // namespace dks

@@ -23,6 +23,7 @@
 // triangles in LDS when n_Z <= 120, else full rows in the global scratch area.
 #include <algorithm>
 #include <cfloat>
+#include <mutex>
 
 #include "dks_internal.h"
 
@@ -914,13 +915,15 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
                       sizeof(unsigned short) * (size_t)kRRThreads * kSturmPts <=
                   sizeof(double2) * kRRThreads,
               DKS_EINVAL, "Rayleigh-Ritz: too many wanted pairs");
-  static bool attr = false;
-  if (!attr) {
+  // once per process, also when batch lanes arrive here together
+  static std::once_flag attr;
+  hipError_t attr_rc = hipSuccess;
+  std::call_once(attr, [&] {
     const size_t mx = std::max(rr_lds_bytes(kRRPackedMax), rr_lds_bytes(kRRMax));
-    DKS_HIP(hipFuncSetAttribute((const void *)k_rayleigh_ritz,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)mx));
-    attr = true;
-  }
+    attr_rc = hipFuncSetAttribute((const void *)k_rayleigh_ritz,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)mx);
+  });
+  DKS_HIP(attr_rc);
   const size_t lds = rr_lds_bytes(nz);
   const size_t nn = (size_t)nz * nz;
   const size_t bytes = sizeof(double2) * (5 * nn + (size_t)nz * nkeep) +

@@ -18,6 +18,9 @@
 #include <limits>
 
 #include <type_traits>
+#include <vector>
+#include <thread>
+#include <string>
 
 #include "dks_internal.h"
 
@@ -46,11 +49,37 @@ struct Solver {
   Blocks<double> b64;
   Blocks<float> b32;
   DevBuf gS, gA, Vz, Vp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2, tst;
+  Workspace ws;   // H.X scratch of this solver's applies
 };
 
-static Solver *solver_of(dks_basis *b) {
-  if (!b->solver) b->solver = new Solver();
-  return static_cast<Solver *>(b->solver);
+// Lanes of dks_lobpcgf_solve_batch: a solver workspace and a stream each,
+// kept with the basis so that repeated batches reuse their allocations.
+constexpr int kBatchLanes = 4;   // hardware queues a process gets by default
+struct Lane {
+  Solver sv;
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+};
+struct BatchLanes {
+  Lane lane[kBatchLanes];
+  ~BatchLanes() {
+    for (auto &l : lane) {
+      if (l.done) (void)hipEventDestroy(l.done);
+      if (l.st) (void)hipStreamDestroy(l.st);
+    }
+  }
+};
+
+// The basis keeps one Solver for the unbatched entry point and, once a batch
+// has run, its lanes.
+struct SolverSet {
+  Solver main;
+  BatchLanes *lanes = nullptr;
+  ~SolverSet() { delete lanes; }
+};
+static SolverSet *solvers_of(dks_basis *b) {
+  if (!b->solver) b->solver = new SolverSet();
+  return static_cast<SolverSet *>(b->solver);
 }
 
 // DKS_LOG=1 in the environment prints one JSON line per Rayleigh-Ritz step to stderr.
@@ -90,8 +119,8 @@ __global__ void k_offsets(int64_t *off, int n, int m, int mp, int64_t K) {
 template <typename T>
 static void filter_inplace(Ctx &x, cplx<T> *Y, cplx<T> *W, int m) {
   // W = (H - C) Y ; Y = (H - C) W / Omega^2   (Eq. filter)
-  apply_h<T>(x.b, x.sys, Y, W, m, x.C, 1.0, x.st);
-  apply_h<T>(x.b, x.sys, W, Y, m, x.C, 1.0 / (x.Om * x.Om), x.st);
+  apply_h<T>(x.b, x.sys, Y, W, m, x.C, 1.0, x.st, x.sv->ws);
+  apply_h<T>(x.b, x.sys, W, Y, m, x.C, 1.0 / (x.Om * x.Om), x.st, x.sv->ws);
   if (x.info) x.info->h_applies += 2 * m;
 }
 
@@ -100,7 +129,16 @@ static double residual_level(std::vector<double> r) {
   return r[r.size() / 2];
 }
 
-constexpr int kStallFp64 = 10;     // iterations without a new best residual before stopping
+// Median residual of the columns not yet below tol (0 when all are), and their count.
+static double active_level(const std::vector<double> &r, double tol, int &nact) {
+  std::vector<double> a;
+  for (double v : r)
+    if (!(v < tol)) a.push_back(v);
+  nact = (int)a.size();
+  return a.empty() ? 0.0 : residual_level(a);
+}
+
+constexpr int kStallFp64 = 20;     // iterations without a new best residual before stopping
 constexpr int kStallFp32 = 4;
 constexpr int kPolishFilters = 2;  // filter applications on the block entering the FP64 polish
 // MIXED_BF16GRAM: BF16-input Gram products while the median residual exceeds
@@ -273,13 +311,14 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   if (filt)
     for (int k = 0; k < n_init; ++k) filter_inplace<T>(x, bk.z(0, 0), bk.W.template as<cplx<T>>(), n);
   // Rayleigh-Ritz on the start block, first residual
-  apply_h<T>(x.b, x.sys, bk.z(0, 0), bk.hz(0, 0), n, 0.0, 1.0, x.st);
+  apply_h<T>(x.b, x.sys, bk.z(0, 0), bk.hz(0, 0), n, 0.0, 1.0, x.st, x.sv->ws);
   if (x.info) x.info->h_applies += n;
   std::vector<double2> hV;
   if (!ritz<T>(x, bk, s, n, drop_tol, hV))
     throw Error{DKS_ECHOL, "the start block is numerically rank deficient"};
   update<T>(x, bk, s, n, hV, tol);
-  double best = residual_level(s.res);
+  int best_nact = 0;
+  double best = active_level(s.res, tol, best_nact);
   int stall = 0;
   // main loop
   while (!s.converged && s.iters < max_iter) {
@@ -293,7 +332,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
     // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
-    apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st);
+    apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st, x.sv->ws);
     if (x.info) x.info->h_applies += m;
     // Rayleigh-Ritz on Z = [X, Y, P]
     if (!ritz<T>(x, bk, s, n, drop_tol, hV))
@@ -303,13 +342,20 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     if (x.o->iter_ms && x.iter_slot < x.iter_cap)
       x.o->iter_ms[x.iter_slot++] =
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    // stagnation: no new best residual level for `stall_window` iterations means
-    // the iteration sits on its rounding floor; stop instead of iterating on
-    // noise.  The level is the median residual (the worst one is gap-limited and
-    // not monotone in the first iterations).
-    double level = residual_level(s.res);
-    if (x.bf16_gram && !(level > kBf16GramExit * x.o->mixed_tol)) x.bf16_gram = false;
-    if (level < 0.9 * best) {
+    if (x.bf16_gram && !(residual_level(s.res) > kBf16GramExit * x.o->mixed_tol))
+      x.bf16_gram = false;
+    // stagnation: neither a column newly below tol nor a new low of the median
+    // residual of the remaining columns for `stall_window` iterations means the
+    // iteration sits on its rounding floor; stop instead of iterating on noise.
+    // (The worst residual is gap-limited and not monotone in the first
+    // iterations; columns already converged no longer move the level.)
+    int nact = 0;
+    const double level = active_level(s.res, tol, nact);
+    if (nact < best_nact) {
+      best_nact = nact;
+      best = level;
+      stall = 0;
+    } else if (level < 0.95 * best) {
       best = level;
       stall = 0;
     } else if (stall_window > 0 && ++stall >= stall_window) {
@@ -319,101 +365,24 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   return s.converged ? DKS_OK : DKS_WNOTCONV;
 }
 
-}  // namespace dks
-
-using namespace dks;
-
-extern "C" {
-
-void dks_free_solver(dks_basis *b) {
-  if (b && b->solver) {
-    delete static_cast<Solver *>(b->solver);
-    b->solver = nullptr;
-  }
-}
-
-void dks_default_opts(dks_solve_opts *o) {
-  if (!o) return;
-  o->C = std::numeric_limits<double>::quiet_NaN();
-  o->Omega = std::numeric_limits<double>::quiet_NaN();
-  o->n_init = 3;
-  o->n_iter = 200;
-  o->tol = 1e-8;
-  o->mode = DKS_MODE_FP64;
-  o->mixed_tol = 1e-4;
-  o->mixed_iter = 200;
-  o->kinetic_balance = 0;
-  o->use_filter = 1;
-}
-
-dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb, dks_prec prec,
-                       void *stream) {
-  try {
-    DKS_REQUIRE(b && X && HX && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
-                "bad argument");
-    DKS_REQUIRE(X != HX, DKS_EINVAL, "X and HX must not overlap");
-    DKS_HIP(hipSetDevice(b->device));
-    hipStream_t st = (hipStream_t)stream;
-    if (prec == DKS_FP64)
-      apply_h<double>(b, sys, (const double2 *)X, (double2 *)HX, nb, 0.0, 1.0, st);
-    else
-      apply_h<float>(b, sys, (const float2 *)X, (float2 *)HX, nb, 0.0, 1.0, st);
-    return DKS_OK;
-  } catch (const Error &e) {
-    set_error(e.msg);
-    return e.code;
-  }
-}
-
-dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int nb, double C,
-                            double Omega, dks_prec prec, void *stream) {
-  try {
-    DKS_REQUIRE(b && Y && FY && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
-                "bad argument");
-    DKS_REQUIRE(Y != FY, DKS_EINVAL, "Y and FY must not overlap");
-    DKS_REQUIRE(std::isfinite(C) && std::isfinite(Omega) && Omega != 0.0, DKS_EINVAL,
-                "C and Omega must be finite, Omega nonzero");
-    DKS_HIP(hipSetDevice(b->device));
-    hipStream_t st = (hipStream_t)stream;
-    const System &s = *b->sys[sys];
-    const size_t K = 4 * (size_t)s.N;
-    if (prec == DKS_FP64) {
-      b->ftmp64.ensure(sizeof(double2) * K * nb);
-      apply_h<double>(b, sys, (const double2 *)Y, b->ftmp64.as<double2>(), nb, C, 1.0, st);
-      apply_h<double>(b, sys, b->ftmp64.as<double2>(), (double2 *)FY, nb, C, 1.0 / (Omega * Omega), st);
-    } else {
-      b->ftmp32.ensure(sizeof(float2) * K * nb);
-      apply_h<float>(b, sys, (const float2 *)Y, b->ftmp32.as<float2>(), nb, C, 1.0, st);
-      apply_h<float>(b, sys, b->ftmp32.as<float2>(), (float2 *)FY, nb, C, 1.0 / (Omega * Omega), st);
-    }
-    return DKS_OK;
-  } catch (const Error &e) {
-    set_error(e.msg);
-    return e.code;
-  }
-}
-
-dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lambda,
-                             double *resnorms, const dks_solve_opts *opts, dks_solve_info *info,
-                             void *stream) {
-  try {
-    DKS_REQUIRE(b && X && lambda && sys >= 0 && sys < (int)b->sys.size(), DKS_EINVAL, "bad argument");
-    dks_solve_opts o;
-    if (opts) o = *opts; else dks_default_opts(&o);
+// One solve of Algorithm 1 on `st` with solver workspace `sv`; returns the
+// status and, for a nonzero one, its message.  Throws dks::Error on failures.
+static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *lambda,
+                            double *resnorms, const dks_solve_opts &o, dks_solve_info *info,
+                            hipStream_t st, Solver *sv, std::string &msg) {
+  {
     const System &s = *b->sys[sys];
     DKS_REQUIRE(n >= 1 && n <= 170 && n <= 4 * s.N, DKS_EINVAL,
                 "n must be in [1, min(170, 4N)] (subspace dimension 3n <= 512)");
     DKS_REQUIRE(o.n_init >= 0 && o.n_iter >= 0 && o.tol > 0, DKS_EINVAL, "bad options");
     DKS_REQUIRE(o.mode >= 0 && o.mode <= 2, DKS_EINVAL, "bad mode");
-    DKS_HIP(hipSetDevice(b->device));
-    hipStream_t st = (hipStream_t)stream;
     dks_solve_info inf{};
     inf.min_ritz = std::numeric_limits<double>::infinity();
     Ctx x;
     x.b = b;
     x.sys = sys;
     x.st = st;
-    x.sv = solver_of(b);
+    x.sv = sv;
     x.o = &o;
     x.info = &inf;
     x.N = s.N;
@@ -428,7 +397,6 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
     inf.Omega = x.Om;
     x.iter_cap = o.n_iter + (o.mode != DKS_MODE_FP64 ? o.mixed_iter : 0);
     x.floor = o.use_filter ? -x.c2 : -std::numeric_limits<double>::infinity();
-    double2 *Xu = (double2 *)X;
     if (o.kinetic_balance) kinetic_balance(b, sys, Xu, n, st);
     dks_status rc = DKS_OK;
     LoopState<double> s64;
@@ -475,11 +443,181 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
     if (info) *info = inf;
     for (int j = 0; j < n; ++j)
       if (lambda[j] < -x.c2) {
-        set_error("a Ritz value fell below -c^2 (variational collapse)");
+        msg = "a Ritz value fell below -c^2 (variational collapse)";
         return DKS_ECOLLAPSE;
       }
-    if (rc != DKS_OK) set_error("iteration limit reached before every residual fell below tol");
+    if (rc != DKS_OK) msg = "iteration limit reached before every residual fell below tol";
     return rc;
+  }
+}
+
+
+}  // namespace dks
+
+using namespace dks;
+
+extern "C" {
+
+void dks_free_solver(dks_basis *b) {
+  if (b && b->solver) {
+    delete static_cast<SolverSet *>(b->solver);
+    b->solver = nullptr;
+  }
+}
+
+void dks_default_opts(dks_solve_opts *o) {
+  if (!o) return;
+  o->C = std::numeric_limits<double>::quiet_NaN();
+  o->Omega = std::numeric_limits<double>::quiet_NaN();
+  o->n_init = 3;
+  o->n_iter = 200;
+  o->tol = 1e-8;
+  o->mode = DKS_MODE_FP64;
+  o->mixed_tol = 1e-4;
+  o->mixed_iter = 200;
+  o->kinetic_balance = 0;
+  o->use_filter = 1;
+}
+
+dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb, dks_prec prec,
+                       void *stream) {
+  try {
+    DKS_REQUIRE(b && X && HX && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
+                "bad argument");
+    DKS_REQUIRE(X != HX, DKS_EINVAL, "X and HX must not overlap");
+    DKS_HIP(hipSetDevice(b->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == DKS_FP64)
+      apply_h<double>(b, sys, (const double2 *)X, (double2 *)HX, nb, 0.0, 1.0, st, b->ws);
+    else
+      apply_h<float>(b, sys, (const float2 *)X, (float2 *)HX, nb, 0.0, 1.0, st, b->ws);
+    return DKS_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int nb, double C,
+                            double Omega, dks_prec prec, void *stream) {
+  try {
+    DKS_REQUIRE(b && Y && FY && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
+                "bad argument");
+    DKS_REQUIRE(Y != FY, DKS_EINVAL, "Y and FY must not overlap");
+    DKS_REQUIRE(std::isfinite(C) && std::isfinite(Omega) && Omega != 0.0, DKS_EINVAL,
+                "C and Omega must be finite, Omega nonzero");
+    DKS_HIP(hipSetDevice(b->device));
+    hipStream_t st = (hipStream_t)stream;
+    const System &s = *b->sys[sys];
+    const size_t K = 4 * (size_t)s.N;
+    if (prec == DKS_FP64) {
+      b->ftmp64.ensure(sizeof(double2) * K * nb);
+      apply_h<double>(b, sys, (const double2 *)Y, b->ftmp64.as<double2>(), nb, C, 1.0, st, b->ws);
+      apply_h<double>(b, sys, b->ftmp64.as<double2>(), (double2 *)FY, nb, C, 1.0 / (Omega * Omega), st,
+                      b->ws);
+    } else {
+      b->ftmp32.ensure(sizeof(float2) * K * nb);
+      apply_h<float>(b, sys, (const float2 *)Y, b->ftmp32.as<float2>(), nb, C, 1.0, st, b->ws);
+      apply_h<float>(b, sys, b->ftmp32.as<float2>(), (float2 *)FY, nb, C, 1.0 / (Omega * Omega), st,
+                     b->ws);
+    }
+    return DKS_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lambda,
+                             double *resnorms, const dks_solve_opts *opts, dks_solve_info *info,
+                             void *stream) {
+  try {
+    DKS_REQUIRE(b && X && lambda && sys >= 0 && sys < (int)b->sys.size(), DKS_EINVAL, "bad argument");
+    dks_solve_opts o;
+    if (opts) o = *opts; else dks_default_opts(&o);
+    DKS_HIP(hipSetDevice(b->device));
+    std::string msg;
+    const dks_status rc = solve_one(b, sys, n, (double2 *)X, lambda, resnorms, o, info,
+                                    (hipStream_t)stream, &solvers_of(b)->main, msg);
+    if (rc != DKS_OK) set_error(msg);
+    return rc;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+dks_status dks_lobpcgf_solve_batch(dks_basis *b, int nsys, const int *sys, const int *n,
+                                   void *const *X, double *const *lambda,
+                                   double *const *resnorms, const dks_solve_opts *opts,
+                                   dks_solve_info *info, void *stream) {
+  try {
+    DKS_REQUIRE(b && nsys >= 0 && (nsys == 0 || (sys && n && X && lambda)), DKS_EINVAL,
+                "bad argument");
+    for (int i = 0; i < nsys; ++i)
+      DKS_REQUIRE(sys[i] >= 0 && sys[i] < (int)b->sys.size() && X[i] && lambda[i], DKS_EINVAL,
+                  "bad system index or null block in the batch");
+    if (nsys == 0) return DKS_OK;
+    dks_solve_opts o;
+    if (opts) o = *opts; else dks_default_opts(&o);
+    o.iter_ms = nullptr;   // per-iteration times are a single-solve feature
+    DKS_HIP(hipSetDevice(b->device));
+    SolverSet *set = solvers_of(b);
+    if (!set->lanes) {
+      auto *bl = new BatchLanes();
+      set->lanes = bl;
+      for (auto &l : bl->lane) {
+        DKS_HIP(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
+        DKS_HIP(hipEventCreateWithFlags(&l.done, hipEventDisableTiming));
+      }
+    }
+    BatchLanes &bl = *set->lanes;
+    const int L = std::min(kBatchLanes, nsys);
+    // lanes start after the work already queued on the caller's stream
+    hipStream_t cst = (hipStream_t)stream;
+    hipEvent_t start;
+    DKS_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    DKS_HIP(hipEventRecord(start, cst));
+    for (int l = 0; l < L; ++l) DKS_HIP(hipStreamWaitEvent(bl.lane[l].st, start, 0));
+    std::vector<dks_status> rc(nsys, DKS_OK);
+    std::vector<std::string> msg(nsys);
+    auto run_lane = [&](int l) {
+      if (hipSetDevice(b->device) != hipSuccess) {
+        for (int i = l; i < nsys; i += L) rc[i] = DKS_EHIP;
+        return;
+      }
+      for (int i = l; i < nsys; i += L) {
+        try {
+          rc[i] = solve_one(b, sys[i], n[i], (double2 *)X[i], lambda[i],
+                            resnorms ? resnorms[i] : nullptr, o, info ? &info[i] : nullptr,
+                            bl.lane[l].st, &bl.lane[l].sv, msg[i]);
+        } catch (const Error &e) {
+          rc[i] = e.code;
+          msg[i] = e.msg;
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    for (int l = 1; l < L; ++l) th.emplace_back(run_lane, l);
+    run_lane(0);
+    for (auto &t : th) t.join();
+    // the caller's stream waits for every lane
+    for (int l = 0; l < L; ++l) {
+      DKS_HIP(hipEventRecord(bl.lane[l].done, bl.lane[l].st));
+      DKS_HIP(hipStreamWaitEvent(cst, bl.lane[l].done, 0));
+    }
+    DKS_HIP(hipEventDestroy(start));
+    // errors first (most negative), then warnings
+    dks_status worst = DKS_OK;
+    for (int i = 0; i < nsys; ++i) {
+      const bool take = (rc[i] < 0 && (worst >= 0 || rc[i] < worst)) || (worst == DKS_OK && rc[i] > 0);
+      if (take) {
+        worst = rc[i];
+        set_error("batch item " + std::to_string(i) + " (system " + std::to_string(sys[i]) +
+                  "): " + msg[i]);
+      }
+    }
+    return worst;
   } catch (const Error &e) {
     set_error(e.msg);
     return e.code;

@@ -1,0 +1,104 @@
+"""Batched Algorithm 1 (dks_lobpcgf_solve_batch) on the GPU against the dense
+FP64 oracle: uneven independent systems (the shape of the 64-system batch, at
+sizes the dense oracle diagonalises in seconds) and the k-points of one
+description (a k, -k pair, whose spectra coincide by time reversal)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import sysgen
+from oracle import dks, lobpcgf
+from tests.test_gpu_parity import _dk, _hexagonal_system
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _start_blocks(dk, b, systems, ns, seed):
+    import torch
+    Xs = []
+    for i, (s, n) in enumerate(zip(systems, ns)):
+        N, _, mil = dk.basis_info(b, i)
+        X0 = np.zeros((n, 4, N), dtype=np.complex128)
+        kidx = 0 if s.kpts.shape[0] == 1 else i
+        X0[:, :2] = sysgen.start_block(mil, s.lattice, s.kpts[kidx], n, seed + i)
+        Xs.append(torch.from_numpy(X0).to("cuda:0"))
+    return Xs
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_uneven_systems_match_dense(dev, mode):
+    dk = _dk()
+    systems = sysgen.uneven_batch(seed=3, count=5, npw_range=(400, 650))
+    # block boundaries at spectral gaps (the block method needs one there): per
+    # system the even n <= min(n_bands, 24) with the widest gap to the next
+    # state; system 1 takes n = 5, which splits a Kramers pair
+    ns, refs = [], []
+    for i, s in enumerate(systems):
+        w = lobpcgf.lowest_positive(dks.DKSOperator(s).dense(), 26, s.c)[0]
+        nmax = min(s.n_bands, 24)
+        n = 5 if i == 1 else max(range(4, nmax + 1, 2), key=lambda m: w[m] - w[m - 1])
+        ns.append(n)
+        refs.append(w[:n])
+    b = dk.init_basis(systems)
+    Xs = _start_blocks(dk, b, systems, ns, seed=11)
+    print(f"[batch uneven] mode={mode} N={[dk.basis_info(b, i, miller=False)[0] for i in range(len(systems))]} n={ns}",
+          flush=True)
+    opts = dk.default_opts(mode=mode, kinetic_balance=1, n_iter=400)
+    lams, ress, infos, rc = dk.lobpcgf_solve_batch(b, list(range(len(systems))), ns, Xs, opts)
+    b.close()
+    assert rc == 0, infos
+    for i, (lam, ref, res) in enumerate(zip(lams, refs, ress)):
+        assert np.max(np.abs(lam - ref)) < 1e-8, (i, lam - ref)
+        assert np.all(res < 1e-8), (i, res)
+        assert infos[i]["converged"] == 1
+        if mode == 1:
+            assert infos[i]["iters_reduced"] > 0
+
+
+def test_batch_kpoint_pair(dev):
+    """k and -k of one description in one batch: equal spectra (time reversal),
+    the k spectrum equal to the dense one."""
+    dk = _dk()
+    s1 = _hexagonal_system()
+    k = s1.kpts[0]
+    s = dataclasses.replace(s1, kpts=np.array([k, -k]))
+    n = 6
+    ref = lobpcgf.lowest_positive(dks.DKSOperator(s, 0).dense(), n, s.c)[0]
+    b = dk.init_basis([s])
+    assert dk.num_systems(b) == 2
+    Xs = _start_blocks(dk, b, [s, s], [n, n], seed=4)
+    print("[batch k-point pair] n=6", flush=True)
+    lams, ress, infos, rc = dk.lobpcgf_solve_batch(b, [0, 1], [n, n], Xs,
+                                                   dk.default_opts(kinetic_balance=1, n_iter=400))
+    b.close()
+    assert rc == 0, infos
+    assert np.max(np.abs(lams[0] - ref)) < 1e-8, lams[0] - ref
+    assert np.max(np.abs(lams[1] - lams[0])) < 2e-8, lams[1] - lams[0]
+
+
+def test_batch_errors_are_per_item(dev):
+    """An invalid item (n above the limit) fails with EINVAL naming it, while
+    the valid item in the same batch is still solved."""
+    import torch
+    dk = _dk()
+    s = sysgen.tiny_dimer(0)
+    b = dk.init_basis([s])
+    N, _, mil = dk.basis_info(b, 0)
+    good = torch.zeros((8, 4, N), dtype=torch.complex128, device=dev)
+    phi = sysgen.start_block(mil, s.lattice, s.kpts[0], 8, 0)
+    good[:, :2] = torch.from_numpy(phi).to(dev)
+    bad = torch.zeros((171, 4, N), dtype=torch.complex128, device=dev)
+    with pytest.raises(dk.DksError) as e:
+        dk.lobpcgf_solve_batch(b, [0, 0], [8, 171], [good, bad], dk.default_opts(kinetic_balance=1))
+    b.close()
+    assert e.value.code == -1
+    assert "batch item 1" in str(e.value)
