@@ -38,25 +38,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic(kernel, s, N, ncol, nb):
-    """Algorithmic bytes (or flops) of one launch of `kernel` on nb bands.
+def algorithmic(kernel, s, N, ncol, nrows, nb):
+    """Algorithmic HBM bytes and flops of one launch of `kernel` on nb bands.
 
-    k_plane: each (band-component, z plane) reads and writes its ncol pruned
-    column values once; the local potential is read once per launch.
-    k_zfft_inv / k_zfft_fwd: the sphere block (read, or read+write for the
-    accumulate) plus the pruned column block.  k_gemm_ip: 8 flops per complex
-    multiply-add.  Returns (amount, unit, bound)."""
+    Bytes -- k_plane: each (band-component, z plane) reads and writes its ncol
+    pruned column values once, and the local potential is read once per
+    launch; k_zfft_inv / k_zfft_fwd: the sphere block (read, or read + write for
+    the accumulate) plus the pruned column block.
+    Flops -- the nominal 5 n log2 n of a length-n complex FFT per line: k_plane
+    transforms nrows lines along a2 and n2 lines along a1, each inverse and
+    forward, plus 2 flops per point for the real potential; the z transforms
+    one line of n3 per column.  Returns (bytes, flops) or (None, None)."""
     n1, n2, n3 = s.grid
     cs = 16 if kernel.endswith(".f64") else 8
     rs = cs // 2
     ncols = 4 * nb
+    f1, f2, f3 = (5 * m * math.log2(m) for m in (n1, n2, n3))
     if kernel.startswith("k_plane"):
-        return ncols * n3 * 2 * ncol * cs + n1 * n2 * n3 * rs, "GB/s", "hbm"
+        by = ncols * n3 * 2 * ncol * cs + n1 * n2 * n3 * rs
+        fl = ncols * n3 * (2 * nrows * f2 + 2 * n2 * f1 + 2 * n1 * n2)
+        return by, fl
     if kernel.startswith("k_zfft_inv"):
-        return ncols * (N + n3 * ncol) * cs, "GB/s", "hbm"
+        return ncols * (N + n3 * ncol) * cs, ncols * ncol * f3
     if kernel.startswith("k_zfft_fwd"):
-        return ncols * (2 * N + n3 * ncol) * cs, "GB/s", "hbm"
-    return None, None, None
+        return ncols * (2 * N + n3 * ncol) * cs, ncols * ncol * f3
+    return None, None
 
 
 def measured_traffic(kernel):
@@ -84,6 +90,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve runs")
     ap.add_argument("--only-apply", action="store_true",
                     help="profiling aid: only K FP64 H.X applications of the 40-band block, then "
                          "one device copy of 1 GiB (the calibration kernel for HBM counters)")
@@ -108,6 +115,7 @@ def main():
     n = s.n_bands
     log(f"[bench] heavy dimer: N={N} grid={grid} n={n} setup {time.time() - t0:.1f}s")
     ncol = len({(int(a), int(c)) for a, c in mil[:, :2]})
+    nrows = len({int(a) for a in mil[:, 0]})
 
     phi = sysgen.start_block(mil, s.lattice, s.kpts[0], n, 0)
     X0 = np.zeros((n, 4, N), dtype=np.complex128)
@@ -158,13 +166,24 @@ def main():
     dk.profile_enable(False)
     kernels = {k: {"count": v["count"], "avg_ms": v["total_ms"] / v["count"]} for k, v in kstats.items()}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["count"])
-    amount, unit, bound = algorithmic(dom, s, N, ncol, n)
+    by, fl = algorithmic(dom, s, N, ncol, nrows, n)
     roof = None
-    if amount is not None:
-        achieved = amount / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": unit, "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
-                "algorithmic_bytes_per_launch": amount, "avg_launch_ms": kernels[dom]["avg_ms"]}
+    if by is not None:
+        # the binding roofline is the one whose ideal time is longer: HBM bytes at
+        # 8 TB/s or FP64 vector flops at 78.6 TFLOP/s (FFT arithmetic, no MFMA)
+        t = kernels[dom]["avg_ms"] * 1e-3
+        gbs, tfs = by / t / 1e9, fl / t / 1e12
+        alu = fl / (FP64_PEAK_TFLOPS * 1e12) > by / (HBM_PEAK_GBS * 1e9)
+        roof = {"kernel": dom, "bound": "alu" if alu else "hbm",
+                "achieved": tfs if alu else gbs,
+                "peak": FP64_PEAK_TFLOPS if alu else HBM_PEAK_GBS,
+                "unit": "TFLOP/s" if alu else "GB/s",
+                "frac": tfs / FP64_PEAK_TFLOPS if alu else gbs / HBM_PEAK_GBS,
+                "traffic": measured_traffic(dom),
+                "algorithmic_bytes_per_launch": by, "algorithmic_flops_per_launch": fl,
+                "hbm_GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                "fp64_TFLOPs": tfs, "fp64_frac": tfs / FP64_PEAK_TFLOPS,
+                "avg_launch_ms": kernels[dom]["avg_ms"]}
     log(f"[bench] kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}ms" for k, v in kernels.items()))
 
     # ---- LOBPCG-F iterations (FP64), all columns active
@@ -193,7 +212,8 @@ def main():
     if os.path.exists(gpath):
         golden = np.array(json.load(open(gpath))["eigenvalues"])
     if not args.no_solve:
-        for tag, mode in (("fp64", dk.MODE_FP64), ("mixed_fp32", dk.MODE_MIXED_FP32)):
+        for tag, mode in (("fp64", dk.MODE_FP64), ("mixed_fp32", dk.MODE_MIXED_FP32),
+                          ("mixed_bf16gram", dk.MODE_MIXED_BF16GRAM)):
             Xd = X0d.clone()
             o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1)
             torch.cuda.synchronize()
@@ -210,6 +230,46 @@ def main():
                 rec["per_band_err_Ha"] = [float(x) for x in err]
             tts[tag] = rec
             log(f"[bench] solve {tag}: {dt:.3f}s, {info['iterations']} it, max|r| {info['max_resnorm']:.2e}")
+
+    # ---- batched solves: 16 uneven independent systems (the shape of the 64-system
+    # batch), in one dks_lobpcgf_solve_batch call versus one solve after another
+    batch = None
+    if not args.no_solve and not args.no_batch:
+        systems = sysgen.uneven_batch(seed=0, count=16)
+        bb = dk.init_basis(systems)
+        ns = [s_.n_bands for s_ in systems]
+        sizes = [dk.basis_info(bb, i, miller=False)[0] for i in range(len(systems))]
+
+        def blocks():
+            Xs = []
+            for i, (s_, n_) in enumerate(zip(systems, ns)):
+                _, _, mil_ = dk.basis_info(bb, i)
+                X0_ = np.zeros((n_, 4, sizes[i]), dtype=np.complex128)
+                X0_[:, :2] = sysgen.start_block(mil_, s_.lattice, s_.kpts[0], n_, 100 + i)
+                Xs.append(torch.from_numpy(X0_).to(dev))
+            return Xs
+        batch = {"systems": len(systems), "npw": sizes, "bands": ns}
+        for tag, mode in (("fp64", dk.MODE_FP64), ("mixed_fp32", dk.MODE_MIXED_FP32)):
+            o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1)
+            Xs = blocks()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, _, infos, _ = dk.lobpcgf_solve_batch(bb, list(range(len(systems))), ns, Xs, o)
+            torch.cuda.synchronize()
+            batch[f"{tag}_batch_s"] = time.perf_counter() - t
+            batch[f"{tag}_batch_converged"] = sum(int(i_["converged"]) for i_ in infos)
+            log(f"[bench] batch of {len(systems)} uneven systems, {tag}: "
+                f"{batch[f'{tag}_batch_s']:.3f}s, {batch[f'{tag}_batch_converged']} converged")
+        o = dk.default_opts(mode=dk.MODE_FP64, tol=1e-8, n_iter=400, kinetic_balance=1)
+        Xs = blocks()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(len(systems)):
+            dk.lobpcgf_solve(bb, i, ns[i], Xs[i], o)
+        torch.cuda.synchronize()
+        batch["fp64_sequential_s"] = time.perf_counter() - t
+        log(f"[bench] same systems one after another, fp64: {batch['fp64_sequential_s']:.3f}s")
+        bb.close()
 
     # ---- CPU oracle on a bounded sample: one Algorithm 1 iteration on the same system
     cpu = None
@@ -256,6 +316,7 @@ def main():
         "hx_ms_per_40_bands": {k: v["ms_per_apply"] for k, v in hx.items()},
         "mixed_fp32_iters_per_s": 1000.0 / step32_ms,
         "time_to_solution_1e-8": tts,
+        "batch_uneven": batch,
         "kernels_apply_H_fp64": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
