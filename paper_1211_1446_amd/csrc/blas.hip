@@ -2,7 +2,8 @@
 //  gemm_ip   small Gram-type products  out[i][j] = sum_k conj(A_i[k]) B_j[k]
 //            on the matrix cores (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32),
 //            split along k over many workgroups, partial sums reduced in FP64;
-//  gemm_up   block updates  out_j[k] = sum_i V[i][j] A_i[k] (+ beta out_j[k]);
+//  gemm_up   block updates  out_j[k] = sum_i V[i][j] A_i[k] (+ beta out_j[k]),
+//            also on the matrix cores;
 //  residuals, column norms, gathers and conversions.
 #include "dks_internal.h"
 #include "fft_device.h"
@@ -416,77 +417,103 @@ template void gemm_ip<float>(const float2 *, const int64_t *, int, const float2 
 // block update
 // ---------------------------------------------------------------------------
 constexpr int kUpICH = 64;   // rows of V staged in LDS at a time
-constexpr int kUpIU = 4;     // input rows whose loads are issued together
 
-// out_j[k] = sum_i V[i][j] A_i[k] (+ beta out_j[k]) for j in [j0, j0 + JT): one
-// thread per k holds all JT outputs, so each A element is read once per
-// column block; V rows are LDS broadcasts.
-template <typename T, int JT>
-__global__ void __launch_bounds__(256) k_gemm_up(const typename CT<T>::c *__restrict__ A,
-                                                 const int64_t *__restrict__ aoff, int m,
-                                                 const double2 *__restrict__ V, int ldv, int n,
-                                                 int64_t K, typename CT<T>::c *__restrict__ out,
-                                                 int64_t ldo, T beta) {
+// Block update out_j[k] = sum_i V[i][j] A_i[k] (+ beta out_j[k]) on the matrix
+// cores: out (n x K) = V^T (n x m) A (m x K) as
+// 16 x 16 x 4 products, V^T the left operand (rows j, reduction over i) and the
+// rows of A the right one.  A workgroup of 4 waves covers kUpMK k values of
+// kUpMJ columns j: each wave 3 j-tiles x 2 k-tiles of 16, complex as four real
+// products.  V comes through LDS in chunks of kUpICH rows; the A fragments of
+// the next 4-row step are fetched while the current one is multiplied.
+constexpr int kUpMJ = 48;
+constexpr int kUpMK = 128;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *__restrict__ A,
+                                                      const int64_t *__restrict__ aoff, int m,
+                                                      const double2 *__restrict__ V, int ldv,
+                                                      int n, int64_t K,
+                                                      typename CT<T>::c *__restrict__ out,
+                                                      int64_t ldo, T beta) {
   using C = typename CT<T>::c;
-  __shared__ C Vs[kUpICH * JT];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j0 = blockIdx.y * JT;
-  C acc[JT];
+  using MF = Mfma<T>;
+  using acc_t = typename MF::acc;
+  __shared__ T Vr[kUpICH * kUpMJ], Vi[kUpICH * kUpMJ];
+  __shared__ int64_t offs[kUpICH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j0 = blockIdx.y * kUpMJ;
+  const int64_t k0 = (int64_t)blockIdx.x * kUpMK + wave * 32;
+  const int li = lane >> 4, lc = lane & 15;
+  acc_t re[3][2], im[3][2];
 #pragma unroll
-  for (int j = 0; j < JT; ++j) acc[j] = C{0, 0};
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      re[a][b] = acc_t{0, 0, 0, 0};
+      im[a][b] = acc_t{0, 0, 0, 0};
+    }
   for (int i0 = 0; i0 < m; i0 += kUpICH) {
     const int ic = min(kUpICH, m - i0);
-    for (int e = threadIdx.x; e < kUpICH * JT; e += blockDim.x) {
-      const int ii = e / JT, jj = e - (e / JT) * JT;
+    for (int e = tid; e < kUpICH * kUpMJ; e += blockDim.x) {
+      const int ii = e / kUpMJ, jj = e - (e / kUpMJ) * kUpMJ;
       const double2 v = (ii < ic && j0 + jj < n) ? V[(size_t)(i0 + ii) * ldv + j0 + jj] : make_double2(0, 0);
-      Vs[e] = C{(T)v.x, (T)v.y};
+      Vr[e] = (T)v.x;
+      Vi[e] = (T)v.y;
+    }
+    for (int e = tid; e < kUpICH; e += blockDim.x)
+      offs[e] = (e < ic) ? (aoff ? aoff[i0 + e] : (int64_t)(i0 + e) * K) : 0;
+    __syncthreads();
+    // A fragments of 4-row step s: row ii = 4 s + li, columns k0 + 16 kt + lc
+    C fa[2], nx[2];
+    auto fetch = [&](int st, C *f) {
+      const int ii = 4 * st + li;
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {
+        const int64_t k = k0 + 16 * kt + lc;
+        f[kt] = (ii < ic && k < K) ? A[offs[ii] + k] : C{0, 0};
+      }
+    };
+    const int nst = (ic + 3) / 4;
+    fetch(0, fa);
+    for (int st = 0; st < nst; ++st) {
+      if (st + 1 < nst) fetch(st + 1, nx);
+      const int ii = 4 * st + li;
+#pragma unroll
+      for (int jt = 0; jt < 3; ++jt) {
+        const T vr = Vr[ii * kUpMJ + jt * 16 + lc], vi = Vi[ii * kUpMJ + jt * 16 + lc];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+          // v a: re += vr ar - vi ai, im += vr ai + vi ar
+          re[jt][kt] = MF::mma(vr, fa[kt].x, re[jt][kt]);
+          im[jt][kt] = MF::mma(vr, fa[kt].y, im[jt][kt]);
+          re[jt][kt] = MF::mma(-vi, fa[kt].y, re[jt][kt]);
+          im[jt][kt] = MF::mma(vi, fa[kt].x, im[jt][kt]);
+        }
+      }
+      fa[0] = nx[0];
+      fa[1] = nx[1];
     }
     __syncthreads();
-    if (k < K) {
-      int ii = 0;
-      for (; ii + kUpIU <= ic; ii += kUpIU) {
-        C a[kUpIU];
+  }
 #pragma unroll
-        for (int u = 0; u < kUpIU; ++u) {
-          const int i = i0 + ii + u;
-          a[u] = A[(aoff ? aoff[i] : (int64_t)i * K) + k];
-        }
+  for (int jt = 0; jt < 3; ++jt)
 #pragma unroll
-        for (int u = 0; u < kUpIU; ++u)
+    for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-          for (int jj = 0; jj < JT; ++jj) {
-            const C v = Vs[(ii + u) * JT + jj];
-            acc[jj].x += v.x * a[u].x - v.y * a[u].y;
-            acc[jj].y += v.x * a[u].y + v.y * a[u].x;
+      for (int v = 0; v < 4; ++v) {
+        const int j = j0 + jt * 16 + MF::row(lane, v);
+        const int64_t k = k0 + 16 * kt + lc;
+        if (j < n && k < K) {
+          C *o = out + (size_t)j * ldo + k;
+          C r{(T)re[jt][kt][v], (T)im[jt][kt][v]};
+          if (beta != T(0)) {
+            const C ov = *o;
+            r.x += beta * ov.x;
+            r.y += beta * ov.y;
           }
-      }
-      for (; ii < ic; ++ii) {
-        const int i = i0 + ii;
-        const C a = A[(aoff ? aoff[i] : (int64_t)i * K) + k];
-#pragma unroll
-        for (int jj = 0; jj < JT; ++jj) {
-          const C v = Vs[ii * JT + jj];
-          acc[jj].x += v.x * a.x - v.y * a.y;
-          acc[jj].y += v.x * a.y + v.y * a.x;
+          *o = r;
         }
       }
-    }
-    __syncthreads();
-  }
-  if (k >= K) return;
-#pragma unroll
-  for (int jj = 0; jj < JT; ++jj) {
-    if (j0 + jj < n) {
-      C *o = out + (size_t)(j0 + jj) * ldo + k;
-      C r = acc[jj];
-      if (beta != T(0)) {
-        C ov = *o;
-        r.x += beta * ov.x;
-        r.y += beta * ov.y;
-      }
-      *o = r;
-    }
-  }
 }
 
 template <typename T>
@@ -494,16 +521,9 @@ void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int
              int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st) {
   if (n <= 0 || K <= 0) return;
   const char *name = sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32";
-  const unsigned gx = (unsigned)((K + 255) / 256);
-#define DKS_UP(JT_)                                                                            \
-  DKS_LAUNCH(name, (k_gemm_up<T, JT_>), dim3(gx, (n + JT_ - 1) / JT_), dim3(256), 0, st, A,    \
-             aoff, m, V, ldv, n, K, out, ldo, (T)beta)
-  if (n <= 8) DKS_UP(8);
-  else if (n <= 16) DKS_UP(16);
-  else if (n <= 24) DKS_UP(24);
-  else if (n <= 32) DKS_UP(32);
-  else DKS_UP(40);
-#undef DKS_UP
+  dim3 grid((unsigned)((K + kUpMK - 1) / kUpMK), (n + kUpMJ - 1) / kUpMJ);
+  DKS_LAUNCH(name, k_gemm_up_mfma<T>, grid, dim3(256), 0, st, A, aoff, m, V, ldv, n, K, out, ldo,
+             (T)beta);
   DKS_HIP(hipGetLastError());
 }
 template void gemm_up<double>(const double2 *, const int64_t *, int, const double2 *, int, int,

@@ -875,6 +875,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rayleigh_ritz(
   // ---- 7. back-transformation: Uc = Q U, then V = D Li^H Uc
   if (packed) back_transform<16, 8>(PackedLower{big}, r, nkeep, tauv, U, Uc);
   else back_transform<64, 8>(FullLower{Mm, r}, r, nkeep, tauv, U, Uc);
+  DKS_RR_STAMP(11);
   for (int e = tid; e < nz * nkeep; e += nt) Vout[e] = make_double2(0, 0);
   __syncthreads();
   // Vout[kb][j] = d_kb sum_{a >= b} conj(Li[a][b]) Uc[a][j]
