@@ -359,7 +359,7 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   DKS_HIP(hipGetLastError());
   dim3 gp(n3, ncols);
   size_t smp = sizeof(C) * (size_t)s.grid[0] * (s.grid[1] + 1);
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), k_plane<T>, gp, dim3(sizeof(T) == 8 ? 768 : 512), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), k_plane<T>, gp, dim3(768), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
                      s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(), Tw<T>(pot, 0),
                      Tw<T>(pot, 1), Vtab<T>(pot));
   DKS_HIP(hipGetLastError());
