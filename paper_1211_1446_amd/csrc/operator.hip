@@ -104,11 +104,13 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
 // ---------------------------------------------------------------------------
 // one z plane: 2D inverse FFT, x V, 2D forward FFT, all in LDS
 // ---------------------------------------------------------------------------
-// 768 threads: three waves per SIMD for the FP64 planes (one 149 KB plane per
-// CU), with a 168-VGPR budget that still holds the codelets; FP32 planes run
-// at 512 threads, two workgroups per CU.
+// One plane per workgroup, one workgroup per CU (the FP64 plane fills the LDS;
+// the FP32 codelets need more than the 64 VGPRs two workgroups would leave).
+// Measured best: 768 threads in FP64 (three waves per SIMD, a 168-VGPR budget
+// that still holds the codelets), 1024 in FP32.
+template <typename T> constexpr int kPlaneThreads = sizeof(T) == 8 ? 768 : 1024;
 template <typename T>
-__global__ void __launch_bounds__(768) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
+__global__ void __launch_bounds__(kPlaneThreads<T>) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
                                                 const int4 *__restrict__ col_info,
                                                 const int *__restrict__ rows, int nrows,
                                                 const FftPlan *__restrict__ pxy,
@@ -359,7 +361,7 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   DKS_HIP(hipGetLastError());
   dim3 gp(n3, ncols);
   size_t smp = sizeof(C) * (size_t)s.grid[0] * (s.grid[1] + 1);
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), k_plane<T>, gp, dim3(768), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), k_plane<T>, gp, dim3(kPlaneThreads<T>), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
                      s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(), Tw<T>(pot, 0),
                      Tw<T>(pot, 1), Vtab<T>(pot));
   DKS_HIP(hipGetLastError());
