@@ -155,7 +155,8 @@ dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, d
       for (int d = 0; d < 3; ++d)
         DKS_REQUIRE(smooth235(D.grid[d]) && D.grid[d] <= 512, DKS_EINVAL,
                     "grid sizes must be products of 2, 3, 5 and <= 512");
-      DKS_REQUIRE((size_t)D.grid[0] * (D.grid[1] + 1) * sizeof(double2) <= 163840 &&
+      DKS_REQUIRE((size_t)D.grid[0] * (D.grid[1] + 1) * sizeof(double2) +
+                          sizeof(int) * (size_t)((D.grid[0] + 3) & ~3) <= 163840 &&
                       (size_t)D.grid[0] * D.grid[1] <= 16 * 1024,
                   DKS_EINVAL, "N1 x N2 plane does not fit the 160 KB LDS in FP64");
       // lattice and reciprocal lattice

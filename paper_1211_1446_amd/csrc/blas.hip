@@ -84,16 +84,19 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
     brow = B + o;
     if (two) b2row = B2 + o;
   }
-  acc_t re[2][2], im[2][2], re2[2][2], im2[2][2];
+  // conj(a) b. FP64: four real products, t[0] = re, t[1] = im. FP32: three
+  // (Gauss), t[0] = ar br, t[1] = ai bi, t[2] = (ar - ai)(br + bi), so that
+  // re = t0 + t1 and im = t2 - t0 + t1; the FP64 form keeps four because six
+  // FP64 accumulator sets halve the occupancy and cost more than they save.
+  constexpr bool gauss = sizeof(T) == 4;
+  constexpr int NT = gauss ? 3 : 2;
+  acc_t t[NT][2][2], u[NT][2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int q = 0; q < NT; ++q)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      re[i][j] = acc_t{0, 0, 0, 0};
-      im[i][j] = acc_t{0, 0, 0, 0};
-      re2[i][j] = acc_t{0, 0, 0, 0};
-      im2[i][j] = acc_t{0, 0, 0, 0};
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) t[q][i][j] = u[q][i][j] = acc_t{0, 0, 0, 0};
   // the next k step is fetched into registers while the current one is multiplied
   C ra[4], rb[4], rb2[4];
   auto fetch = [&](int64_t k0) {
@@ -126,29 +129,53 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
         bb[i] = Bs[(wn + i * 16 + (lane & 15)) * LD + kk];
         if (two) b2[i] = B2s[(wn + i * 16 + (lane & 15)) * LD + kk];
       }
+      if constexpr (gauss) {
+        T ad[2], bs[2], b2s[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          // conj(a) b: re += ar br + ai bi, im += ar bi - ai br
-          re[i][j] = MF::mma(a[i].x, bb[j].x, re[i][j]);
-          im[i][j] = MF::mma(a[i].x, bb[j].y, im[i][j]);
-          if (two) {
-            re2[i][j] = MF::mma(a[i].x, b2[j].x, re2[i][j]);
-            im2[i][j] = MF::mma(a[i].x, b2[j].y, im2[i][j]);
-          }
+        for (int i = 0; i < 2; ++i) {
+          ad[i] = a[i].x - a[i].y;
+          bs[i] = bb[i].x + bb[i].y;
+          if (two) b2s[i] = b2[i].x + b2[i].y;
         }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          re[i][j] = MF::mma(a[i].y, bb[j].y, re[i][j]);
-          im[i][j] = MF::mma(-a[i].y, bb[j].x, im[i][j]);
-          if (two) {
-            re2[i][j] = MF::mma(a[i].y, b2[j].y, re2[i][j]);
-            im2[i][j] = MF::mma(-a[i].y, b2[j].x, im2[i][j]);
+          for (int j = 0; j < 2; ++j) {
+            t[0][i][j] = MF::mma(a[i].x, bb[j].x, t[0][i][j]);
+            t[1][i][j] = MF::mma(a[i].y, bb[j].y, t[1][i][j]);
+            t[NT - 1][i][j] = MF::mma(ad[i], bs[j], t[NT - 1][i][j]);
+            if (two) {
+              u[0][i][j] = MF::mma(a[i].x, b2[j].x, u[0][i][j]);
+              u[1][i][j] = MF::mma(a[i].y, b2[j].y, u[1][i][j]);
+              u[NT - 1][i][j] = MF::mma(ad[i], b2s[j], u[NT - 1][i][j]);
+            }
           }
-        }
+      } else {
+        // re += ar br + ai bi, im += ar bi - ai br; the .x products of all
+        // tiles first so that no accumulator is reused back to back
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            t[0][i][j] = MF::mma(a[i].x, bb[j].x, t[0][i][j]);
+            t[1][i][j] = MF::mma(a[i].x, bb[j].y, t[1][i][j]);
+            if (two) {
+              u[0][i][j] = MF::mma(a[i].x, b2[j].x, u[0][i][j]);
+              u[1][i][j] = MF::mma(a[i].x, b2[j].y, u[1][i][j]);
+            }
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            t[0][i][j] = MF::mma(a[i].y, bb[j].y, t[0][i][j]);
+            t[1][i][j] = MF::mma(-a[i].y, bb[j].x, t[1][i][j]);
+            if (two) {
+              u[0][i][j] = MF::mma(a[i].y, b2[j].y, u[0][i][j]);
+              u[1][i][j] = MF::mma(-a[i].y, b2[j].x, u[1][i][j]);
+            }
+          }
+      }
     }
     __syncthreads();
   }
@@ -163,8 +190,17 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
         int r = tm0 + wm + i * 16 + MF::row(lane, v);
         int c = tn0 + wn + j * 16 + (lane & 15);
         if (r < M && c < Nn) {
-          p1[(size_t)r * Nn + c] = make_double2((double)re[i][j][v], (double)im[i][j][v]);
-          if (two) p2[(size_t)r * Nn + c] = make_double2((double)re2[i][j][v], (double)im2[i][j][v]);
+          auto val = [&](acc_t (&w)[NT][2][2]) {
+            const double x0 = w[0][i][j][v], x1 = w[1][i][j][v];
+            if constexpr (gauss) {
+              const double x2 = w[NT - 1][i][j][v];
+              return make_double2(x0 + x1, x2 - x0 + x1);
+            } else {
+              return make_double2(x0, x1);
+            }
+          };
+          p1[(size_t)r * Nn + c] = val(t);
+          if (two) p2[(size_t)r * Nn + c] = val(u);
         }
       }
 }

@@ -137,7 +137,7 @@ __device__ __forceinline__ C twt(const C *tw, int e) {
 
 // inverse step 1 on nl lines (in place)
 template <int A, int B, typename T>
-__device__ void inv_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
+__device__ __forceinline__ void inv_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
   using C = typename CT<T>::c;
   if constexpr (A > 1) {
     const int tasks = nl * B;
@@ -158,7 +158,7 @@ __device__ void inv_step1(typename CT<T>::c *buf, int nl, Lines L, const typenam
 
 // forward step 1' on nl lines (in place): DFT_A over k_a, natural output
 template <int A, int B, typename T>
-__device__ void fwd_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
+__device__ __forceinline__ void fwd_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
   using C = typename CT<T>::c;
   if constexpr (A > 1) {
     const int tasks = nl * B;
@@ -177,7 +177,7 @@ __device__ void fwd_step1(typename CT<T>::c *buf, int nl, Lines L, const typenam
 
 // inverse step 2 on the blocks (in place)
 template <int A, int B, typename T>
-__device__ void inv_step2(typename CT<T>::c *buf, int nl, Lines L) {
+__device__ __forceinline__ void inv_step2(typename CT<T>::c *buf, int nl, Lines L) {
   using C = typename CT<T>::c;
   const int tasks = nl * A;
   for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
@@ -194,7 +194,7 @@ __device__ void inv_step2(typename CT<T>::c *buf, int nl, Lines L) {
 
 // forward step 2' on the blocks (in place), including the w_n^{-b k_a} twiddle
 template <int A, int B, typename T>
-__device__ void fwd_step2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
+__device__ __forceinline__ void fwd_step2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
   using C = typename CT<T>::c;
   const int tasks = nl * A;
   for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
@@ -216,7 +216,7 @@ __device__ void fwd_step2(typename CT<T>::c *buf, int nl, Lines L, const typenam
 // inverse step 2, x V (scrambled layout, element-wise), forward step 2' fused.
 // V for line l, position p is Vp[l * vls + p * vps].
 template <int A, int B, typename T>
-__device__ void inv2_mul_fwd2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
+__device__ __forceinline__ void inv2_mul_fwd2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
                               const T *__restrict__ Vp, int vls, int vps) {
   using C = typename CT<T>::c;
   const int tasks = nl * A;
@@ -262,6 +262,27 @@ __device__ void inv2_mul_fwd2(typename CT<T>::c *buf, int nl, Lines L, const typ
   case N_:                           \
     f.template operator()<A_, B_>(); \
     return true;
+
+#define DKS_FFT_HAS(N_, A_, B_) case N_:
+// whether plane axis length n has a compiled split (host and device)
+__host__ __device__ constexpr bool plane_has(int n) {
+  switch (n) {
+    DKS_FFT_PLANE_CASES(DKS_FFT_HAS)
+    return true;
+    default:
+      return false;
+  }
+}
+// whether z length n has a compiled split (host and device)
+__host__ __device__ constexpr bool z_has(int n) {
+  switch (n) {
+    DKS_FFT_Z_CASES(DKS_FFT_HAS)
+    return true;
+    default:
+      return false;
+  }
+}
+#undef DKS_FFT_HAS
 
 template <typename F>
 __device__ __forceinline__ bool dispatch_plane(int n, F &&f) {

@@ -20,7 +20,11 @@ namespace dks {
 // ---------------------------------------------------------------------------
 // z transforms of the sphere columns
 // ---------------------------------------------------------------------------
-template <typename T>
+// Global reads are issued kZU per thread before any of them is waited for, so
+// that a wave keeps several HBM requests in flight.  kTab: n3 has a compiled
+// two-step split; the generic transforms run in a kernel of their own.
+constexpr int kZU = 4;
+template <typename T, bool kTab>
 __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__restrict__ X, int N,
                                                   const int *__restrict__ col_off,
                                                   const int2 *__restrict__ gmap, int ncol,
@@ -36,22 +40,43 @@ __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__res
   const int c0 = blockIdx.x * tile;
   const int w = min(tile, ncol - c0);
   const int cc = blockIdx.y;
-  for (int e = threadIdx.x; e < w * ld; e += blockDim.x) lines[e] = C{0, 0};
-  __syncthreads();
   const C *x = X + (size_t)cc * N;
   const int g0 = col_off[c0], g1 = col_off[c0 + w];
-  for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-    int2 m = gmap[g];
-    lines[(m.x - c0) * ld + m.y] = x[g];
+  const int nthr = blockDim.x;
+  for (int b = g0; b < g1; b += kZU * nthr) {
+    T vr[kZU], vi[kZU];
+    int pos[kZU];
+#pragma unroll
+    for (int u = 0; u < kZU; ++u) {
+      const int g = b + u * nthr + (int)threadIdx.x;
+      const int gl = min(g, g1 - 1);
+      const int2 m = gmap[gl];
+      const C v = x[gl];
+      vr[u] = v.x;
+      vi[u] = v.y;
+      pos[u] = g < g1 ? (m.x - c0) * ld + m.y : -1;
+    }
+    if (b == g0) {   // the first reads are in flight while the lines are cleared
+      for (int e = threadIdx.x; e < w * ld; e += nthr) lines[e] = C{0, 0};
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < kZU; ++u)
+      if (pos[u] >= 0) lines[pos[u]] = C{vr[u], vi[u]};
   }
+  if (g1 <= g0)
+    for (int e = threadIdx.x; e < w * ld; e += nthr) lines[e] = C{0, 0};
   __syncthreads();
   const fft2::Lines Lz{nullptr, ld, 1};
-  bool fast = fft2::dispatch_z(n3, [&]<int A, int B>() {
-    fft2::inv_step1<A, B, T>(lines, w, Lz, twz);
-    __syncthreads();
-    fft2::inv_step2<A, B, T>(lines, w, Lz);
-  });
-  if (!fast) fft_lines<+1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  if constexpr (kTab) {
+    fft2::dispatch_z(n3, [&]<int A, int B>() {
+      fft2::inv_step1<A, B, T>(lines, w, Lz, twz);
+      __syncthreads();
+      fft2::inv_step2<A, B, T>(lines, w, Lz);
+    });
+  } else {
+    fft_lines<+1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  }
   __syncthreads();
   C *t = T1 + (size_t)cc * n3 * ncol;
   for (int e = threadIdx.x; e < w * n3; e += blockDim.x) {
@@ -60,7 +85,7 @@ __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__res
   }
 }
 
-template <typename T>
+template <typename T, bool kTab>
 __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__restrict__ T1,
                                                   typename CT<T>::c *__restrict__ HX, int N,
                                                   const int *__restrict__ col_off,
@@ -78,39 +103,88 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
   const int w = min(tile, ncol - c0);
   const int cc = blockIdx.y;
   const C *t = T1 + (size_t)cc * n3 * ncol;
-  for (int e = threadIdx.x; e < w * n3; e += blockDim.x) {
-    int z = e / w, ci = e - (e / w) * w;
-    lines[ci * ld + z] = t[(size_t)z * ncol + c0 + ci];
+  const int nthr = blockDim.x;
+  const int ne = w * n3;
+  for (int b = 0; b < ne; b += kZU * nthr) {
+    T vr[kZU], vi[kZU];
+#pragma unroll
+    for (int u = 0; u < kZU; ++u) {
+      const int e = min(b + u * nthr + (int)threadIdx.x, ne - 1);
+      const int z = e / w, ci = e - (e / w) * w;
+      const C v = t[(size_t)z * ncol + c0 + ci];
+      vr[u] = v.x;
+      vi[u] = v.y;
+    }
+#pragma unroll
+    for (int u = 0; u < kZU; ++u) {
+      const int e = b + u * nthr + (int)threadIdx.x;
+      if (e < ne) {
+        const int z = e / w, ci = e - (e / w) * w;
+        lines[ci * ld + z] = C{vr[u], vi[u]};
+      }
+    }
   }
   __syncthreads();
   const fft2::Lines Lz{nullptr, ld, 1};
-  bool fast = fft2::dispatch_z(n3, [&]<int A, int B>() {
-    fft2::fwd_step2<A, B, T>(lines, w, Lz, twz);
-    __syncthreads();
-    fft2::fwd_step1<A, B, T>(lines, w, Lz, twz);
-  });
-  if (!fast) fft_lines<-1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  if constexpr (kTab) {
+    fft2::dispatch_z(n3, [&]<int A, int B>() {
+      fft2::fwd_step2<A, B, T>(lines, w, Lz, twz);
+      __syncthreads();
+      fft2::fwd_step1<A, B, T>(lines, w, Lz, twz);
+    });
+  } else {
+    fft_lines<-1, T>(lines, w, nullptr, ld, 1, pz, twz);
+  }
   __syncthreads();
   C *hx = HX + (size_t)cc * N;
   const int g0 = col_off[c0], g1 = col_off[c0 + w];
-  for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-    int2 m = gmap[g];
-    C v = lines[(m.x - c0) * ld + m.y];
-    C h = hx[g];
-    hx[g] = C{scale * (h.x + inv_ng * v.x), scale * (h.y + inv_ng * v.y)};
+  for (int b = g0; b < g1; b += kZU * nthr) {
+    T hr[kZU], hi[kZU];
+    int pos[kZU];
+#pragma unroll
+    for (int u = 0; u < kZU; ++u) {
+      const int gl = min(b + u * nthr + (int)threadIdx.x, g1 - 1);
+      const int2 m = gmap[gl];
+      const C h = hx[gl];
+      hr[u] = h.x;
+      hi[u] = h.y;
+      pos[u] = (m.x - c0) * ld + m.y;
+    }
+#pragma unroll
+    for (int u = 0; u < kZU; ++u) {
+      const int g = b + u * nthr + (int)threadIdx.x;
+      if (g < g1) {
+        const C v = lines[pos[u]];
+        hx[g] = C{scale * (hr[u] + inv_ng * v.x), scale * (hi[u] + inv_ng * v.y)};
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // one z plane: 2D inverse FFT, x V, 2D forward FFT, all in LDS
 // ---------------------------------------------------------------------------
-// One plane per workgroup, one workgroup per CU (the FP64 plane fills the LDS;
-// the FP32 codelets need more than the 64 VGPRs two workgroups would leave).
-// Measured best: 768 threads in FP64 (three waves per SIMD, a 168-VGPR budget
-// that still holds the codelets), 1024 in FP32.
-template <typename T> constexpr int kPlaneThreads = sizeof(T) == 8 ? 768 : 1024;
+// One plane per workgroup.  FP64: the plane fills the LDS, one workgroup per
+// CU, 768 threads (three waves per SIMD).  FP32: two workgroups of 512 threads
+// per CU (two planes in LDS, 128 VGPRs per lane), so that one workgroup's
+// barriers and column loads overlap the other's transforms.
+template <typename T> constexpr int kPlaneThreads = sizeof(T) == 8 ? 768 : 512;
+template <typename T> constexpr int kPlaneWaves = sizeof(T) == 8 ? 3 : 4;
+// The list of rows that hold sphere columns sits in LDS behind the plane; so
+// do the twiddle tables in FP32.  FP64 reads its twiddles through the vector
+// cache: in LDS they slow the FP64 transforms, whose LDS traffic binds.
+template <typename T> constexpr bool kPlaneTwLds = sizeof(T) == 4;
 template <typename T>
-__global__ void __launch_bounds__(kPlaneThreads<T>) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
+size_t plane_lds_bytes(int n1, int n2) {
+  using C = typename CT<T>::c;
+  return sizeof(C) * ((size_t)n1 * (n2 + 1) + (kPlaneTwLds<T> ? n1 + n2 : 0)) +
+         sizeof(int) * (size_t)((n1 + 3) & ~3);
+}
+// kTab: both plane axes have a compiled two-step split (fft2.h); otherwise the
+// generic radix transforms run, in a kernel of their own so that their calls
+// and registers stay out of the table kernel.
+template <typename T, bool kTab>
+__global__ void __launch_bounds__(kPlaneThreads<T>, kPlaneWaves<T>) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
                                                 const int4 *__restrict__ col_info,
                                                 const int *__restrict__ rows, int nrows,
                                                 const FftPlan *__restrict__ pxy,
@@ -126,34 +200,70 @@ __global__ void __launch_bounds__(kPlaneThreads<T>) k_plane(typename CT<T>::c *_
   const int z = blockIdx.x;
   const int cc = blockIdx.y;
   const int n3 = gridDim.x;
-  for (int e = threadIdx.x; e < n1 * ld; e += blockDim.x) pl[e] = C{0, 0};
-  __syncthreads();
+  int *rows_s = reinterpret_cast<int *>(pl + n1 * ld);
+  C *twx_s = reinterpret_cast<C *>(rows_s + ((n1 + 3) & ~3)), *twy_s = twx_s + n1;
+  const C *tx = kPlaneTwLds<T> ? twx_s : twx;
+  const C *ty = kPlaneTwLds<T> ? twy_s : twy;
+  auto stage = [&]() {
+    for (int e = threadIdx.x; e < n1 * ld; e += blockDim.x) pl[e] = C{0, 0};
+    for (int e = threadIdx.x; e < nrows; e += blockDim.x) rows_s[e] = rows[e];
+    if constexpr (kPlaneTwLds<T>) {
+      for (int e = threadIdx.x; e < n1; e += blockDim.x) twx_s[e] = twx[e];
+      for (int e = threadIdx.x; e < n2; e += blockDim.x) twy_s[e] = twy[e];
+    }
+  };
   C *t = T1 + ((size_t)cc * n3 + z) * ncol;
-  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-    int4 ci = col_info[c];
-    pl[ci.x * ld + ci.y] = t[c];
+  // The column values are fetched kPre per thread at a time, all loads in
+  // flight together; the first batch is in flight while the plane is cleared.
+  constexpr int kPre = 4;
+  const int nthr = blockDim.x;
+  for (int c0 = 0; c0 < ncol; c0 += kPre * nthr) {
+    T vr[kPre], vi[kPre];
+    int pos[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int c = c0 + u * nthr + (int)threadIdx.x;
+      const int cl = min(c, ncol - 1);   // loads unconditional, stores masked
+      const int4 ci = col_info[cl];
+      const C x = t[cl];
+      vr[u] = x.x;
+      vi[u] = x.y;
+      pos[u] = c < ncol ? ci.x * ld + ci.y : -1;
+    }
+    if (c0 == 0) {
+      stage();
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < kPre; ++u)
+      if (pos[u] >= 0) pl[pos[u]] = C{vr[u], vi[u]};
   }
+  if (ncol <= 0) stage();
   __syncthreads();
   const T *v = V + (size_t)z * n1 * n2;   // potential of this plane, [p1][p2] scrambled
-  const fft2::Lines Ly{rows, ld, 1};       // rows holding sphere columns, along a2
+  const fft2::Lines Ly{rows_s, ld, 1};       // rows holding sphere columns, along a2
   const fft2::Lines Lx{nullptr, 1, ld};    // every a2 position, along a1
   // inverse along a2
-  bool fy = fft2::dispatch_plane(n2, [&]<int A, int B>() {
-    fft2::inv_step1<A, B, T>(pl, nrows, Ly, twy);
-    __syncthreads();
-    fft2::inv_step2<A, B, T>(pl, nrows, Ly);
-  });
-  if (!fy) fft_lines<+1, T>(pl, nrows, rows, ld, 1, py, twy);
+  if constexpr (kTab) {
+    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+      fft2::inv_step1<A, B, T>(pl, nrows, Ly, ty);
+      __syncthreads();
+      fft2::inv_step2<A, B, T>(pl, nrows, Ly);
+    });
+  } else {
+    fft_lines<+1, T>(pl, nrows, rows, ld, 1, py, twy);
+  }
   __syncthreads();
   // inverse along a1, x V, forward along a1
-  bool fx = fft2::dispatch_plane(n1, [&]<int A, int B>() {
-    fft2::inv_step1<A, B, T>(pl, n2, Lx, twx);
-    __syncthreads();
-    fft2::inv2_mul_fwd2<A, B, T>(pl, n2, Lx, twx, v, 1, n2);
-    __syncthreads();
-    fft2::fwd_step1<A, B, T>(pl, n2, Lx, twx);
-  });
-  if (!fx) {
+  if constexpr (kTab) {
+    fft2::dispatch_plane(n1, [&]<int A, int B>() {
+      fft2::inv_step1<A, B, T>(pl, n2, Lx, tx);
+      __syncthreads();
+      fft2::inv2_mul_fwd2<A, B, T>(pl, n2, Lx, tx, v, 1, n2);
+      __syncthreads();
+      fft2::fwd_step1<A, B, T>(pl, n2, Lx, tx);
+    });
+  } else {
     fft_lines<+1, T>(pl, n2, nullptr, 1, ld, px, twx);
     for (int e = threadIdx.x; e < n1 * n2; e += blockDim.x) {
       int i = e / n2, j = e - (e / n2) * n2;
@@ -166,16 +276,31 @@ __global__ void __launch_bounds__(kPlaneThreads<T>) k_plane(typename CT<T>::c *_
   }
   __syncthreads();
   // forward along a2
-  fy = fft2::dispatch_plane(n2, [&]<int A, int B>() {
-    fft2::fwd_step2<A, B, T>(pl, nrows, Ly, twy);
-    __syncthreads();
-    fft2::fwd_step1<A, B, T>(pl, nrows, Ly, twy);
-  });
-  if (!fy) fft_lines<-1, T>(pl, nrows, rows, ld, 1, py, twy);
+  if constexpr (kTab) {
+    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+      fft2::fwd_step2<A, B, T>(pl, nrows, Ly, ty);
+      __syncthreads();
+      fft2::fwd_step1<A, B, T>(pl, nrows, Ly, ty);
+    });
+  } else {
+    fft_lines<-1, T>(pl, nrows, rows, ld, 1, py, twy);
+  }
   __syncthreads();
-  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-    int4 ci = col_info[c];
-    t[c] = pl[ci.x * ld + ci.y];
+  for (int c0 = 0; c0 < ncol; c0 += kPre * nthr) {
+    T vr[kPre], vi[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int cl = min(c0 + u * nthr + (int)threadIdx.x, ncol - 1);
+      const int4 ci = col_info[cl];
+      const C x = pl[ci.x * ld + ci.y];
+      vr[u] = x.x;
+      vi[u] = x.y;
+    }
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int c = c0 + u * nthr + (int)threadIdx.x;
+      if (c < ncol) t[c] = C{vr[u], vi[u]};
+    }
   }
 }
 
@@ -306,12 +431,17 @@ template <> const float2 *Tw<float>(const Potential &p, int d) { return p.d_tw32
 void init_kernel_attributes() {
   static bool done = false;
   if (done) return;
-  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
-  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
-  DKS_HIP(hipFuncSetAttribute((const void *)k_zfft_inv<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
-  DKS_HIP(hipFuncSetAttribute((const void *)k_zfft_inv<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
-  DKS_HIP(hipFuncSetAttribute((const void *)k_zfft_fwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
-  DKS_HIP(hipFuncSetAttribute((const void *)k_zfft_fwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  const void *big_lds[] = {
+      (const void *)k_zfft_inv<double, true>, (const void *)k_zfft_inv<double, false>,
+      (const void *)k_zfft_inv<float, true>,  (const void *)k_zfft_inv<float, false>,
+      (const void *)k_zfft_fwd<double, true>, (const void *)k_zfft_fwd<double, false>,
+      (const void *)k_zfft_fwd<float, true>,  (const void *)k_zfft_fwd<float, false>};
+  for (const void *f : big_lds)
+    DKS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   done = true;
@@ -356,16 +486,21 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   const int tile = s.tile_z;
   dim3 gz((s.ncol + tile - 1) / tile, ncols);
   size_t smz = sizeof(C) * (size_t)tile * (n3 + 1);
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_inv.f64" : "k_zfft_inv.f32"), k_zfft_inv<T>, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
+  const bool ztab = fft2::z_has(n3);
+  auto kzinv = ztab ? k_zfft_inv<T, true> : k_zfft_inv<T, false>;
+  auto kzfwd = ztab ? k_zfft_fwd<T, true> : k_zfft_fwd<T, false>;
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_inv.f64" : "k_zfft_inv.f32"), kzinv, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
                      s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2), t1);
   DKS_HIP(hipGetLastError());
   dim3 gp(n3, ncols);
-  size_t smp = sizeof(C) * (size_t)s.grid[0] * (s.grid[1] + 1);
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), k_plane<T>, gp, dim3(kPlaneThreads<T>), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
+  size_t smp = plane_lds_bytes<T>(s.grid[0], s.grid[1]);
+  const bool tab = fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]);
+  auto kplane = tab ? k_plane<T, true> : k_plane<T, false>;
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(kPlaneThreads<T>), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
                      s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(), Tw<T>(pot, 0),
                      Tw<T>(pot, 1), Vtab<T>(pot));
   DKS_HIP(hipGetLastError());
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_fwd.f64" : "k_zfft_fwd.f32"), k_zfft_fwd<T>, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_fwd.f64" : "k_zfft_fwd.f32"), kzfwd, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
                      s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2),
                      (T)(1.0 / s.ng), (T)scale);
   DKS_HIP(hipGetLastError());
