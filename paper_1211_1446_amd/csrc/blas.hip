@@ -33,6 +33,7 @@ template <> struct Mfma<float> {
 
 constexpr int kIpTile = 64;   // output tile per workgroup (4 waves of 32 x 32)
 constexpr int kIpKT = 16;     // complex k values staged per step
+constexpr int kIpBlocks = 1024;  // split-K: about this many workgroups per product launch
 
 // Output tile (ti, tj) of workgroup x: row-major over all tiles, or over the
 // tiles on and above the diagonal when only the upper triangle is wanted.
@@ -205,28 +206,54 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
       }
 }
 
-// out[i][j] = sum over splits; with `upper`, entries of tiles below the
-// diagonal were not computed and are the conjugates of their mirror images.
-// Both products (part -> out, part2 -> out2) in one launch.
-__global__ void k_reduce_part(const double2 *__restrict__ part, const double2 *__restrict__ part2,
-                              int nsplit, int M, int Nn, int upper, double2 *__restrict__ out,
-                              double2 *__restrict__ out2, int ldo) {
+// out[i][j] = sum over splits of the partial products.  A block takes 64
+// consecutive entries of one product; its kRedWaves waves take every
+// kRedWaves-th split and the wave sums meet in LDS in a fixed order, so the
+// result does not depend on scheduling.  With `upper`, only tiles on or above
+// the diagonal were computed: an entry of a tile above it also writes its
+// mirror image, conjugated.  Both products (part -> out, part2 -> out2) in one
+// launch.
+constexpr int kRedWaves = 16;
+__global__ void __launch_bounds__(64 * kRedWaves)
+    k_reduce_part(const double2 *__restrict__ part, const double2 *__restrict__ part2, int nsplit,
+                  int M, int Nn, int upper, double2 *__restrict__ out, double2 *__restrict__ out2,
+                  int ldo) {
+  __shared__ double2 red[kRedWaves][64];
   const int nel = M * Nn;
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int e = blockIdx.x * 64 + lane;
   const bool second = e >= nel;
   if (second) e -= nel;
-  if (e >= nel || (second && !part2)) return;
-  const double2 *p = second ? part2 : part;
   const int i = e / Nn, j = e - (e / Nn) * Nn;
-  const bool mirror = upper && (i / kIpTile) > (j / kIpTile);
-  const int src = mirror ? j * Nn + i : e;
+  const bool valid = e < nel && (!second || part2) && !(upper && (i / kIpTile) > (j / kIpTile));
   double re = 0, im = 0;
-  for (int z = 0; z < nsplit; ++z) {
-    double2 v = p[(size_t)z * nel + src];
-    re += v.x;
-    im += v.y;
+  if (valid) {
+    const double2 *p = (second ? part2 : part) + e;
+#pragma unroll 4
+    for (int z = w; z < nsplit; z += kRedWaves) {
+      const double2 v = p[(size_t)z * nel];
+      re += v.x;
+      im += v.y;
+    }
   }
-  (second ? out2 : out)[(size_t)i * ldo + j] = make_double2(re, mirror ? -im : im);
+  red[w][lane] = make_double2(re, im);
+  __syncthreads();
+  if (w != 0 || !valid) return;
+  for (int q = 1; q < kRedWaves; ++q) {
+    re += red[q][lane].x;
+    im += red[q][lane].y;
+  }
+  double2 *o = second ? out2 : out;
+  o[(size_t)i * ldo + j] = make_double2(re, im);
+  if (upper && (i / kIpTile) < (j / kIpTile)) o[(size_t)j * ldo + i] = make_double2(re, -im);
+}
+
+static void reduce_parts(const double2 *p1, const double2 *p2, int nsplit, int M, int Nn, bool upper,
+                         double2 *out, double2 *out2, int ldo, hipStream_t st) {
+  const int nel = M * Nn * (p2 ? 2 : 1);
+  DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 63) / 64), dim3(64 * kRedWaves), 0, st, p1,
+             p2, nsplit, M, Nn, (int)upper, out, out2, ldo);
+  DKS_HIP(hipGetLastError());
 }
 
 template <typename T>
@@ -238,7 +265,7 @@ void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, con
   const bool upper = hermitian && M == Nn;
   const int tiles = upper ? tm * (tm + 1) / 2 : tm * tn;
   int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
-  int64_t nsplit = (1024 + tiles - 1) / tiles;
+  int64_t nsplit = (kIpBlocks + tiles - 1) / tiles;
   nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
   int64_t kchunk = (K + nsplit - 1) / nsplit;
   kchunk = (kchunk + kIpKT - 1) / kIpKT * kIpKT;
@@ -254,10 +281,7 @@ void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, con
   DKS_LAUNCH(name, k_gemm_ip<T>, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk, tm,
              (int)upper, p1, p2);
   DKS_HIP(hipGetLastError());
-  int nel = M * Nn * nmat;
-  DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p1, p2,
-             (int)nsplit, M, Nn, (int)upper, out, out2, ldo);
-  DKS_HIP(hipGetLastError());
+  reduce_parts(p1, p2, (int)nsplit, M, Nn, upper, out, out2, ldo, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,7 +446,7 @@ void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, 
   const bool upper = hermitian && M == Nn;
   const int tiles = upper ? tm * (tm + 1) / 2 : tm * tn;
   int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
-  int64_t nsplit = (1024 + tiles - 1) / tiles;
+  int64_t nsplit = (kIpBlocks + tiles - 1) / tiles;
   nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
   int64_t kchunk = (K + nsplit - 1) / nsplit;
   kchunk = (kchunk + kIpKT - 1) / kIpKT * kIpKT;
@@ -436,10 +460,7 @@ void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, 
   DKS_LAUNCH("k_gemm_ip.gram.bf16", k_gemm_ip_bf16, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn,
              B2, K, kchunk, tm, (int)upper, p1, p2);
   DKS_HIP(hipGetLastError());
-  int nel = M * Nn * nmat;
-  DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 255) / 256), dim3(256), 0, st, p1, p2,
-             (int)nsplit, M, Nn, (int)upper, out, out2, ldo);
-  DKS_HIP(hipGetLastError());
+  reduce_parts(p1, p2, (int)nsplit, M, Nn, upper, out, out2, ldo, st);
 }
 
 template void gemm_ip<double>(const double2 *, const int64_t *, int, const double2 *,
