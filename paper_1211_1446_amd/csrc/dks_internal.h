@@ -177,6 +177,18 @@ struct dks_basis {
 
 namespace dks {
 
+// Workgroups are handed to the eight XCDs of the chip in turn (workgroup L to
+// XCD L mod 8), and each XCD has its own L2.  xcd_order maps L to a work index
+// so that each XCD gets one contiguous range of work indices, issued in order:
+// work items that share data (neighbouring indices) then meet in one L2.
+// A bijection of [0, total).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_order(int L, int total) {
+  const int per = total / kXcds, rem = total % kXcds;
+  const int x = L % kXcds, q = L / kXcds;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + q;
+}
+
 // ---------------------------------------------------------------------------
 // launchers (all asynchronous on `st`)
 // ---------------------------------------------------------------------------

@@ -332,8 +332,12 @@ __global__ void k_apply_w(const double2 *__restrict__ Cin, double2 *__restrict__
   }
 }
 
-// HX = B C' + kinetic(X) - shift X, for a tile of kBT bands per workgroup.
+// HX = B C' + kinetic(X) - shift X.  A workgroup takes 256 planewaves of kBT
+// bands; the band tiles of one planewave block are neighbouring work items in
+// XCD order, so the block's projector rows B[:, g] come from one L2.  B is read
+// kPB rows at a time, all loads in flight together.
 constexpr int kBT = 4;
+constexpr int kPB = 6;
 template <typename T>
 __global__ void __launch_bounds__(256) k_nl_kin(const typename CT<T>::c *__restrict__ X,
                                                 typename CT<T>::c *__restrict__ HX, int N, int nb,
@@ -343,7 +347,10 @@ __global__ void __launch_bounds__(256) k_nl_kin(const typename CT<T>::c *__restr
   using C = typename CT<T>::c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *cs = reinterpret_cast<C *>(smem_raw);  // [nproj][4 kBT]
-  const int b0 = blockIdx.y * kBT;
+  const int ntb = (nb + kBT - 1) / kBT;
+  const int w = xcd_order(blockIdx.x, gridDim.x);
+  const int gb = w / ntb, tb = w - (w / ntb) * ntb;
+  const int b0 = tb * kBT;
   const int bw = min(kBT, nb - b0);
   for (int e = threadIdx.x; e < nproj * 4 * kBT; e += blockDim.x) {
     int p = e / (4 * kBT), j = e - (e / (4 * kBT)) * (4 * kBT);
@@ -351,18 +358,26 @@ __global__ void __launch_bounds__(256) k_nl_kin(const typename CT<T>::c *__restr
     cs[e] = C{(T)v.x, (T)v.y};
   }
   __syncthreads();
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = gb * blockDim.x + threadIdx.x;
   if (g >= N) return;
   C acc[4 * kBT];
 #pragma unroll
   for (int j = 0; j < 4 * kBT; ++j) acc[j] = C{0, 0};
-  for (int p = 0; p < nproj; ++p) {
-    C bv = B[(size_t)p * N + g];
+  for (int p0 = 0; p0 < nproj; p0 += kPB) {
+    C bv[kPB];
 #pragma unroll
-    for (int j = 0; j < 4 * kBT; ++j) {
-      C cv = cs[p * 4 * kBT + j];
-      acc[j].x += cv.x * bv.x - cv.y * bv.y;
-      acc[j].y += cv.x * bv.y + cv.y * bv.x;
+    for (int u = 0; u < kPB; ++u) bv[u] = B[(size_t)min(p0 + u, nproj - 1) * N + g];
+#pragma unroll
+    for (int u = 0; u < kPB; ++u) {
+      if (p0 + u < nproj) {
+        const C *cr = cs + (p0 + u) * 4 * kBT;
+#pragma unroll
+        for (int j = 0; j < 4 * kBT; ++j) {
+          const C cv = cr[j];
+          acc[j].x += cv.x * bv[u].x - cv.y * bv[u].y;
+          acc[j].y += cv.x * bv[u].y + cv.y * bv[u].x;
+        }
+      }
     }
   }
   const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
@@ -473,7 +488,7 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
     Cp = ws.nlc2.as<double2>();
   }
   {
-    dim3 grid((N + 255) / 256, (nb + kBT - 1) / kBT);
+    dim3 grid((unsigned)(((N + 255) / 256) * ((nb + kBT - 1) / kBT)));
     size_t sm = sizeof(C) * (size_t)s.nproj * 4 * kBT;
     DKS_LAUNCH((sizeof(T) == 8 ? "k_nl_kin.f64" : "k_nl_kin.f32"), k_nl_kin<T>, grid, dim3(256), sm, st, X, HX, N, nb, Btab<T>(s), s.nproj, Cp,
                        ncols, Qtab<T>(s), (T)s.c, (T)shift);
