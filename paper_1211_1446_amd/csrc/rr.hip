@@ -2,8 +2,9 @@
 // the subspace, sorted ascending) in FP64 on the device.
 //
 // Solves A v = theta S v for the nkeep lowest theta above `floor_val`, with
-// A = Z^H H Z and S = Z^H Z of the current subspace Z = [X, Y, P], in one
-// workgroup of 1024 threads:
+// A = Z^H H Z and S = Z^H Z of the current subspace Z = [X, Y, P], in three
+// launches on one stream:
+//   k_rr_reduce (one workgroup of 1024 threads; every step depends on the last)
 //   1. symmetric diagonal scaling D S D, D = diag(S)^-1/2;
 //   2. left-looking Cholesky D S D = L L^H; a column whose pivot falls below
 //      `drop_tol` (its direction is numerically inside the span of the
@@ -12,13 +13,15 @@
 //      skip the zero triangles;
 //   4. Householder reduction C = Q T Q^H to a real symmetric tridiagonal T,
 //      three workgroup barriers per reflector;
+//   k_rr_values (one small workgroup per wanted eigenvalue)
 //   5. the wanted eigenvalues of T by multisection on Sturm counts: those
 //      below floor_val (the mid-gap -c^2: negative-band Ritz values) are
 //      skipped;
+//   k_rr_vectors (one workgroup per cluster of (nearly) equal eigenvalues)
 //   6. their eigenvectors by inverse iteration, re-orthogonalised inside
-//      clusters of (nearly) equal eigenvalues such as Kramers pairs;
-//   7. back-transformation v = D Li^H Q y, each column of y held in the
-//      registers of a group of lanes while all reflectors are applied.
+//      the cluster (Kramers pairs, for one);
+//   7. back-transformation v = D Li^H Q y, each y held in the registers of a
+//      group of lanes while all reflectors are applied.
 // Triangular factors and the Hermitian working matrix are packed lower
 // triangles in LDS when n_Z <= 120, else full rows in the global scratch area.
 #include <algorithm>
@@ -200,13 +203,18 @@ __device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double 
       dot[p] = make_double2(0, 0);
       if (p * kRowsPass < m) {   // uniform
         const int ii = p * kRowsPass + rl;
-        double2 s = make_double2(0, 0);
+        double2 s = make_double2(0, 0), s1 = make_double2(0, 0);
         if (ii < m) {
           const int i = j + ii;
-#pragma unroll 4
-          for (int k = g; k < j; k += kRowG) s = zfma(M.lo(i, k), zconj(M.lo(j, k)), s);
+          int k = g;
+#pragma unroll 2
+          for (; k + kRowG < j; k += 2 * kRowG) {   // two chains in flight
+            s = zfma(M.lo(i, k), zconj(M.lo(j, k)), s);
+            s1 = zfma(M.lo(i, k + kRowG), zconj(M.lo(j, k + kRowG)), s1);
+          }
+          if (k < j) s = zfma(M.lo(i, k), zconj(M.lo(j, k)), s);
         }
-        dot[p] = gsum2<kRowG>(s);
+        dot[p] = gsum2<kRowG>(zadd(s, s1));
       }
     }
     if (tid == 0) sc[0] = M.lo(j, j).x - dot[0].x;
@@ -247,13 +255,17 @@ __device__ void trtri_lower(const Mat M, int n) {
       y[p] = make_double2(0, 0);
       if (p * kRowsPass < m) {   // uniform
         const int ii = p * kRowsPass + rl;
-        double2 s = make_double2(0, 0);
+        double2 s = make_double2(0, 0), s1 = make_double2(0, 0);
         if (ii < m) {
-#pragma unroll 4
-          for (int k = g; k <= ii; k += kRowG)
+          int k = g;
+#pragma unroll 2
+          for (; k + kRowG <= ii; k += 2 * kRowG) {   // two chains in flight
             s = zfma(M.lo(j + 1 + ii, j + 1 + k), M.lo(j + 1 + k, j), s);
+            s1 = zfma(M.lo(j + 1 + ii, j + 1 + k + kRowG), M.lo(j + 1 + k + kRowG, j), s1);
+          }
+          if (k <= ii) s = zfma(M.lo(j + 1 + ii, j + 1 + k), M.lo(j + 1 + k, j), s);
         }
-        y[p] = gsum2<kRowG>(s);
+        y[p] = gsum2<kRowG>(zadd(s, s1));
       }
     }
     __syncthreads();   // column j and its diagonal are read everywhere
@@ -299,49 +311,63 @@ __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
   }
   for (int k = 0; k + 1 < r; ++k) {
     const int m = r - k - 1;   // trailing size, rows/cols k+1..r-1
-    // (a) reflector; identical arithmetic on every thread
-    double xn2 = 0;
+    // (a) reflector, by wave 0 alone (the other waves would only repeat the
+    // same scalar arithmetic); tau reaches them through LDS
+    if (wid == 0) {
+      double xn2 = 0;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) xn2 += w.nred[q];
-    const double2 alpha = M.lo(k + 1, k);
-    double2 tau = make_double2(0, 0), scal = make_double2(0, 0);
-    double beta = alpha.x;
-    if (!(xn2 == 0.0 && alpha.y == 0.0)) {
-      const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
-      beta = (alpha.x >= 0) ? -nrm : nrm;
-      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-      const double2 den = make_double2(alpha.x - beta, alpha.y);
-      const double dn = den.x * den.x + den.y * den.y;
-      scal = make_double2(den.x / dn, -den.y / dn);
-    }
-    if (tid == 0) {
-      w.tauv[k] = tau;
-      w.ee[k] = beta;
-      w.dd[k] = M.lo(k, k).x;
-    }
-    for (int i = tid; i < m; i += nt) {
-      const double2 v = (i == 0) ? make_double2(1, 0) : zmul(M.lo(k + 1 + i, k), scal);
-      w.vv[i] = v;
-      if (i > 0) M.set(k + 1 + i, k, v);
+      for (int q = 0; q < NW; ++q) xn2 += w.nred[q];
+      const double2 alpha = M.lo(k + 1, k);
+      double2 tau = make_double2(0, 0), scal = make_double2(0, 0);
+      double beta = alpha.x;
+      if (!(xn2 == 0.0 && alpha.y == 0.0)) {
+        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+        beta = (alpha.x >= 0) ? -nrm : nrm;
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 den = make_double2(alpha.x - beta, alpha.y);
+        const double dn = den.x * den.x + den.y * den.y;
+        scal = make_double2(den.x / dn, -den.y / dn);
+      }
+      if (lane == 0) {
+        w.tauv[k] = tau;
+        w.ee[k] = beta;
+        w.dd[k] = M.lo(k, k).x;
+      }
+      for (int i = lane; i < m; i += 64) {
+        const double2 v = (i == 0) ? make_double2(1, 0) : zmul(M.lo(k + 1 + i, k), scal);
+        w.vv[i] = v;
+        if (i > 0) M.set(k + 1 + i, k, v);
+      }
     }
     __syncthreads();
+    const double2 tau = w.tauv[k];
     // (b) x = tau C22 v, C22 Hermitian from its lower triangle
     double qp = 0;
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
       if (p * kRowsPass < m) {   // uniform
         const int ii = p * kRowsPass + rl;
-        double2 s = make_double2(0, 0);
+        double2 s = make_double2(0, 0), s1 = make_double2(0, 0);
         if (ii < m) {
           const int gi = k + 1 + ii;
-#pragma unroll 4
-          for (int jj = g; jj < m; jj += kRowG) {
+          // one load from a selected address (a select between two loads
+          // would become a branch around each of them)
+          auto elem = [&](int jj) {
             const int gj = k + 1 + jj;
-            const double2 c = (jj <= ii) ? M.lo(gi, gj) : zconj(M.lo(gj, gi));
-            s = zfma(c, w.vv[jj], s);
+            const bool low = jj <= ii;
+            double2 c = M.lo(low ? gi : gj, low ? gj : gi);
+            if (!low) c.y = -c.y;
+            return c;
+          };
+          int jj = g;
+#pragma unroll 2
+          for (; jj + kRowG < m; jj += 2 * kRowG) {   // two chains in flight
+            s = zfma(elem(jj), w.vv[jj], s);
+            s1 = zfma(elem(jj + kRowG), w.vv[jj + kRowG], s1);
           }
+          if (jj < m) s = zfma(elem(jj), w.vv[jj], s);
         }
-        s = gsum2<kRowG>(s);
+        s = gsum2<kRowG>(zadd(s, s1));
         if (ii < m && g == 0) {
           w.xv[ii] = zmul(tau, s);
           const double2 vi = w.vv[ii];
@@ -604,11 +630,49 @@ __device__ void orthonormalise_cluster(int r, int t, int tend, double *__restric
   }
 }
 
-__global__ void __launch_bounds__(kRRThreads) k_rayleigh_ritz(
+// Global scratch of one Rayleigh-Ritz (n_Z = nz, nkeep wanted pairs): the
+// reduction's working matrices and what the three kernels hand on.
+struct RRScratch {
+  double2 *Sg;     // scaled S lower triangle (full-row path)
+  double2 *Am;     // scaled A (full)
+  double2 *Lc;     // L^-1 column-major: Lc[c r + b] = Li[b][c]
+  double2 *Mm;     // A_r Li^H; compaction buffer; C and its reflectors (full-row path)
+  double2 *Cg;     // C = Li A_r Li^H, lower tiles
+  double2 *refl;   // packed reflectors (packed path)
+  double2 *tau;    // reflector scalars
+  double *U;       // nkeep real eigenvectors of T, r each
+  double *dd, *ee, *dsc, *lam;
+  int *kept;
+  __host__ __device__ static size_t bytes(int nz, int nkeep) {
+    const size_t nn = (size_t)nz * nz;
+    return sizeof(double2) * (5 * nn + (size_t)nz * (nz + 1) / 2 + nz) +
+           sizeof(double) * ((size_t)nkeep * nz + 3 * (size_t)nz + nkeep + 1) + sizeof(int) * nz;
+  }
+  __host__ __device__ static RRScratch at(void *base, int nz, int nkeep) {
+    const size_t nn = (size_t)nz * nz;
+    RRScratch w;
+    w.Sg = static_cast<double2 *>(base);
+    w.Am = w.Sg + nn;
+    w.Lc = w.Am + nn;
+    w.Mm = w.Lc + nn;
+    w.Cg = w.Mm + nn;
+    w.refl = w.Cg + nn;
+    w.tau = w.refl + (size_t)nz * (nz + 1) / 2;
+    w.U = reinterpret_cast<double *>(w.tau + nz);
+    w.dd = w.U + (size_t)nkeep * nz;
+    w.ee = w.dd + nz;
+    w.dsc = w.ee + nz;
+    w.lam = w.dsc + nz;
+    w.kept = reinterpret_cast<int *>(w.lam + nkeep + 1);
+    return w;
+  }
+};
+
+// ---- 1-4 in one workgroup: scaling, Cholesky, L^-1, C, tridiagonal T
+__global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     const double2 *__restrict__ Ain, const double2 *__restrict__ Sin, int nz, int nkeep,
-    double drop_tol, double floor_val, const int *__restrict__ forced, double2 *__restrict__ Vout,
-    double *__restrict__ theta, int *__restrict__ info, double *__restrict__ dinfo,
-    double2 *__restrict__ ws, long long *__restrict__ tstamp) {
+    double drop_tol, const int *__restrict__ forced, int *__restrict__ info, RRScratch W,
+    long long *__restrict__ tstamp) {
   // no static LDS in this kernel: the dynamic arena then starts at offset 0,
   // 16-byte aligned, as the double2 accesses (ds_read_b128) need for speed
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -636,19 +700,10 @@ __global__ void __launch_bounds__(kRRThreads) k_rayleigh_ritz(
   double2 *ta = big, *tb = big + kGT * kGK;
   int &s_r = reinterpret_cast<int *>(red)[0];
   int &s_flag = reinterpret_cast<int *>(red)[1];
-  int &s_k0 = reinterpret_cast<int *>(red)[2];
-  double &s_lmin = red[2];
 
   const int tid = threadIdx.x, nt = blockDim.x;
   const size_t nn = (size_t)nz * nz;
-  double2 *Sg = ws;              // scaled S lower triangle (global path)
-  double2 *Am = Sg + nn;         // scaled A (full)
-  double2 *Lc = Am + nn;         // L^-1 column-major: Lc[c r + b] = Li[b][c]
-  double2 *Mm = Lc + nn;         // A_r Li^H; compaction buffer; C (global path)
-  double2 *Cg = Mm + nn;         // C = Li A_r Li^H, lower tiles
-  double2 *Uc = Cg + nn;         // r x nkeep complex eigenvectors
-  double *U = reinterpret_cast<double *>(Uc + (size_t)nz * nkeep);   // nkeep x r real, per vector
-  double *lu = U + (size_t)nz * nkeep;                                // 5 r per cluster leader
+  double2 *Sg = W.Sg, *Am = W.Am, *Lc = W.Lc, *Mm = W.Mm, *Cg = W.Cg;
   const bool packed = (nz <= kRRPackedMax);
 
   // ---- 1. scaling and Hermitian parts
@@ -755,144 +810,368 @@ __global__ void __launch_bounds__(kRRThreads) k_rayleigh_ritz(
     TriWork tw{dd, ee, tauv, vv, xv, red + 32, red + 48};
     if (packed) tridiagonalise(PackedLower{big}, r, tw); else tridiagonalise(FullLower{Mm, r}, r, tw);
   }
-  for (int i = tid; i + 1 < r; i += nt) e2[i] = ee[i] * ee[i];
-  __syncthreads();
-  DKS_RR_STAMP(5);
 
-  // ---- 5. multisection for the kept eigenvalues and the smallest one
+  // ---- hand-off to the eigenvalue and eigenvector kernels
+  for (int i = tid; i < r; i += nt) {
+    W.dd[i] = dd[i];
+    W.ee[i] = (i + 1 < r) ? ee[i] : 0.0;
+    W.tau[i] = (i + 1 < r) ? tauv[i] : make_double2(0, 0);
+    W.kept[i] = kept[i];
+  }
+  for (int i = tid; i < nz; i += nt) W.dsc[i] = dsc[i];
+  if (packed)
+    for (int e = tid; e < r * (r + 1) / 2; e += nt) W.refl[e] = big[e];
+  DKS_RR_STAMP(5);
+#undef DKS_RR_STAMP
+}
+
+// Sturm tolerances and the padded Gershgorin interval [glo, ghi] of T
+// (emax2 = the largest squared off-diagonal entry).
+struct SturmBounds {
+  double glo, ghi, tnorm, pivmin, atol;
+};
+__device__ SturmBounds sturm_bounds_of(double glo, double ghi, double emax2) {
+  SturmBounds b;
+  b.tnorm = fmax(fabs(glo), fabs(ghi));
+  b.pivmin = DBL_MIN * fmax(1.0, emax2);
+  b.atol = DBL_EPSILON * b.tnorm;
+  b.glo = glo - (2.0 * DBL_EPSILON * b.tnorm + 2 * b.pivmin);
+  b.ghi = ghi + (2.0 * DBL_EPSILON * b.tnorm + 2 * b.pivmin);
+  return b;
+}
+
+// ---- 5. one wanted eigenvalue of T per workgroup by multisection: target
+// t < nkeep is eigenvalue k0 + t (k0 = number below floor_val), target nkeep
+// the smallest.  Each round every thread takes a Sturm count at one of
+// blockDim.x interior points of the bracket [lo, hi) (count(lo) <= index <
+// count(hi)); the counts are monotone in the point, so the number of points
+// with count <= index locates the new bracket between two neighbouring points.
+// Small workgroups: a round is one Sturm recurrence long, and more points per
+// round would cost more than the rounds they save.
+constexpr int kValThreads = 128;   // Sturm points per round and target
+__global__ void __launch_bounds__(kValThreads) k_rr_values(
+    const double *__restrict__ g_dd, const double *__restrict__ g_ee, int nkeep, double floor_val,
+    int *__restrict__ info, double *__restrict__ lam, double *__restrict__ theta,
+    double *__restrict__ dinfo, long long *__restrict__ tstamp) {
+  __shared__ double dd[kRRMax], e2[kRRMax];
+  __shared__ double bred[3][kValThreads / 64];
+  __shared__ int cnt[2][kValThreads / 64];
+  __shared__ int s_k0;
+  if (info[1]) return;   // the Cholesky dropped too much: nothing to do
+  const int r = info[0];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
+  const bool stamp = tstamp && blockIdx.x == 0 && tid == 0;
+  if (stamp) tstamp[12] = wall_clock64();
+  for (int i = tid; i < r; i += nt) {
+    dd[i] = g_dd[i];
+    e2[i] = g_ee[i] * g_ee[i];
+  }
+  // Gershgorin interval, one row per thread, reduced over the workgroup
   double glo = 1e300, ghi = -1e300, emax2 = 0;
-#pragma unroll 8
+  for (int i = tid; i < r; i += nt) {
+    const double el = (i > 0) ? g_ee[i - 1] : 0.0, er = (i + 1 < r) ? g_ee[i] : 0.0;
+    const double off = fabs(el) + fabs(er);
+    const double di = g_dd[i];
+    glo = fmin(glo, di - off);
+    ghi = fmax(ghi, di + off);
+    emax2 = fmax(emax2, er * er);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    glo = fmin(glo, __shfl_xor(glo, o));
+    ghi = fmax(ghi, __shfl_xor(ghi, o));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o));
+  }
+  if (lane == 0) {
+    bred[0][wid] = glo;
+    bred[1][wid] = ghi;
+    bred[2][wid] = emax2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kValThreads / 64; ++q) {
+    glo = fmin(glo, bred[0][q]);
+    ghi = fmax(ghi, bred[1][q]);
+    emax2 = fmax(emax2, bred[2][q]);
+  }
+  const SturmBounds sb = sturm_bounds_of(glo, ghi, emax2);
+  if (tid == 0) {
+    const int k0 = (floor_val > sb.glo) ? sturm_count(dd, e2, r, floor_val, sb.pivmin) : 0;
+    s_k0 = k0;
+    if (blockIdx.x == 0) {
+      info[3] = k0;
+      if (r - k0 < nkeep) info[1] = 2;
+    }
+  }
+  __syncthreads();
+  const int k0 = s_k0;
+  if (r - k0 < nkeep) return;
+  if (stamp) tstamp[13] = wall_clock64();
+  const int t = blockIdx.x;
+  const int idx = (t < nkeep) ? k0 + t : 0;
+  const double inv_np1 = 1.0 / (double)(nt + 1);
+  double lo = sb.glo, hi = sb.ghi;
+  for (int round = 0; round < 64; ++round) {
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + sb.atol + sb.pivmin) break;
+    const double x = lo + (hi - lo) * ((double)(tid + 1) * inv_np1);
+    const int c = sturm_count(dd, e2, r, x, sb.pivmin);
+    const unsigned long long bal = __ballot(c <= idx);
+    if (lane == 0) cnt[round & 1][wid] = __popcll(bal);
+    __syncthreads();
+    int a = -1;   // index of the last point with count <= idx
+#pragma unroll
+    for (int q = 0; q < kValThreads / 64; ++q) a += cnt[round & 1][q];
+    const double nlo = (a >= 0) ? lo + (hi - lo) * ((double)(a + 1) * inv_np1) : lo;
+    const double nhi = (a + 1 < nt) ? lo + (hi - lo) * ((double)(a + 2) * inv_np1) : hi;
+    if (nhi > nlo && nhi - nlo < hi - lo) {
+      lo = nlo;
+      hi = nhi;
+    } else {
+      // no representable interior point left: the bracket has converged
+      lo = hi = 0.5 * (lo + hi);
+    }
+  }
+  if (tid == 0) {
+    const double v = 0.5 * (lo + hi);
+    if (t < nkeep) {
+      lam[t] = v;
+      theta[t] = v;
+    } else {
+      dinfo[0] = v;
+    }
+  }
+  if (stamp) tstamp[14] = wall_clock64();
+}
+
+// LDS of k_rr_vectors: inverse-iteration slots (x, LU factors, swaps), later
+// reused for the packed reflectors when n_Z <= kRRPackedMax.
+__host__ __device__ inline size_t rr_slot_bytes(int nz) {
+  return sizeof(double) * 5 * (size_t)nz + (((size_t)nz + 15) & ~(size_t)15);
+}
+constexpr int kRRSlots = kRRThreads / 64;
+constexpr int kUc = 16;   // eigenvectors back-transformed per pass (LDS copies)
+constexpr size_t kRRVecLds = 144 * 1024;
+__host__ __device__ inline int rr_slots(int nz) {
+  const size_t fixed = sizeof(double) * 2 * (size_t)nz + sizeof(int) * (size_t)nz + 256;
+  const size_t s = (kRRVecLds - fixed) / rr_slot_bytes(nz);
+  return s < 1 ? 1 : (s > (size_t)kRRSlots ? kRRSlots : (int)s);
+}
+
+// sum over the workgroup (every thread gets it); red holds kRRThreads / 64 doubles
+__device__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0;
+#pragma unroll
+  for (int q = 0; q < kRRThreads / 64; ++q) s += red[q];
+  return s;
+}
+
+// Back-transformation of one eigenvector by a group of G lanes: u = Q x (x
+// real, length r), Q = H_0 ... H_{r-2} with reflector k in column k of M below
+// the subdiagonal; lane l of the group holds rows l + G s.  u goes to out.
+template <int G, int NPL, typename Mat>
+__device__ void bt_group(const Mat M, int r, const double2 *tauv, const double *x, double2 *out) {
+  const int gl = threadIdx.x % G;
+  double2 u[NPL];
+#pragma unroll
+  for (int s = 0; s < NPL; ++s) {
+    const int i = gl + G * s;
+    u[s] = (i < r) ? make_double2(x[i], 0.0) : make_double2(0, 0);
+  }
+  for (int k = r - 2; k >= 0; --k) {
+    const double2 tau = tauv[k];
+    if (tau.x == 0.0 && tau.y == 0.0) continue;   // uniform
+    // every lane loads (rows outside k+2..r-1 read row k+1 and are masked
+    // after): conditional loads would be serialised behind branches
+    double2 v[NPL];
+    double2 acc = make_double2(0, 0);
+#pragma unroll
+    for (int s = 0; s < NPL; ++s) {
+      const int i = gl + G * s;
+      const bool on = i > k && i < r;
+      const double2 m = M.lo(on ? i : k + 1, k);
+      v[s] = on ? (i == k + 1 ? make_double2(1, 0) : m) : make_double2(0, 0);
+      acc = zadd(acc, zcmul(v[s], u[s]));
+    }
+    acc = zmul(tau, gsum2<G>(acc));
+#pragma unroll
+    for (int s = 0; s < NPL; ++s) u[s] = zsub(u[s], zmul(v[s], acc));
+  }
+#pragma unroll
+  for (int s = 0; s < NPL; ++s) {
+    const int i = gl + G * s;
+    if (i < r) out[i] = u[s];
+  }
+}
+
+// V = D Li^H Uc for nc vectors held in LDS (uc[c r + a]): row kept[i] of
+// column j0 + c gets d_i sum_{a >= i} conj(Li[a][i]) Uc_c[a], Lc[i r + a] =
+// Li[a][i].  One wave per row, lane l takes a = l + 64 s.
+template <int NPL>
+__device__ void li_rows(const double2 *__restrict__ Lc, int r, const int *kept, const double *dsc,
+                        const double2 *uc, int nc, double2 *__restrict__ V, int ldv, int j0) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = wid; i < r; i += kRRThreads / 64) {
+    double2 l[NPL];
+#pragma unroll
+    for (int s = 0; s < NPL; ++s) {
+      const int a = lane + 64 * s;
+      l[s] = (a >= i && a < r) ? Lc[(size_t)i * r + a] : make_double2(0, 0);
+    }
+    const int ki = kept[i];
+    const double d = dsc[ki];
+    for (int c = 0; c < nc; ++c) {
+      double2 acc = make_double2(0, 0);
+#pragma unroll
+      for (int s = 0; s < NPL; ++s) {
+        const int a = lane + 64 * s;
+        if (a < r) acc = zadd(acc, zcmul(l[s], uc[(size_t)c * r + a]));
+      }
+      acc = gsum2<64>(acc);
+      if (lane == 0) V[(size_t)ki * ldv + j0 + c] = zscale(acc, d);
+    }
+  }
+}
+
+// ---- 6-7. eigenvectors, one cluster of (nearly) equal eigenvalues per
+// workgroup (the workgroup of the cluster's first member; the others exit):
+// inverse iteration with the shifts spread by 10 ulp(T), one vector per wave
+// with its LU factors in LDS; modified Gram-Schmidt (two passes) inside the
+// cluster; then each wave back-transforms one vector, v = D Li^H Q x.
+// kSmall: n_Z <= 128, so r <= 128 (register columns of 8 rows per 16-lane
+// group); the general form keeps 8 rows per lane of a wave.
+template <bool kSmall>
+__global__ void __launch_bounds__(kRRThreads) k_rr_vectors(
+    const double *__restrict__ g_dd, const double *__restrict__ g_ee,
+    const double2 *__restrict__ g_tau, const double2 *__restrict__ g_refl,
+    const double2 *__restrict__ Mfull, const double2 *__restrict__ Lc, const int *__restrict__ g_kept,
+    const double *__restrict__ g_dsc, const double *__restrict__ lam, const int *__restrict__ info,
+    int nz, int nkeep, double *__restrict__ U, double2 *__restrict__ Vout,
+    long long *__restrict__ tstamp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (info[1]) return;
+  const int r = info[0];
+  const int t = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
+  const bool stamp = tstamp && t == 0 && tid == 0;
+  if (stamp) tstamp[16] = wall_clock64();
+  double *dd = reinterpret_cast<double *>(smem_raw);
+  double *ee = dd + nz;
+  int *kinv = reinterpret_cast<int *>(ee + nz);
+  double *red = reinterpret_cast<double *>(kinv + ((nz + 3) & ~3));   // 32
+  unsigned char *area = reinterpret_cast<unsigned char *>(red + 32);
+  for (int i = tid; i < r; i += nt) {
+    dd[i] = g_dd[i];
+    ee[i] = g_ee[i];
+  }
+  __syncthreads();
+  // the cluster tolerances, from T's Gershgorin bound (as the values kernel)
+  double tn = 0;
   for (int i = 0; i < r; ++i) {
     const double off = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < r ? fabs(ee[i]) : 0.0);
-    glo = fmin(glo, dd[i] - off);
-    ghi = fmax(ghi, dd[i] + off);
-    if (i + 1 < r) emax2 = fmax(emax2, e2[i]);
+    tn = fmax(tn, fmax(fabs(dd[i] - off), fabs(dd[i] + off)));
   }
-  const double tnorm = fmax(fabs(glo), fabs(ghi));
-  const double pivmin = DBL_MIN * fmax(1.0, emax2);
-  const double atol = DBL_EPSILON * tnorm;
-  glo -= 2.0 * DBL_EPSILON * tnorm + 2 * pivmin;
-  ghi += 2.0 * DBL_EPSILON * tnorm + 2 * pivmin;
-  if (tid == 0) {
-    const int k0 = (floor_val > glo) ? sturm_count(dd, e2, r, floor_val, pivmin) : 0;
-    s_k0 = k0;
-    info[3] = k0;
-    if (r - k0 < nkeep) {
-      s_flag = 2;
-      info[1] = 2;
+  const double ctol = 1e-7 * fmax(tn, 1e-300);
+  const double eps_t = DBL_EPSILON * fmax(tn, 1e-300);
+  if (t > 0 && lam[t] - lam[t - 1] <= ctol) return;   // not a cluster leader (uniform)
+  int tend = t + 1;
+  while (tend < nkeep && lam[tend] - lam[tend - 1] <= ctol) ++tend;
+  const int csz = tend - t;
+  if (stamp) tstamp[17] = wall_clock64();
+  // inverse iteration, nslot vectors at a time (lane 0 of waves 0..nslot-1)
+  const int nslot = rr_slots(nz);
+  const size_t sb = rr_slot_bytes(nz);
+  for (int q0 = 0; q0 < csz; q0 += nslot) {
+    const int q = q0 + wid;
+    unsigned char *slot = area + (size_t)wid * sb;
+    double *x = reinterpret_cast<double *>(slot);
+    double *f = x + nz;
+    unsigned char *sw = reinterpret_cast<unsigned char *>(f + 4 * nz);
+    if (wid < nslot && q < csz && lane == 0)
+      inverse_iteration(dd, ee, r, lam[t + q] + (double)q * 10.0 * eps_t, eps_t, t + q, x, f, sw);
+    __syncthreads();
+    for (int e = tid; e < nslot * r; e += nt) {
+      const int w = e / r, i = e - (e / r) * r;
+      if (q0 + w < csz)
+        U[(size_t)(t + q0 + w) * r + i] = reinterpret_cast<const double *>(area + (size_t)w * sb)[i];
+    }
+    __syncthreads();
+  }
+  if (stamp) tstamp[18] = wall_clock64();
+  // modified Gram-Schmidt inside the cluster, two passes, the whole workgroup
+  for (int jv = 1; jv < csz; ++jv) {
+    double *xv = U + (size_t)(t + jv) * r;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int jp = 0; jp < jv; ++jp) {
+        const double *yv = U + (size_t)(t + jp) * r;
+        double d = 0;
+        for (int i = tid; i < r; i += nt) d += yv[i] * xv[i];
+        d = block_sum(d, red);
+        for (int i = tid; i < r; i += nt) xv[i] -= d * yv[i];
+        __syncthreads();
+      }
+    double nn = 0;
+    for (int i = tid; i < r; i += nt) nn += xv[i] * xv[i];
+    nn = block_sum(nn, red);
+    const double inv = 1.0 / sqrt(nn);
+    for (int i = tid; i < r; i += nt) xv[i] *= inv;
+    __syncthreads();
+  }
+  if (stamp) tstamp[19] = wall_clock64();
+  // rows of V outside the kept set are zero
+  for (int i = tid; i < nz; i += nt) kinv[i] = -1;
+  __syncthreads();
+  for (int i = tid; i < r; i += nt) kinv[g_kept[i]] = i;
+  __syncthreads();
+  for (int e = tid; e < nz * csz; e += nt) {
+    const int row = e / csz, c = e - (e / csz) * csz;
+    if (kinv[row] < 0) Vout[(size_t)row * nkeep + t + c] = make_double2(0, 0);
+  }
+  // back-transformation and V = D Li^H Uc, kUc vectors at a time
+  const bool packed = nz <= kRRPackedMax;
+  double2 *tv = reinterpret_cast<double2 *>(area);
+  double2 *pk = tv + ((nz + 1) & ~1);
+  double2 *ucs = packed ? pk + (size_t)nz * (nz + 1) / 2 : reinterpret_cast<double2 *>(area);
+  if (packed) {
+    for (int i = tid; i < r; i += nt) tv[i] = g_tau[i];
+    const int tri = r * (r + 1) / 2;
+    for (int e0 = 0; e0 < tri; e0 += 8 * kRRThreads) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = g_refl[min(e0 + u * kRRThreads + tid, tri - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + u * kRRThreads + tid < tri) pk[e0 + u * kRRThreads + tid] = v[u];
     }
   }
   __syncthreads();
-  if (s_flag) return;
-  const int k0 = s_k0;
-  {
-    // target t < nkeep: eigenvalue k0 + t; t == nkeep: the smallest.  Each
-    // round, G threads per target count at NP interior points of its bracket
-    // [lo, hi) (count(lo) <= index < count(hi)) and the bracket shrinks to the
-    // pair of neighbouring points around the index.
-    const int ntar = nkeep + 1;
-    const int G = max(1, nt / ntar);
-    const int NP = G * kSturmPts;
-    double *los = reinterpret_cast<double *>(part);
-    double *his = los + ntar;
-    unsigned short *cnts = reinterpret_cast<unsigned short *>(his + ntar);
-    const double inv_np1 = 1.0 / (double)(NP + 1);
-    auto narrow = [&](double lo, double hi) {
-      return hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + atol + pivmin;
-    };
-    for (int t = tid; t < ntar; t += nt) {
-      los[t] = glo;
-      his[t] = ghi;
-    }
-    __syncthreads();
-    for (int round = 0; round < 64; ++round) {
-      for (int u = tid; u < ntar * G; u += nt) {
-        const int t = u / G, g = u - (u / G) * G;
-        const double lo = los[t], hi = his[t];
-        if (narrow(lo, hi)) continue;
-#pragma unroll
-        for (int p = 0; p < kSturmPts; ++p) {
-          const double x = lo + (hi - lo) * ((double)(g * kSturmPts + p + 1) * inv_np1);
-          cnts[t * NP + g * kSturmPts + p] = (unsigned short)sturm_count(dd, e2, r, x, pivmin);
-        }
+  if (stamp) tstamp[20] = wall_clock64();
+  const FullLower Mf{const_cast<double2 *>(Mfull), r};
+  for (int c0 = 0; c0 < csz; c0 += kUc) {
+    const int nc = min(kUc, csz - c0);
+    if constexpr (kSmall) {
+      // 16 lanes per vector, 8 rows each: DPP-only reductions
+      const int grp = tid / 16;
+      if (grp < nc) {
+        const double *xq = U + (size_t)(t + c0 + grp) * r;
+        if (packed) bt_group<16, 8>(PackedLower{pk}, r, tv, xq, ucs + (size_t)grp * r);
+        else bt_group<16, 8>(Mf, r, g_tau, xq, ucs + (size_t)grp * r);
       }
       __syncthreads();
-      int active = 0;
-      for (int t = tid; t < ntar; t += nt) {
-        const double lo = los[t], hi = his[t];
-        if (narrow(lo, hi)) continue;
-        const int idx = (t < nkeep) ? k0 + t : 0;
-        int a = -1, b = NP;   // count(point a) <= idx < count(point b)
-        while (b - a > 1) {
-          const int mid = (a + b) >> 1;
-          if ((int)cnts[t * NP + mid] <= idx) a = mid; else b = mid;
-        }
-        const double nlo = (a >= 0) ? lo + (hi - lo) * ((double)(a + 1) * inv_np1) : lo;
-        const double nhi = (b < NP) ? lo + (hi - lo) * ((double)(b + 1) * inv_np1) : hi;
-        if (nhi > nlo && nhi - nlo < hi - lo) {
-          los[t] = nlo;
-          his[t] = nhi;
-          active |= narrow(nlo, nhi) ? 0 : 1;
-        } else {
-          // no representable interior point left: the bracket has converged
-          const double mid = 0.5 * (lo + hi);
-          los[t] = mid;
-          his[t] = mid;
-        }
-      }
-      if (!__syncthreads_or(active)) break;
-    }
-    for (int t = tid; t < ntar; t += nt) {
-      const double v = 0.5 * (los[t] + his[t]);
-      if (t < nkeep) lam[t] = v; else s_lmin = v;
+      if (stamp && c0 == 0) tstamp[22] = wall_clock64();
+      li_rows<2>(Lc, r, g_kept, g_dsc, ucs, nc, Vout, nkeep, t + c0);
+    } else {
+      if (wid < nc)
+        bt_group<64, kRRMax / 64>(Mf, r, g_tau, U + (size_t)(t + c0 + wid) * r, ucs + (size_t)wid * r);
+      __syncthreads();
+      li_rows<kRRMax / 64>(Lc, r, g_kept, g_dsc, ucs, nc, Vout, nkeep, t + c0);
     }
     __syncthreads();
   }
-  DKS_RR_STAMP(6);
-
-  // ---- 6. inverse iteration, one thread per eigenvalue; within a cluster of
-  // close eigenvalues the shifts are spread by 10 ulp(T) and the vectors are
-  // orthonormalised afterwards
-  const double ctol = 1e-7 * fmax(tnorm, 1e-300);
-  const double eps_t = DBL_EPSILON * fmax(tnorm, 1e-300);
-  for (int t = tid; t < nkeep; t += nt) {
-    int t0 = t;
-    while (t0 > 0 && lam[t0] - lam[t0 - 1] <= ctol) --t0;
-    double *fb = lu + (size_t)t * 5 * r;
-    inverse_iteration(dd, ee, r, lam[t] + (double)(t - t0) * 10.0 * eps_t, eps_t, t,
-                      U + (size_t)t * r, fb, reinterpret_cast<unsigned char *>(fb + 4 * r));
-  }
-  __syncthreads();
-  for (int t = tid; t < nkeep; t += nt) {
-    if (t > 0 && lam[t] - lam[t - 1] <= ctol) continue;   // not a cluster leader
-    int tend = t + 1;
-    while (tend < nkeep && lam[tend] - lam[tend - 1] <= ctol) ++tend;
-    if (tend > t + 1) orthonormalise_cluster(r, t, tend, U);
-  }
-  __syncthreads();
-  DKS_RR_STAMP(7);
-
-  // ---- 7. back-transformation: Uc = Q U, then V = D Li^H Uc
-  if (packed) back_transform<16, 8>(PackedLower{big}, r, nkeep, tauv, U, Uc);
-  else back_transform<64, 8>(FullLower{Mm, r}, r, nkeep, tauv, U, Uc);
-  DKS_RR_STAMP(11);
-  for (int e = tid; e < nz * nkeep; e += nt) Vout[e] = make_double2(0, 0);
-  __syncthreads();
-  // Vout[kb][j] = d_kb sum_{a >= b} conj(Li[a][b]) Uc[a][j]
-  wg_gemm(
-      r, nkeep, r, [&](int i, int k) { return zconj(Lc[(size_t)i * r + k]); },
-      [&](int k, int j) { return Uc[(size_t)k * nkeep + j]; },
-      [&](int i, int j, double2 v) {
-        const int ki = kept[i];
-        Vout[(size_t)ki * nkeep + j] = zscale(v, dsc[ki]);
-      },
-      [&](int i0, int, int &kb, int &ke) { kb = i0; ke = r; },
-      [&](int, int) { return true; }, ta, tb);
-  for (int t = tid; t < nkeep; t += nt) theta[t] = lam[t];
-  if (tid == 0) dinfo[0] = s_lmin;
-  __syncthreads();
-  DKS_RR_STAMP(8);
-#undef DKS_RR_STAMP
+  if (stamp) tstamp[21] = wall_clock64();
 }
 
 // dynamic LDS of one launch with subspace dimension nz (layout of the kernel's arena)
@@ -906,32 +1185,53 @@ static size_t rr_lds_bytes(int nz) {
   return ((arrays + 15) & ~(size_t)15) + (packed > tiles ? packed : tiles);
 }
 
+// dynamic LDS of k_rr_vectors: dd, ee, kinv, red, then the slots or the
+// packed reflectors with their scalars
+static size_t rr_vec_lds_bytes(int nz) {
+  const size_t fixed = sizeof(double) * 2 * (size_t)nz + sizeof(int) * (size_t)((nz + 3) & ~3) +
+                       sizeof(double) * 32;
+  const size_t slots = (size_t)rr_slots(nz) * rr_slot_bytes(nz);
+  const size_t refl = nz <= kRRPackedMax ? sizeof(double2) * ((size_t)((nz + 1) & ~1) +
+                                                              (size_t)nz * (nz + 1) / 2)
+                                         : 0;
+  const size_t ucs = sizeof(double2) * (size_t)kUc * nz;
+  return fixed + std::max(slots, refl + ucs);
+}
+
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info,
                    double *dinfo, DevBuf &scratch, hipStream_t st, long long *tstamp) {
   DKS_REQUIRE(nz > 0 && nz <= kRRMax && nkeep > 0 && nkeep <= nz, DKS_EINVAL,
               "Rayleigh-Ritz size out of range (subspace dimension must be <= 512)");
-  // the multisection brackets and counts share the kRRThreads partial-sum area
-  DKS_REQUIRE(sizeof(double) * 2 * (nkeep + 1) +
-                      sizeof(unsigned short) * (size_t)kRRThreads * kSturmPts <=
-                  sizeof(double2) * kRRThreads,
-              DKS_EINVAL, "Rayleigh-Ritz: too many wanted pairs");
   // once per process, also when batch lanes arrive here together
   static std::once_flag attr;
   hipError_t attr_rc = hipSuccess;
   std::call_once(attr, [&] {
     const size_t mx = std::max(rr_lds_bytes(kRRPackedMax), rr_lds_bytes(kRRMax));
-    attr_rc = hipFuncSetAttribute((const void *)k_rayleigh_ritz,
+    attr_rc = hipFuncSetAttribute((const void *)k_rr_reduce,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)mx);
+    if (attr_rc == hipSuccess) {
+      size_t mv = 0;
+      for (int z = 1; z <= kRRMax; ++z) mv = std::max(mv, rr_vec_lds_bytes(z));
+      attr_rc = hipFuncSetAttribute((const void *)k_rr_vectors<true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mv);
+      if (attr_rc == hipSuccess)
+        attr_rc = hipFuncSetAttribute((const void *)k_rr_vectors<false>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)mv);
+    }
   });
   DKS_HIP(attr_rc);
-  const size_t lds = rr_lds_bytes(nz);
-  const size_t nn = (size_t)nz * nz;
-  const size_t bytes = sizeof(double2) * (5 * nn + (size_t)nz * nkeep) +
-                       sizeof(double) * (size_t)nz * nkeep * 6;
-  scratch.ensure(bytes);
-  DKS_LAUNCH("k_rayleigh_ritz", k_rayleigh_ritz, dim3(1), dim3(kRRThreads), lds, st, A, S, nz,
-             nkeep, drop_tol, floor_val, forced_drop, V, theta, info, dinfo, scratch.as<double2>(),
+  scratch.ensure(RRScratch::bytes(nz, nkeep));
+  const RRScratch W = RRScratch::at(scratch.p, nz, nkeep);
+  DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, A, S,
+             nz, nkeep, drop_tol, forced_drop, info, W, tstamp);
+  DKS_HIP(hipGetLastError());
+  DKS_LAUNCH("k_rr_values", k_rr_values, dim3(nkeep + 1), dim3(kValThreads), 0, st, W.dd, W.ee,
+             nkeep, floor_val, info, W.lam, theta, dinfo, tstamp);
+  DKS_HIP(hipGetLastError());
+  auto kvec = nz <= 128 ? k_rr_vectors<true> : k_rr_vectors<false>;
+  DKS_LAUNCH("k_rr_vectors", kvec, dim3(nkeep), dim3(kRRThreads), rr_vec_lds_bytes(nz), st,
+             W.dd, W.ee, W.tau, W.refl, W.Mm, W.Lc, W.kept, W.dsc, W.lam, info, nz, nkeep, W.U, V,
              tstamp);
   DKS_HIP(hipGetLastError());
 }
