@@ -237,7 +237,13 @@ def main():
     if not args.no_solve and not args.no_batch:
         systems = sysgen.uneven_batch(seed=0, count=16)
         bb = dk.init_basis(systems)
-        ns = [s_.n_bands for s_ in systems]
+        # wanted bands per system from the generator, plus kBuf buffer columns
+        # (n_buffer: iterated, not required to converge; one value for the whole
+        # batch call), the usual LOBPCG practice for spectra whose wanted count
+        # falls inside a close group
+        kbuf = 8
+        wanted = [s_.n_bands for s_ in systems]
+        ns = [w_ + kbuf for w_ in wanted]
         sizes = [dk.basis_info(bb, i, miller=False)[0] for i in range(len(systems))]
 
         def blocks():
@@ -248,9 +254,9 @@ def main():
                 X0_[:, :2] = sysgen.start_block(mil_, s_.lattice, s_.kpts[0], n_, 100 + i)
                 Xs.append(torch.from_numpy(X0_).to(dev))
             return Xs
-        batch = {"systems": len(systems), "npw": sizes, "bands": ns}
+        batch = {"systems": len(systems), "npw": sizes, "bands": wanted, "buffer_columns": kbuf}
         for tag, mode in (("fp64", dk.MODE_FP64), ("mixed_fp32", dk.MODE_MIXED_FP32)):
-            o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1)
+            o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=kbuf)
             Xs = blocks()
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -260,7 +266,7 @@ def main():
             batch[f"{tag}_batch_converged"] = sum(int(i_["converged"]) for i_ in infos)
             log(f"[bench] batch of {len(systems)} uneven systems, {tag}: "
                 f"{batch[f'{tag}_batch_s']:.3f}s, {batch[f'{tag}_batch_converged']} converged")
-        o = dk.default_opts(mode=dk.MODE_FP64, tol=1e-8, n_iter=400, kinetic_balance=1)
+        o = dk.default_opts(mode=dk.MODE_FP64, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=kbuf)
         Xs = blocks()
         torch.cuda.synchronize()
         t = time.perf_counter()

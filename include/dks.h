@@ -148,6 +148,13 @@ typedef struct {
   double *iter_ms;      /* optional caller-owned host array of n_iter (+ mixed_iter in the
                            mixed modes) entries: wall time of each main-loop iteration in
                            ms, in execution order (each iteration ends with a stream sync) */
+  int n_buffer;         /* 0 <= n_buffer < n: the last n_buffer columns of the block are
+                           iterated with the rest but need not converge; convergence, the
+                           stagnation test and info.n_converged / max_resnorm cover the
+                           first n - n_buffer.  A block larger than the wanted count speeds
+                           up the wanted columns when a near-degenerate group straddles
+                           the wanted count (the rate of column i is set by the gap to
+                           eigenvalue n + 1, not i + 1).  Default 0 */
 } dks_solve_opts;
 
 typedef struct {

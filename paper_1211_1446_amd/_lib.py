@@ -46,7 +46,7 @@ class SolveOpts(ct.Structure):
                 ("n_iter", ct.c_int), ("tol", ct.c_double), ("mode", ct.c_int),
                 ("mixed_tol", ct.c_double), ("mixed_iter", ct.c_int),
                 ("kinetic_balance", ct.c_int), ("use_filter", ct.c_int),
-                ("iter_ms", ct.POINTER(ct.c_double))]
+                ("iter_ms", ct.POINTER(ct.c_double)), ("n_buffer", ct.c_int)]
 
 
 class SolveInfo(ct.Structure):

@@ -30,6 +30,7 @@ template <typename T> struct Blocks {
   int n = 0;
   int64_t K = 0;
   DevBuf Z[2], HZ[2], R, W;
+  DevBuf snap;   // best X of a stage that met an ill-conditioned basis (lazily allocated)
   void ensure(int n_, int64_t K_) {
     size_t rowb = sizeof(cplx<T>) * (size_t)K_;
     for (int i = 0; i < 2; ++i) {
@@ -139,6 +140,7 @@ static double active_level(const std::vector<double> &r, double tol, int &nact) 
 }
 
 constexpr int kStallFp64 = 20;     // iterations without a new best residual before stopping
+constexpr int kMaxRollbacks = 8;   // discarded broken-down steps before a stage gives up
 constexpr int kStallFp32 = 4;
 constexpr int kPolishFilters = 2;  // filter applications on the block entering the FP64 polish
 // MIXED_BF16GRAM: BF16-input Gram products while the median residual exceeds
@@ -156,6 +158,7 @@ template <typename T> struct LoopState {
   std::vector<double> lam, res;
   bool converged = false;
   int iters = 0;
+  int dropped = 0;   // directions the last Rayleigh-Ritz removed as dependent
 };
 
 // Rayleigh-Ritz on Z_cur rows described by (n, m, mp); returns false when
@@ -222,6 +225,7 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
                    "\"status\": %d, \"min_ritz\": %.12g}\n",
                    (int)sizeof(T), nz, n, s.m, mp, info[0], info[1], dinfo[0]);
     if (info[1] == 0) {
+      s.dropped = info[2];
       if (x.info) {
         x.info->basis_drops += info[2];
         x.info->neg_ritz_discarded += info[3];
@@ -273,9 +277,12 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
   for (int j = 0; j < n; ++j)
     if (!(s.res[j] < tol)) act.push_back(j);
   const int mnew = (int)act.size();
-  if (mnew == 0) {
-    s.converged = true;
-  } else if (s.m + s.mp > 0) {
+  // converged once the wanted columns are (the buffer columns stay active)
+  const int nwant = n - x.o->n_buffer;
+  s.converged = true;
+  for (int j = 0; j < nwant; ++j)
+    if (!(s.res[j] < tol)) s.converged = false;
+  if (mnew > 0 && s.m + s.mp > 0) {
     // conjugate directions P = [0, Y, P] V[:, act] (Algorithm 1), HP alike
     const int nyp = s.m + s.mp;
     std::vector<double2> vp((size_t)nyp * mnew);
@@ -318,8 +325,53 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     throw Error{DKS_ECHOL, "the start block is numerically rank deficient"};
   update<T>(x, bk, s, n, hV, tol);
   int best_nact = 0;
-  double best = active_level(s.res, tol, best_nact);
+  double best =
+      active_level(std::vector<double>(s.res.begin(), s.res.begin() + (n - x.o->n_buffer)), tol, best_nact);
   int stall = 0;
+  int rollbacks = 0;
+  // Restart from the current X after a discarded step: the filter, applied
+  // twice, removes the negative-band content the broken-down step let in (each
+  // pass damps it by ~(w/2c^2)^2, as for the block entering the FP64 polish);
+  // then H X is formed anew and the Rayleigh-Ritz runs on X alone (no Y, P).
+  auto restart = [&]() {
+    if (filt)
+      for (int k = 0; k < kPolishFilters; ++k)
+        filter_inplace<T>(x, bk.z(s.cur, 0), bk.W.template as<cplx<T>>(), n);
+    apply_h<T>(x.b, x.sys, bk.z(s.cur, 0), bk.hz(s.cur, 0), n, 0.0, 1.0, x.st, x.sv->ws);
+    if (x.info) {
+      x.info->h_applies += n;
+      x.info->p_restarts += 1;
+    }
+    s.m = 0;
+    s.mp = 0;
+    if (!ritz<T>(x, bk, s, n, drop_tol, hV))
+      throw Error{DKS_ECHOL, "the restarted block is numerically rank deficient"};
+    update<T>(x, bk, s, n, hV, tol);
+  };
+  // Once the basis has turned ill-conditioned (a dropped direction or a
+  // discarded step) the iteration can degrade gradually; from then on the best
+  // X so far (largest wanted residual) is kept and returned if the last is worse.
+  const int nwant = n - x.o->n_buffer;
+  auto wanted_max = [&]() {
+    double mx = 0;
+    for (int j = 0; j < nwant; ++j) mx = std::max(mx, s.res[j]);
+    return mx;
+  };
+  bool risky = false, snap_ok = false;
+  double snap_mx = std::numeric_limits<double>::infinity();
+  std::vector<double> snap_lam, snap_res;
+  auto keep_best = [&]() {
+    risky = risky || s.dropped > 0 || rollbacks > 0;
+    const double mx = wanted_max();
+    if (!risky || !(mx < snap_mx)) return;
+    bk.snap.ensure(sizeof(cplx<T>) * (size_t)bk.K * n);
+    DKS_HIP(hipMemcpyAsync(bk.snap.p, bk.z(s.cur, 0), sizeof(cplx<T>) * (size_t)bk.K * n,
+                           hipMemcpyDeviceToDevice, x.st));
+    snap_ok = true;
+    snap_mx = mx;
+    snap_lam = s.lam;
+    snap_res = s.res;
+  };
   // main loop
   while (!s.converged && s.iters < max_iter) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -335,10 +387,56 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st, x.sv->ws);
     if (x.info) x.info->h_applies += m;
     // Rayleigh-Ritz on Z = [X, Y, P]
+    const std::vector<double> lam_prev = s.lam;
     if (!ritz<T>(x, bk, s, n, drop_tol, hV))
       throw Error{DKS_ECHOL, "Rayleigh-Ritz lost the X block"};
+    // Breakdown guard.  span Z contains span X, so no Ritz value can lie
+    // below its predecessor by more than the block residual allows (Weyl:
+    // the i-th eigenvalue of H is within |R|_2 <= |R|_F of the i-th Ritz
+    // value of X).  A larger fall means the projected pencil is no longer a
+    // compression of H: the recurrences for HX and HP have drifted in an
+    // ill-conditioned basis.  The step is then discarded (X is still that of
+    // the previous step) and the iteration restarts from X.
+    {
+      double rf = 0;
+      for (double r : s.res) rf += r * r;
+      rf = std::sqrt(rf);
+      bool broke = false;
+      for (int j = 0; j < n; ++j)
+        if (s.lam[j] < lam_prev[j] - (10.0 * rf + 1e-9 * std::fabs(lam_prev[j]))) broke = true;
+      if (broke) {
+        s.lam = lam_prev;
+        if (++rollbacks > kMaxRollbacks) break;   // keep the last good state
+        restart();
+        continue;
+      }
+    }
     // new X, residuals, soft locking, new P
+    keep_best();   // the state this step starts from (its X survives in Z[cur])
+    const std::vector<double> res_prev = s.res;
+    const std::vector<int> act_prev = s.act;
+    const int m_prev = s.m, cur_prev = s.cur;
     update<T>(x, bk, s, n, hV, tol);
+    {
+      // the same guard on the residuals: a jump by three orders of magnitude
+      // in one step is the same breakdown seen from the vectors.  The previous
+      // X is still in Z[cur_prev].
+      double mx_prev = 0, mx = 0;
+      for (double r : res_prev) mx_prev = std::max(mx_prev, r);
+      for (double r : s.res) mx = std::max(mx, r);
+      if (!(mx <= 1e3 * mx_prev)) {
+        s.cur = cur_prev;
+        s.lam = lam_prev;
+        s.res = res_prev;
+        s.act = act_prev;
+        s.m = m_prev;
+        s.mp = 0;
+        s.converged = false;
+        if (++rollbacks > kMaxRollbacks) break;
+        restart();
+        continue;
+      }
+    }
     if (x.o->iter_ms && x.iter_slot < x.iter_cap)
       x.o->iter_ms[x.iter_slot++] =
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -350,7 +448,8 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     // (The worst residual is gap-limited and not monotone in the first
     // iterations; columns already converged no longer move the level.)
     int nact = 0;
-    const double level = active_level(s.res, tol, nact);
+    const double level =
+        active_level(std::vector<double>(s.res.begin(), s.res.begin() + (n - x.o->n_buffer)), tol, nact);
     if (nact < best_nact) {
       best_nact = nact;
       best = level;
@@ -361,6 +460,13 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     } else if (stall_window > 0 && ++stall >= stall_window) {
       break;
     }
+  }
+  keep_best();
+  if (snap_ok && !s.converged && wanted_max() > snap_mx) {
+    DKS_HIP(hipMemcpyAsync(bk.z(s.cur, 0), bk.snap.p, sizeof(cplx<T>) * (size_t)bk.K * n,
+                           hipMemcpyDeviceToDevice, x.st));
+    s.lam = snap_lam;
+    s.res = snap_res;
   }
   return s.converged ? DKS_OK : DKS_WNOTCONV;
 }
@@ -376,6 +482,7 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
                 "n must be in [1, min(170, 4N)] (subspace dimension 3n <= 512)");
     DKS_REQUIRE(o.n_init >= 0 && o.n_iter >= 0 && o.tol > 0, DKS_EINVAL, "bad options");
     DKS_REQUIRE(o.mode >= 0 && o.mode <= 2, DKS_EINVAL, "bad mode");
+    DKS_REQUIRE(o.n_buffer >= 0 && o.n_buffer < n, DKS_EINVAL, "n_buffer must be in [0, n)");
     dks_solve_info inf{};
     inf.min_ritz = std::numeric_limits<double>::infinity();
     Ctx x;
@@ -432,12 +539,14 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
     for (int j = 0; j < n; ++j) lambda[j] = s64.lam[j];
     double mx = 0;
     int nconv = 0;
+    const int nwant = n - o.n_buffer;
     for (int j = 0; j < n; ++j) {
       if (resnorms) resnorms[j] = s64.res[j];
+      if (j >= nwant) continue;
       mx = std::max(mx, s64.res[j]);
       if (s64.res[j] < o.tol) ++nconv;
     }
-    inf.converged = (nconv == n);
+    inf.converged = (nconv == nwant);
     inf.n_converged = nconv;
     inf.max_resnorm = mx;
     if (info) *info = inf;
@@ -477,6 +586,7 @@ void dks_default_opts(dks_solve_opts *o) {
   o->mixed_iter = 200;
   o->kinetic_balance = 0;
   o->use_filter = 1;
+  o->n_buffer = 0;
 }
 
 dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb, dks_prec prec,

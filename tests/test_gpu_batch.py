@@ -102,3 +102,41 @@ def test_batch_errors_are_per_item(dev):
     b.close()
     assert e.value.code == -1
     assert "batch item 1" in str(e.value)
+
+
+@pytest.mark.parametrize("mode,buf", [(0, 0), (0, 7), (1, 7)])
+def test_close_gap_system_buffer_and_guard(dev, mode, buf):
+    """System 15 of the 16-system uneven batch (N = 1839): eigenvalue 41 lies
+    2e-3 Ha above eigenvalue 40.  Without a buffer the wanted block converges
+    slowly and its basis turns ill-conditioned; the breakdown guard must keep
+    the result a Rayleigh-Ritz approximation (every value above the dense one
+    up to rounding, residuals bounded).  With 7 buffer columns the 40 wanted pairs
+    converge to the dense eigenvalues (tests/golden, dense oracle)."""
+    import json
+    import os
+    import torch
+    dk = _dk()
+    ref = np.array(json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                               "uneven_batch_seed0_sys15.json")))["eigenvalues"])
+    s = sysgen.uneven_batch(seed=0, count=16)[15]
+    n = s.n_bands
+    nb = n + buf
+    b = dk.init_basis([s])
+    N, _, mil = dk.basis_info(b, 0)
+    X0 = np.zeros((nb, 4, N), dtype=np.complex128)
+    X0[:, :2] = sysgen.start_block(mil, s.lattice, s.kpts[0], nb, 115)
+    X = torch.from_numpy(X0).to(dev)
+    o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=buf)
+    print(f"[close-gap system] mode={mode} n={n} buffer={buf} N={N}", flush=True)
+    lam, res, info, rc = dk.lobpcgf_solve(b, 0, nb, X, o)
+    b.close()
+    lam = np.asarray(lam)
+    # Rayleigh-Ritz values bound the eigenvalues from above, up to the rounding
+    # of an ill-conditioned basis (~1e-7 here); broken-down steps fall far below
+    assert np.all(lam[:n] > ref[:n] - 1e-6), (lam[:n] - ref[:n]).min()
+    if buf == 0:
+        assert info["max_resnorm"] < 1e-1, info
+        assert info["min_ritz"] > -2.01 * s.c ** 2, info
+    else:
+        assert rc == 0 and info["converged"] == 1, info
+        assert np.max(np.abs(lam[:n] - ref[:n])) < 1e-8, np.abs(lam[:n] - ref[:n]).max()

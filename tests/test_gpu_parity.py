@@ -192,6 +192,32 @@ def test_lobpcgf_tiny_dimer_matches_dense(dev, mode):
         assert info["iters_reduced"] > 0
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_lobpcgf_buffer_columns(dev, mode):
+    """A block of 10 with n_buffer = 2: the 8 wanted pairs converge to the dense
+    ones; convergence and the info fields cover only them."""
+    lam, res, info, rc, lam_ref, vec_ref, Xo, s = _solve_tiny(dev, mode, n=10, n_buffer=2)
+    assert rc == 0, info
+    assert info["converged"] == 1 and info["n_converged"] == 8, info
+    assert np.max(np.abs(lam[:8] - lam_ref[:8])) < 1e-8, (lam[:8] - lam_ref[:8])
+    assert np.all(res[:8] < 1e-8)
+    assert info["max_resnorm"] == pytest.approx(float(np.max(res[:8])))
+    assert cluster_projectors_match(lam_ref[:8], vec_ref[:, :8], Xo[:, :8]) < 1e-6
+
+
+def test_lobpcgf_buffer_out_of_range(dev):
+    dk = _dk()
+    s = sysgen.tiny_dimer(0)
+    b = dk.init_basis([s])
+    N, _, mil = dk.basis_info(b, 0)
+    X0 = np.zeros((4, 4, N), dtype=np.complex128)
+    X0[:, :2] = sysgen.start_block(mil, s.lattice, s.kpts[0], 4, 0)
+    Xd = torch.from_numpy(X0).to(dev)
+    with pytest.raises(Exception):
+        dk.lobpcgf_solve(b, 0, 4, Xd, dk.default_opts(n_buffer=4))
+    b.close()
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_reduced_precision_stage_alone(dev, mode):
     """The FP32 (mode 1) or BF16-Gram (mode 2) stage by itself, 40 iterations,
