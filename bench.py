@@ -31,7 +31,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3        # FP32 matrix (dense)
+BF16_PEAK_TFLOPS = 2500.0       # BF16 matrix (dense)
+
+
+def ip_pairs(nz, tile=64):
+    """(i, j) output pairs of the Hermitian Gram kernel: the 64 x 64 tiles on and
+    above the diagonal of an nz x nz product, clipped at nz."""
+    t = (nz + tile - 1) // tile
+    size = [min(tile, nz - a * tile) for a in range(t)]
+    return sum(size[a] * size[b] for a in range(t) for b in range(a, t))
 
 
 def log(*a):
@@ -198,6 +207,46 @@ def main():
         lam, res, info, rc = dk.lobpcgf_solve(b, 0, n, Xd, o, iter_ms=it_ms)
         return it_ms, info
 
+    # ---- matrix-core kernels of one full iteration (n_Z = 3n, every column active):
+    # per-launch times from two profiled runs (2 and 8 iterations) differenced, so
+    # that only full-size launches remain; algorithmic flops 8 per complex MAC
+    # (the FP32 Gram's three-product form does 6 real flops per MAC of useful work)
+    def profiled(mode, nit):
+        dk.profile_enable(True)
+        iterations(mode, nit)
+        rep_ = dk.profile_report()
+        dk.profile_enable(False)
+        return rep_
+    K4 = 4 * N
+    nz = 3 * n
+    nproj = sum(g.n_rad * (2 * g.l + 1) for g in s.proj)   # scalar projectors (B has nproj rows)
+    mk = {}
+    for mode, sfx, peak in ((dk.MODE_FP64, "f64", FP64_PEAK_TFLOPS),
+                            (dk.MODE_MIXED_FP32, "f32", FP32_PEAK_TFLOPS),
+                            (dk.MODE_MIXED_BF16GRAM, "bf16", BF16_PEAK_TFLOPS)):
+        a, c = profiled(mode, 2), profiled(mode, 8)
+        per_it = {
+            f"k_gemm_ip.gram.{sfx}": (1, 8.0 * 2 * ip_pairs(nz) * K4),
+            f"k_gemm_up.{sfx}": (4, 8.0 * K4 * n * (2 * nz + 2 * (2 * n)) / 4),
+            f"k_gemm_ip.{sfx}": (3, 8.0 * nproj * 4 * n * N),
+        }
+        for kname, spec in per_it.items():
+            if spec is None or kname not in c or kname not in a:
+                continue
+            launches, flops = spec
+            cnt = c[kname]["count"] - a[kname]["count"]
+            tot = c[kname]["total_ms"] - a[kname]["total_ms"]
+            if cnt <= 0 or tot <= 0:
+                continue
+            ms = tot / cnt
+            tf = flops / (ms * 1e-3) / 1e12
+            kp = peak if sfx != "bf16" or "gram" in kname else FP32_PEAK_TFLOPS
+            mk[kname] = {"avg_ms": ms, "launches_per_iteration": cnt / 6.0,
+                         "algorithmic_gflop_per_launch": flops / 1e9, "tflops": tf,
+                         "peak_tflops": kp, "frac": tf / kp}
+    log("[bench] matrix kernels: " + ", ".join(f"{k} {v['tflops']:.1f} TF/s ({100 * v['frac']:.0f} %)"
+                                              for k, v in mk.items()))
+
     it_ms, info64 = iterations(dk.MODE_FP64, W + K)
     step_ms = float(np.mean(it_ms[W:W + K]))
     log(f"[bench] FP64 LOBPCG-F iteration: {step_ms:.3f} ms (min {it_ms[W:W+K].min():.3f})")
@@ -324,6 +373,7 @@ def main():
         "time_to_solution_1e-8": tts,
         "batch_uneven": batch,
         "kernels_apply_H_fp64": kernels,
+        "matrix_kernels": mk,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

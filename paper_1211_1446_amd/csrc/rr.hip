@@ -280,10 +280,11 @@ __device__ void trtri_lower(const Mat M, int n) {
 }
 
 struct TriWork {
-  double *dd, *ee;      // diagonal (r), off-diagonal (r-1)
-  double2 *tauv;        // reflector scalars (r-1)
-  double2 *vv, *xv;     // reflector vector, tau C v (r)
-  double *nred, *qred;  // per-wave partial sums (16 each)
+  double *dd, *ee;       // diagonal (r), off-diagonal (r-1)
+  double2 *tauv;         // reflector scalars (r-1)
+  double2 *vv0, *vv1, *xv;   // reflector vectors (even, odd steps), tau C v (r)
+  __device__ double2 *vv(int k) const { return (k & 1) ? vv1 : vv0; }
+  double *nred, *qred;   // per-wave partial sums (16 each)
 };
 
 // Householder tridiagonalisation of the r x r Hermitian matrix held in M's lower
@@ -291,14 +292,51 @@ struct TriWork {
 // rows k+1..r-1; the column below the subdiagonal keeps v for the
 // back-transformation.  With x = tau C22 v and q = v^H C22 v (real), the
 // two-sided update is C22 -= v w^H + w v^H, w = x - |tau|^2 q v / 2.  Per
-// reflector: (a) every thread forms tau from the per-wave partial sums of the
-// column norm and v is written; (b) x by row groups, and q's per-wave partials;
-// (c) the rank-2 update by row groups, which also sums the next column's norm.
+// reflector, three barriers: (b) x by row groups of all waves, and q's per-wave
+// partials; (c1) the update of the trailing matrix's first column, which also
+// sums that column's norm; (c2) waves 1-15 update the rest while wave 0 forms
+// the next reflector from the finished column (look-ahead: its scalar
+// arithmetic and the writing of v no longer stand between two barriers).
+// Reflector vectors alternate between two LDS buffers, since wave 0 writes
+// v_{k+1} while the others still read v_k.
 template <typename Mat>
 __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
   constexpr int NW = kRRThreads / 64;
+  constexpr int kUpRows = (kRRThreads - 64) / kRowG;                  // rows per pass, waves 1-15
+  constexpr int kUpPasses = (kRRMax + kUpRows - 1) / kUpRows;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wid = tid >> 6, g = tid % kRowG, rl = tid / kRowG;
+  const int rlu = (tid - 64) / kRowG;   // row of waves 1-15 in the update
+  // reflector k from column k (its norm below the subdiagonal in w.nred), by
+  // wave 0: tau, beta and the diagonal entry to LDS, v into w.vv[k & 1] and M
+  auto reflector = [&](int k) {
+    const int m = r - k - 1;
+    double xn2 = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) xn2 += w.nred[q];
+    const double2 alpha = M.lo(k + 1, k);
+    double2 tau = make_double2(0, 0), scal = make_double2(0, 0);
+    double beta = alpha.x;
+    if (!(xn2 == 0.0 && alpha.y == 0.0)) {
+      const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+      beta = (alpha.x >= 0) ? -nrm : nrm;
+      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      const double2 den = make_double2(alpha.x - beta, alpha.y);
+      const double dn = den.x * den.x + den.y * den.y;
+      scal = make_double2(den.x / dn, -den.y / dn);
+    }
+    if (lane == 0) {
+      w.tauv[k] = tau;
+      w.ee[k] = beta;
+      w.dd[k] = M.lo(k, k).x;
+    }
+    double2 *vv = w.vv(k);
+    for (int i = lane; i < m; i += 64) {
+      const double2 v = (i == 0) ? make_double2(1, 0) : zmul(M.lo(k + 1 + i, k), scal);
+      vv[i] = v;
+      if (i > 0) M.set(k + 1 + i, k, v);
+    }
+  };
   {
     double x = 0;
     for (int i = 2 + tid; i < r; i += nt) {
@@ -309,37 +347,11 @@ __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
     if (lane == 0) w.nred[wid] = x;
     __syncthreads();
   }
+  if (r >= 2 && wid == 0) reflector(0);
+  __syncthreads();
   for (int k = 0; k + 1 < r; ++k) {
     const int m = r - k - 1;   // trailing size, rows/cols k+1..r-1
-    // (a) reflector, by wave 0 alone (the other waves would only repeat the
-    // same scalar arithmetic); tau reaches them through LDS
-    if (wid == 0) {
-      double xn2 = 0;
-#pragma unroll
-      for (int q = 0; q < NW; ++q) xn2 += w.nred[q];
-      const double2 alpha = M.lo(k + 1, k);
-      double2 tau = make_double2(0, 0), scal = make_double2(0, 0);
-      double beta = alpha.x;
-      if (!(xn2 == 0.0 && alpha.y == 0.0)) {
-        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
-        beta = (alpha.x >= 0) ? -nrm : nrm;
-        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-        const double2 den = make_double2(alpha.x - beta, alpha.y);
-        const double dn = den.x * den.x + den.y * den.y;
-        scal = make_double2(den.x / dn, -den.y / dn);
-      }
-      if (lane == 0) {
-        w.tauv[k] = tau;
-        w.ee[k] = beta;
-        w.dd[k] = M.lo(k, k).x;
-      }
-      for (int i = lane; i < m; i += 64) {
-        const double2 v = (i == 0) ? make_double2(1, 0) : zmul(M.lo(k + 1 + i, k), scal);
-        w.vv[i] = v;
-        if (i > 0) M.set(k + 1 + i, k, v);
-      }
-    }
-    __syncthreads();
+    const double2 *vv = w.vv(k);
     const double2 tau = w.tauv[k];
     // (b) x = tau C22 v, C22 Hermitian from its lower triangle
     double qp = 0;
@@ -362,15 +374,15 @@ __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
           int jj = g;
 #pragma unroll 2
           for (; jj + kRowG < m; jj += 2 * kRowG) {   // two chains in flight
-            s = zfma(elem(jj), w.vv[jj], s);
-            s1 = zfma(elem(jj + kRowG), w.vv[jj + kRowG], s1);
+            s = zfma(elem(jj), vv[jj], s);
+            s1 = zfma(elem(jj + kRowG), vv[jj + kRowG], s1);
           }
-          if (jj < m) s = zfma(elem(jj), w.vv[jj], s);
+          if (jj < m) s = zfma(elem(jj), vv[jj], s);
         }
         s = gsum2<kRowG>(zadd(s, s1));
         if (ii < m && g == 0) {
           w.xv[ii] = zmul(tau, s);
-          const double2 vi = w.vv[ii];
+          const double2 vi = vv[ii];
           qp += vi.x * s.x + vi.y * s.y;   // Re(conj(v_i) (C22 v)_i)
         }
       }
@@ -378,33 +390,52 @@ __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
     qp = wave_sum(qp);
     if (lane == 0) w.qred[wid] = qp;
     __syncthreads();
-    // (c) rank-2 update of the lower triangle, row groups over j <= i
     double q = 0;
 #pragma unroll
     for (int p = 0; p < NW; ++p) q += w.qred[p];
     const double al = -0.5 * (tau.x * tau.x + tau.y * tau.y) * q;
-    double nx = 0;
+    auto wv = [&](int i) { return zadd(w.xv[i], zscale(vv[i], al)); };
+    // (c1) first column of the trailing matrix (local column 0) and its norm
+    // below the subdiagonal: the next reflector's input
+    {
+      const double2 v0 = vv[0], w0 = wv(0);
+      double nx = 0;
+      for (int ii = tid; ii < m; ii += nt) {
+        const double2 vi = vv[ii], wi = wv(ii);
+        double2 c = M.lo(k + 1 + ii, k + 1);
+        c = zsub(c, zadd(zmul(vi, zconj(w0)), zmul(wi, zconj(v0))));
+        if (ii == 0) c.y = 0.0;
+        M.set(k + 1 + ii, k + 1, c);
+        if (ii >= 2) nx += c.x * c.x + c.y * c.y;
+      }
+      nx = wave_sum(nx);
+      if (lane == 0) w.nred[wid] = nx;
+    }
+    __syncthreads();
+    // (c2) the rest of the update (local columns 1..), waves 1-15, row groups
+    // over 1 <= j <= i; meanwhile wave 0 forms the next reflector
+    if (wid == 0) {
+      if (k + 2 < r) reflector(k + 1);
+    } else {
 #pragma unroll
-    for (int p = 0; p < kPasses; ++p) {
-      const int ii = p * kRowsPass + rl;
-      if (p * kRowsPass < m && ii < m) {
-        const double2 vi = w.vv[ii];
-        const double2 wi = zadd(w.xv[ii], zscale(vi, al));
-        const int gi = k + 1 + ii;
+      for (int p = 0; p < kUpPasses; ++p) {
+        const int ii = p * kUpRows + rlu;
+        if (p * kUpRows < m && ii < m && ii >= 1) {
+          const double2 vi = vv[ii];
+          const double2 wi = wv(ii);
+          const int gi = k + 1 + ii;
 #pragma unroll 4
-        for (int jj = g; jj <= ii; jj += kRowG) {
-          const double2 vj = w.vv[jj];
-          const double2 wj = zadd(w.xv[jj], zscale(vj, al));
-          double2 c = M.lo(gi, k + 1 + jj);
-          c = zsub(c, zadd(zmul(vi, zconj(wj)), zmul(wi, zconj(vj))));
-          if (ii == jj) c.y = 0.0;
-          M.set(gi, k + 1 + jj, c);
-          if (jj == 0 && ii >= 2) nx += c.x * c.x + c.y * c.y;
+          for (int jj = 1 + g; jj <= ii; jj += kRowG) {
+            const double2 vj = vv[jj];
+            const double2 wj = wv(jj);
+            double2 c = M.lo(gi, k + 1 + jj);
+            c = zsub(c, zadd(zmul(vi, zconj(wj)), zmul(wi, zconj(vj))));
+            if (ii == jj) c.y = 0.0;
+            M.set(gi, k + 1 + jj, c);
+          }
         }
       }
     }
-    nx = wave_sum(nx);
-    if (lane == 0) w.nred[wid] = nx;
     __syncthreads();
   }
   if (tid == 0) w.dd[r - 1] = M.lo(r - 1, r - 1).x;
@@ -807,7 +838,8 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
 
   // ---- 4. tridiagonalisation
   {
-    TriWork tw{dd, ee, tauv, vv, xv, red + 32, red + 48};
+    // the second reflector buffer takes the e2 and lam arrays (unused here)
+    TriWork tw{dd, ee, tauv, vv, reinterpret_cast<double2 *>(e2), xv, red + 32, red + 48};
     if (packed) tridiagonalise(PackedLower{big}, r, tw); else tridiagonalise(FullLower{Mm, r}, r, tw);
   }
 
