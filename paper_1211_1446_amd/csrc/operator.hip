@@ -168,8 +168,15 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
 // CU, 768 threads (three waves per SIMD).  FP32: two workgroups of 512 threads
 // per CU (two planes in LDS, 128 VGPRs per lane), so that one workgroup's
 // barriers and column loads overlap the other's transforms.
+// Small planes (a few thousand points, e.g. 48 x 48) leave most of those
+// threads idle and fit several times into LDS: 256 threads, several
+// workgroups per CU (kSmall).
 template <typename T> constexpr int kPlaneThreads = sizeof(T) == 8 ? 768 : 512;
 template <typename T> constexpr int kPlaneWaves = sizeof(T) == 8 ? 3 : 4;
+constexpr int kSmallPlaneThreads = 256;
+constexpr size_t kSmallPlaneLds = 40 * 1024;
+template <typename T, bool kSmall>
+constexpr int kPlaneThr = kSmall ? kSmallPlaneThreads : kPlaneThreads<T>;
 // The list of rows that hold sphere columns sits in LDS behind the plane; so
 // do the twiddle tables in FP32.  FP64 reads its twiddles through the vector
 // cache: in LDS they slow the FP64 transforms, whose LDS traffic binds.
@@ -183,8 +190,8 @@ size_t plane_lds_bytes(int n1, int n2) {
 // kTab: both plane axes have a compiled two-step split (fft2.h); otherwise the
 // generic radix transforms run, in a kernel of their own so that their calls
 // and registers stay out of the table kernel.
-template <typename T, bool kTab>
-__global__ void __launch_bounds__(kPlaneThreads<T>, kPlaneWaves<T>) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
+template <typename T, bool kTab, bool kSmall = false>
+__global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
                                                 const int4 *__restrict__ col_info,
                                                 const int *__restrict__ rows, int nrows,
                                                 const FftPlan *__restrict__ pxy,
@@ -450,6 +457,8 @@ void init_kernel_attributes() {
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   const void *big_lds[] = {
       (const void *)k_zfft_inv<double, true>, (const void *)k_zfft_inv<double, false>,
       (const void *)k_zfft_inv<float, true>,  (const void *)k_zfft_inv<float, false>,
@@ -510,8 +519,10 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   dim3 gp(n3, ncols);
   size_t smp = plane_lds_bytes<T>(s.grid[0], s.grid[1]);
   const bool tab = fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]);
-  auto kplane = tab ? k_plane<T, true> : k_plane<T, false>;
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(kPlaneThreads<T>), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
+  const bool small = tab && smp <= kSmallPlaneLds;
+  auto kplane = small ? k_plane<T, true, true> : tab ? k_plane<T, true> : k_plane<T, false>;
+  const int pthr = small ? kSmallPlaneThreads : kPlaneThreads<T>;
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(pthr), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
                      s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(), Tw<T>(pot, 0),
                      Tw<T>(pot, 1), Vtab<T>(pot));
   DKS_HIP(hipGetLastError());
