@@ -326,6 +326,43 @@ def main():
         log(f"[bench] same systems one after another, fp64: {batch['fp64_sequential_s']:.3f}s")
         bb.close()
 
+    # ---- the layered crystal: 16 k-points of 120 bands (N ~ 17.0k each, 48 x 48 x 320
+    # grid) in one batched call, 4 all-active mixed iterations per k-point (and the
+    # FP64 polish's first Rayleigh-Ritz), plus the FP64 iteration on one k-point
+    layered = None
+    if not args.no_solve and not args.no_batch:
+        sL = sysgen.layered_crystal(0)
+        bL = dk.init_basis([sL])
+        nkL = sL.kpts.shape[0]
+        nL = sL.n_bands
+        XsL, npwL = [], []
+        for i in range(nkL):
+            NL, _, milL = dk.basis_info(bL, i)
+            X0L = np.zeros((nL, 4, NL), dtype=np.complex128)
+            X0L[:, :2] = sysgen.start_block(milL, sL.lattice, sL.kpts[i], nL, i)
+            XsL.append(torch.from_numpy(X0L).to(dev))
+            npwL.append(NL)
+        itL = 4
+        o = dk.default_opts(mode=dk.MODE_MIXED_FP32, tol=1e-300, n_iter=0, mixed_iter=itL,
+                            mixed_tol=-1.0, kinetic_balance=1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dk.lobpcgf_solve_batch(bL, list(range(nkL)), [nL] * nkL, [x.clone() for x in XsL], o)
+        torch.cuda.synchronize()
+        dtL = time.perf_counter() - t
+        it64 = np.zeros(16)
+        o64 = dk.default_opts(tol=1e-300, n_iter=itL, kinetic_balance=1)
+        dk.lobpcgf_solve(bL, 0, nL, XsL[0].clone(), o64, iter_ms=it64)
+        ms64 = float(np.mean(it64[1:itL]))
+        layered = {"kpoints": nkL, "npw_per_k": npwL, "bands": nL, "grid": list(sL.grid),
+                   "mixed_batched_s": dtL, "mixed_iterations_per_k": itL,
+                   "mixed_batched_kpoint_iterations_per_s": nkL * itL / dtL,
+                   "fp64_kpoint_iteration_ms": ms64,
+                   "fp64_kpoint_iterations_per_s": 1000.0 / ms64}
+        log(f"[bench] layered crystal: 16 k x {itL} mixed iterations batched {dtL:.2f}s; "
+            f"FP64 k-point iteration {ms64:.1f} ms")
+        bL.close()
+
     # ---- CPU oracle on a bounded sample: one Algorithm 1 iteration on the same system
     cpu = None
     if not args.no_cpu_baseline:
@@ -372,6 +409,7 @@ def main():
         "mixed_fp32_iters_per_s": 1000.0 / step32_ms,
         "time_to_solution_1e-8": tts,
         "batch_uneven": batch,
+        "layered_kpoints": layered,
         "kernels_apply_H_fp64": kernels,
         "matrix_kernels": mk,
         "roofline": roof,
