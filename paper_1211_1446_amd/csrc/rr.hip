@@ -699,9 +699,12 @@ struct RRScratch {
   }
 };
 
-// ---- 1-4 in one workgroup: scaling, Cholesky, L^-1, C, tridiagonal T
+// ---- 1-4 in one workgroup, in two launches around the two products of
+// k_rr_gemm: phase 0 scales, factors (Cholesky with dropping), compacts and
+// inverts L; phase 1 takes C = Li A Li^H from the products, forms its
+// Hermitian part and reduces it to the tridiagonal T.
 __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
-    const double2 *__restrict__ Ain, const double2 *__restrict__ Sin, int nz, int nkeep,
+    int phase, const double2 *__restrict__ Ain, const double2 *__restrict__ Sin, int nz, int nkeep,
     double drop_tol, const int *__restrict__ forced, int *__restrict__ info, RRScratch W,
     long long *__restrict__ tstamp) {
   // no static LDS in this kernel: the dynamic arena then starts at offset 0,
@@ -712,7 +715,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
   do {                  \
     if (tstamp && threadIdx.x == 0) tstamp[k] = wall_clock64(); \
   } while (0)
-  DKS_RR_STAMP(0);
+  if (phase == 0) DKS_RR_STAMP(0);
   // ---- LDS arena (sized by nz): partial sums, per-index arrays, then the
   // packed triangle or the GEMM tiles
   const int na = (nz + 1) & ~1;
@@ -736,6 +739,42 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
   const size_t nn = (size_t)nz * nz;
   double2 *Sg = W.Sg, *Am = W.Am, *Lc = W.Lc, *Mm = W.Mm, *Cg = W.Cg;
   const bool packed = (nz <= kRRPackedMax);
+  if (phase == 1) {
+    if (info[1]) return;
+    const int r = info[0];
+    {
+      // Hermitian part of the lower triangle (diagonal tiles hold both halves)
+      const int tri = r * (r + 1) / 2;
+      for (int e = tid; e < tri; e += nt) {
+        const int i = tri_row(e), j = e - i * (i + 1) / 2;
+        double2 h = Cg[(size_t)i * r + j];
+        if ((i / kGT) == (j / kGT)) {
+          const double2 y = Cg[(size_t)j * r + i];
+          h = make_double2(0.5 * (h.x + y.x), 0.5 * (h.y - y.y));
+        }
+        if (i == j) h.y = 0.0;
+        if (packed) PackedLower{big}.set(i, j, h); else FullLower{Mm, r}.set(i, j, h);
+      }
+    }
+    __syncthreads();
+    DKS_RR_STAMP(4);
+    // ---- 4. tridiagonalisation
+    {
+      // the second reflector buffer takes the e2 and lam arrays (unused here)
+      TriWork tw{dd, ee, tauv, vv, reinterpret_cast<double2 *>(e2), xv, red + 32, red + 48};
+      if (packed) tridiagonalise(PackedLower{big}, r, tw); else tridiagonalise(FullLower{Mm, r}, r, tw);
+    }
+    // ---- hand-off to the eigenvalue and eigenvector kernels
+    for (int i = tid; i < r; i += nt) {
+      W.dd[i] = dd[i];
+      W.ee[i] = (i + 1 < r) ? ee[i] : 0.0;
+      W.tau[i] = (i + 1 < r) ? tauv[i] : make_double2(0, 0);
+    }
+    if (packed)
+      for (int e = tid; e < r * (r + 1) / 2; e += nt) W.refl[e] = big[e];
+    DKS_RR_STAMP(5);
+    return;
+  }
 
   // ---- 1. scaling and Hermitian parts
   for (int i = tid; i < nz; i += nt) {
@@ -799,62 +838,40 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     Lc[e] = (b >= c) ? (packed ? PackedLower{big}.lo(b, c) : FullLower{Sg, r}.lo(b, c))
                      : make_double2(0, 0);
   }
-  __syncthreads();
-  DKS_RR_STAMP(3);
-  // Mm[a][b] = sum_{c <= b} A[ka][kc] conj(Li[b][c])
-  wg_gemm(
-      r, r, r, [&](int i, int k) { return Am[(size_t)kept[i] * nz + kept[k]]; },
-      [&](int k, int j) { return zconj(Lc[(size_t)k * r + j]); },
-      [&](int i, int j, double2 v) { Mm[(size_t)i * r + j] = v; },
-      [&](int, int j0, int &kb, int &ke) { kb = 0; ke = j0 + kGT; },
-      [&](int, int) { return true; }, ta, tb);
-  __syncthreads();
-  DKS_RR_STAMP(9);
-  // Cg[a][b] = sum_{c <= a} Li[a][c] Mm[c][b] on the tiles touching the lower triangle
-  wg_gemm(
-      r, r, r, [&](int i, int k) { return Lc[(size_t)k * r + i]; },
-      [&](int k, int j) { return Mm[(size_t)k * r + j]; },
-      [&](int i, int j, double2 v) { Cg[(size_t)i * r + j] = v; },
-      [&](int i0, int, int &kb, int &ke) { kb = 0; ke = i0 + kGT; },
-      [&](int i0, int j0) { return j0 <= i0; }, ta, tb);
-  __syncthreads();
-  DKS_RR_STAMP(10);
-  {
-    // Hermitian part of the lower triangle (diagonal tiles hold both halves)
-    const int tri = r * (r + 1) / 2;
-    for (int e = tid; e < tri; e += nt) {
-      const int i = tri_row(e), j = e - i * (i + 1) / 2;
-      double2 h = Cg[(size_t)i * r + j];
-      if ((i / kGT) == (j / kGT)) {
-        const double2 y = Cg[(size_t)j * r + i];
-        h = make_double2(0.5 * (h.x + y.x), 0.5 * (h.y - y.y));
-      }
-      if (i == j) h.y = 0.0;
-      if (packed) PackedLower{big}.set(i, j, h); else FullLower{Mm, r}.set(i, j, h);
-    }
-  }
-  __syncthreads();
-  DKS_RR_STAMP(4);
-
-  // ---- 4. tridiagonalisation
-  {
-    // the second reflector buffer takes the e2 and lam arrays (unused here)
-    TriWork tw{dd, ee, tauv, vv, reinterpret_cast<double2 *>(e2), xv, red + 32, red + 48};
-    if (packed) tridiagonalise(PackedLower{big}, r, tw); else tridiagonalise(FullLower{Mm, r}, r, tw);
-  }
-
-  // ---- hand-off to the eigenvalue and eigenvector kernels
-  for (int i = tid; i < r; i += nt) {
-    W.dd[i] = dd[i];
-    W.ee[i] = (i + 1 < r) ? ee[i] : 0.0;
-    W.tau[i] = (i + 1 < r) ? tauv[i] : make_double2(0, 0);
-    W.kept[i] = kept[i];
-  }
+  for (int i = tid; i < r; i += nt) W.kept[i] = kept[i];
   for (int i = tid; i < nz; i += nt) W.dsc[i] = dsc[i];
-  if (packed)
-    for (int e = tid; e < r * (r + 1) / 2; e += nt) W.refl[e] = big[e];
-  DKS_RR_STAMP(5);
+  DKS_RR_STAMP(3);
+
 #undef DKS_RR_STAMP
+}
+
+// ---- 3b. the two products of C = Li (D A D)_kept Li^H, one 64 x 64 output tile
+// per workgroup: which = 1: Mm[a][b] = sum_{c <= b} A[ka][kc] conj(Li[b][c]);
+// which = 2: Cg[a][b] = sum_{c <= a} Li[a][c] Mm[c][b] on the tiles touching the
+// lower triangle.  The zero triangles of Li bound the k range of each tile.
+__global__ void __launch_bounds__(kRRThreads) k_rr_gemm(int which, int nz, const int *__restrict__ info,
+                                                        RRScratch W) {
+  __shared__ double2 ta[kGT * kGK], tb[kGK * kGT];
+  if (info[1]) return;
+  const int r = info[0];
+  const int ti = blockIdx.x * kGT, tj = blockIdx.y * kGT;
+  if (ti >= r || tj >= r || (which == 2 && tj > ti)) return;   // uniform
+  const int *kept = W.kept;
+  const double2 *Am = W.Am, *Lc = W.Lc;
+  double2 *Mm = W.Mm, *Cg = W.Cg;
+  auto only = [&](int i0, int j0) { return i0 == ti && j0 == tj; };
+  if (which == 1)
+    wg_gemm(
+        r, r, r, [&](int i, int k) { return Am[(size_t)kept[i] * nz + kept[k]]; },
+        [&](int k, int j) { return zconj(Lc[(size_t)k * r + j]); },
+        [&](int i, int j, double2 v) { Mm[(size_t)i * r + j] = v; },
+        [&](int, int j0, int &kb, int &ke) { kb = 0; ke = j0 + kGT; }, only, ta, tb);
+  else
+    wg_gemm(
+        r, r, r, [&](int i, int k) { return Lc[(size_t)k * r + i]; },
+        [&](int k, int j) { return Mm[(size_t)k * r + j]; },
+        [&](int i, int j, double2 v) { Cg[(size_t)i * r + j] = v; },
+        [&](int i0, int, int &kb, int &ke) { kb = 0; ke = i0 + kGT; }, only, ta, tb);
 }
 
 // Sturm tolerances and the padded Gershgorin interval [glo, ghi] of T
@@ -1255,7 +1272,15 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
   DKS_HIP(attr_rc);
   scratch.ensure(RRScratch::bytes(nz, nkeep));
   const RRScratch W = RRScratch::at(scratch.p, nz, nkeep);
-  DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, A, S,
+  DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 0, A, S,
+             nz, nkeep, drop_tol, forced_drop, info, W, tstamp);
+  DKS_HIP(hipGetLastError());
+  const unsigned tiles = (unsigned)((nz + kGT - 1) / kGT);
+  for (int which = 1; which <= 2; ++which) {
+    DKS_LAUNCH("k_rr_gemm", k_rr_gemm, dim3(tiles, tiles), dim3(kRRThreads), 0, st, which, nz, info, W);
+    DKS_HIP(hipGetLastError());
+  }
+  DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 1, A, S,
              nz, nkeep, drop_tol, forced_drop, info, W, tstamp);
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH("k_rr_values", k_rr_values, dim3(nkeep + 1), dim3(kValThreads), 0, st, W.dd, W.ee,
