@@ -244,8 +244,11 @@ __device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double 
 // L^-1 = [1/l 0; -L2^-1 x / l  L2^-1].  Row groups as in the Cholesky; two
 // barriers per column.
 template <typename Mat>
-__device__ void trtri_lower(const Mat M, int n) {
-  const int tid = threadIdx.x, g = tid % kRowG, rl = tid / kRowG;
+__device__ void trtri_lower(const Mat M, int n, double2 *col) {
+  const int tid = threadIdx.x, nt = blockDim.x, g = tid % kRowG, rl = tid / kRowG;
+  // column j below the diagonal (still L's) goes to LDS one step ahead: read
+  // across rows it is a strided access, in global memory for large n
+  // (the last column has nothing below its diagonal)
   for (int j = n - 1; j >= 0; --j) {
     const int m = n - j - 1;
     const double inv = 1.0 / M.lo(j, j).x;
@@ -260,10 +263,10 @@ __device__ void trtri_lower(const Mat M, int n) {
           int k = g;
 #pragma unroll 2
           for (; k + kRowG <= ii; k += 2 * kRowG) {   // two chains in flight
-            s = zfma(M.lo(j + 1 + ii, j + 1 + k), M.lo(j + 1 + k, j), s);
-            s1 = zfma(M.lo(j + 1 + ii, j + 1 + k + kRowG), M.lo(j + 1 + k + kRowG, j), s1);
+            s = zfma(M.lo(j + 1 + ii, j + 1 + k), col[k], s);
+            s1 = zfma(M.lo(j + 1 + ii, j + 1 + k + kRowG), col[k + kRowG], s1);
           }
-          if (k <= ii) s = zfma(M.lo(j + 1 + ii, j + 1 + k), M.lo(j + 1 + k, j), s);
+          if (k <= ii) s = zfma(M.lo(j + 1 + ii, j + 1 + k), col[k], s);
         }
         y[p] = gsum2<kRowG>(zadd(s, s1));
       }
@@ -275,6 +278,9 @@ __device__ void trtri_lower(const Mat M, int n) {
       if (g == 0 && ii < m) M.set(j + 1 + ii, j, zscale(y[p], -inv));
     }
     if (tid == 0) M.set(j, j, make_double2(inv, 0.0));
+    // the next column (j - 1) below its diagonal: rows j..n-1, untouched so far
+    if (j > 0)
+      for (int k = tid; k < n - j; k += nt) col[k] = M.lo(j + k, j - 1);
     __syncthreads();
   }
 }
@@ -832,7 +838,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     }
     __syncthreads();
   }
-  if (packed) trtri_lower(PackedLower{big}, r); else trtri_lower(FullLower{Sg, r}, r);
+  if (packed) trtri_lower(PackedLower{big}, r, vv); else trtri_lower(FullLower{Sg, r}, r, vv);
   for (int e = tid; e < r * r; e += nt) {
     const int c = e / r, b = e - (e / r) * r;   // Lc[c r + b] = Li[b][c]
     Lc[e] = (b >= c) ? (packed ? PackedLower{big}.lo(b, c) : FullLower{Sg, r}.lo(b, c))
