@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <mutex>
+#include <type_traits>
 
 #include "dks_internal.h"
 
@@ -193,10 +194,20 @@ struct FullLower {
 // column, whose L column is zero.  Two barriers per column.
 template <typename Mat>
 __device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double *dsc, int *keep,
-                              double *sc) {
-  const int tid = threadIdx.x, g = tid % kRowG, rl = tid / kRowG;
+                              double *sc, double2 *rowj) {
+  // rows in global memory (n_Z > 120): row j, read by every row group, is
+  // staged in LDS first (one more barrier per column)
+  constexpr bool kStage = std::is_same<Mat, FullLower>::value;
+  const int tid = threadIdx.x, nt = blockDim.x, g = tid % kRowG, rl = tid / kRowG;
   for (int j = 0; j < n; ++j) {
     const int m = n - j;   // rows j..n-1
+    if constexpr (kStage) {
+      for (int k = tid; k < j; k += nt) rowj[k] = M.lo(j, k);
+      __syncthreads();
+    }
+    auto rowv = [&](int k) {
+      if constexpr (kStage) return rowj[k]; else return M.lo(j, k);
+    };
     double2 dot[kPasses];
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
@@ -209,10 +220,10 @@ __device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double 
           int k = g;
 #pragma unroll 2
           for (; k + kRowG < j; k += 2 * kRowG) {   // two chains in flight
-            s = zfma(M.lo(i, k), zconj(M.lo(j, k)), s);
-            s1 = zfma(M.lo(i, k + kRowG), zconj(M.lo(j, k + kRowG)), s1);
+            s = zfma(M.lo(i, k), zconj(rowv(k)), s);
+            s1 = zfma(M.lo(i, k + kRowG), zconj(rowv(k + kRowG)), s1);
           }
-          if (k < j) s = zfma(M.lo(i, k), zconj(M.lo(j, k)), s);
+          if (k < j) s = zfma(M.lo(i, k), zconj(rowv(k)), s);
         }
         dot[p] = gsum2<kRowG>(zadd(s, s1));
       }
@@ -805,8 +816,8 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
   DKS_RR_STAMP(1);
 
   // ---- 2. Cholesky with column dropping
-  if (packed) cholesky_drop(PackedLower{big}, nz, drop_tol, dsc, kept, red + 4);
-  else cholesky_drop(FullLower{Sg, nz}, nz, drop_tol, dsc, kept, red + 4);
+  if (packed) cholesky_drop(PackedLower{big}, nz, drop_tol, dsc, kept, red + 4, vv);
+  else cholesky_drop(FullLower{Sg, nz}, nz, drop_tol, dsc, kept, red + 4, vv);
   if (tid == 0) {
     int r = 0;
     for (int j = 0; j < nz; ++j)
