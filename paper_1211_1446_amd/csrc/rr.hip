@@ -228,12 +228,18 @@ __device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double 
         dot[p] = gsum2<kRowG>(zadd(s, s1));
       }
     }
-    if (tid == 0) sc[0] = M.lo(j, j).x - dot[0].x;
+    // the pivot, its square root and reciprocal by one thread (all 1024
+    // repeating the FP64 square root and division cost more than the barrier)
+    if (tid == 0) {
+      const double piv = M.lo(j, j).x - dot[0].x;
+      const bool dr = (dsc[j] == 0.0) || !(piv > drop_tol);
+      const double l = dr ? 0.0 : sqrt(piv);
+      sc[0] = l;
+      sc[1] = dr ? 0.0 : 1.0 / l;
+    }
     __syncthreads();
-    const double piv = sc[0];
-    const bool drop = (dsc[j] == 0.0) || !(piv > drop_tol);
-    const double ljj = drop ? 0.0 : sqrt(piv);
-    const double inv = drop ? 0.0 : 1.0 / ljj;
+    const double ljj = sc[0], inv = sc[1];
+    const bool drop = !(ljj > 0.0);
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
       const int ii = p * kRowsPass + rl;
@@ -255,14 +261,17 @@ __device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double 
 // L^-1 = [1/l 0; -L2^-1 x / l  L2^-1].  Row groups as in the Cholesky; two
 // barriers per column.
 template <typename Mat>
-__device__ void trtri_lower(const Mat M, int n, double2 *col) {
+__device__ void trtri_lower(const Mat M, int n, double2 *col, double *dinv) {
   const int tid = threadIdx.x, nt = blockDim.x, g = tid % kRowG, rl = tid / kRowG;
+  // reciprocals of the diagonal, all at once (column j only changes its own)
+  for (int j = tid; j < n; j += nt) dinv[j] = 1.0 / M.lo(j, j).x;
+  __syncthreads();
   // column j below the diagonal (still L's) goes to LDS one step ahead: read
   // across rows it is a strided access, in global memory for large n
   // (the last column has nothing below its diagonal)
   for (int j = n - 1; j >= 0; --j) {
     const int m = n - j - 1;
-    const double inv = 1.0 / M.lo(j, j).x;
+    const double inv = dinv[j];
     double2 y[kPasses];
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
@@ -849,7 +858,8 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     }
     __syncthreads();
   }
-  if (packed) trtri_lower(PackedLower{big}, r, vv); else trtri_lower(FullLower{Sg, r}, r, vv);
+  // (dd: free until the tridiagonalisation)
+  if (packed) trtri_lower(PackedLower{big}, r, vv, dd); else trtri_lower(FullLower{Sg, r}, r, vv, dd);
   for (int e = tid; e < r * r; e += nt) {
     const int c = e / r, b = e - (e / r) * r;   // Lc[c r + b] = Li[b][c]
     Lc[e] = (b >= c) ? (packed ? PackedLower{big}.lo(b, c) : FullLower{Sg, r}.lo(b, c))
