@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *_
                                                       const double2 *__restrict__ V, int ldv,
                                                       int n, int64_t K,
                                                       typename CT<T>::c *__restrict__ out,
-                                                      int64_t ldo, T beta) {
+                                                      int64_t ldo, T beta, double alpha) {
   using C = typename CT<T>::c;
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
@@ -514,8 +514,8 @@ __global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *_
     for (int e = tid; e < kUpICH * kUpMJ; e += blockDim.x) {
       const int ii = e / kUpMJ, jj = e - (e / kUpMJ) * kUpMJ;
       const double2 v = (ii < ic && j0 + jj < n) ? V[(size_t)(i0 + ii) * ldv + j0 + jj] : make_double2(0, 0);
-      Vr[e] = (T)v.x;
-      Vi[e] = (T)v.y;
+      Vr[e] = (T)(alpha * v.x);
+      Vi[e] = (T)(alpha * v.y);
     }
     for (int e = tid; e < kUpICH; e += blockDim.x)
       offs[e] = (e < ic) ? (aoff ? aoff[i0 + e] : (int64_t)(i0 + e) * K) : 0;
@@ -575,18 +575,18 @@ __global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *_
 
 template <typename T>
 void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int ldv, int n,
-             int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st) {
+             int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st, double alpha) {
   if (n <= 0 || K <= 0) return;
   const char *name = sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32";
   dim3 grid((unsigned)((K + kUpMK - 1) / kUpMK), (n + kUpMJ - 1) / kUpMJ);
   DKS_LAUNCH(name, k_gemm_up_mfma<T>, grid, dim3(256), 0, st, A, aoff, m, V, ldv, n, K, out, ldo,
-             (T)beta);
+             (T)beta, alpha);
   DKS_HIP(hipGetLastError());
 }
 template void gemm_up<double>(const double2 *, const int64_t *, int, const double2 *, int, int,
-                              int64_t, double2 *, int64_t, double, hipStream_t);
+                              int64_t, double2 *, int64_t, double, hipStream_t, double);
 template void gemm_up<float>(const float2 *, const int64_t *, int, const double2 *, int, int,
-                             int64_t, float2 *, int64_t, double, hipStream_t);
+                             int64_t, float2 *, int64_t, double, hipStream_t, double);
 
 // ---------------------------------------------------------------------------
 // residuals and norms

@@ -213,7 +213,7 @@ void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, 
 // out_j[k] = alpha * sum_i V[i][j] A_i[k] (+ beta out_j[k]); V FP64 m x n (ld ldv).
 template <typename T>
 void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int ldv, int n,
-             int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st);
+             int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st, double alpha = 1.0);
 
 // R_j = HX_j - lambda_j X_j and ||R_j||^2 (FP64) for n columns of length K.
 template <typename T>
@@ -242,7 +242,9 @@ void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st);
 // the nkeep lowest Ritz pairs above floor_val.  info[0] = kept basis columns, info[1] =
 // status (0 ok, 1 too few independent columns, 2 too few Ritz values above floor_val),
 // info[2] = dropped columns, info[3] = Ritz values below floor_val; dinfo[0] = smallest
-// Ritz value.  `forced_drop` (nz ints or null): 1 marks a column to skip.
+// Ritz value, dinfo[1] = smallest Cholesky pivot kept (S scaled to unit diagonal: the
+// squared sine of the angle between a basis column and the span of the columns before it).
+// `forced_drop` (nz ints or null): 1 marks a column to skip.
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
                    DevBuf &scratch, hipStream_t st, long long *tstamp = nullptr);

@@ -191,14 +191,16 @@ struct FullLower {
 // conj(L_jk)) / L_jj.  The dot products of all rows i >= j are formed at once,
 // kRowG lanes per row over strided k and reduced inside the lane group; row j's
 // is the pivot, passed on through LDS (`sc`).  keep[j] = 0 marks a dropped
-// column, whose L column is zero.  Two barriers per column.
+// column, whose L column is zero.  Two barriers per column.  Returns, in
+// thread 0, the smallest pivot kept (1 in the other threads).
 template <typename Mat>
-__device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double *dsc, int *keep,
-                              double *sc, double2 *rowj) {
+__device__ double cholesky_drop(const Mat M, int n, double drop_tol, const double *dsc, int *keep,
+                                double *sc, double2 *rowj) {
   // rows in global memory (n_Z > 120): row j, read by every row group, is
   // staged in LDS first (one more barrier per column)
   constexpr bool kStage = std::is_same<Mat, FullLower>::value;
   const int tid = threadIdx.x, nt = blockDim.x, g = tid % kRowG, rl = tid / kRowG;
+  double pmin = 1.0;
   for (int j = 0; j < n; ++j) {
     const int m = n - j;   // rows j..n-1
     if constexpr (kStage) {
@@ -233,6 +235,7 @@ __device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double 
     if (tid == 0) {
       const double piv = M.lo(j, j).x - dot[0].x;
       const bool dr = (dsc[j] == 0.0) || !(piv > drop_tol);
+      if (!dr) pmin = fmin(pmin, piv);
       const double l = dr ? 0.0 : sqrt(piv);
       sc[0] = l;
       sc[1] = dr ? 0.0 : 1.0 / l;
@@ -254,6 +257,7 @@ __device__ void cholesky_drop(const Mat M, int n, double drop_tol, const double 
     }
     __syncthreads();
   }
+  return pmin;
 }
 
 // In-place inverse of the lower-triangular n x n matrix in M (nonzero real
@@ -731,8 +735,8 @@ struct RRScratch {
 // Hermitian part and reduces it to the tridiagonal T.
 __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     int phase, const double2 *__restrict__ Ain, const double2 *__restrict__ Sin, int nz, int nkeep,
-    double drop_tol, const int *__restrict__ forced, int *__restrict__ info, RRScratch W,
-    long long *__restrict__ tstamp) {
+    double drop_tol, const int *__restrict__ forced, int *__restrict__ info,
+    double *__restrict__ dinfo, RRScratch W, long long *__restrict__ tstamp) {
   // no static LDS in this kernel: the dynamic arena then starts at offset 0,
   // 16-byte aligned, as the double2 accesses (ds_read_b128) need for speed
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -825,9 +829,10 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
   DKS_RR_STAMP(1);
 
   // ---- 2. Cholesky with column dropping
-  if (packed) cholesky_drop(PackedLower{big}, nz, drop_tol, dsc, kept, red + 4, vv);
-  else cholesky_drop(FullLower{Sg, nz}, nz, drop_tol, dsc, kept, red + 4, vv);
+  const double pmin = packed ? cholesky_drop(PackedLower{big}, nz, drop_tol, dsc, kept, red + 4, vv)
+                             : cholesky_drop(FullLower{Sg, nz}, nz, drop_tol, dsc, kept, red + 4, vv);
   if (tid == 0) {
+    dinfo[1] = pmin;
     int r = 0;
     for (int j = 0; j < nz; ++j)
       if (kept[j]) kept[r++] = j;
@@ -1300,7 +1305,7 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
   scratch.ensure(RRScratch::bytes(nz, nkeep));
   const RRScratch W = RRScratch::at(scratch.p, nz, nkeep);
   DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 0, A, S,
-             nz, nkeep, drop_tol, forced_drop, info, W, tstamp);
+             nz, nkeep, drop_tol, forced_drop, info, dinfo, W, tstamp);
   DKS_HIP(hipGetLastError());
   const unsigned tiles = (unsigned)((nz + kGT - 1) / kGT);
   for (int which = 1; which <= 2; ++which) {
@@ -1308,7 +1313,7 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
     DKS_HIP(hipGetLastError());
   }
   DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 1, A, S,
-             nz, nkeep, drop_tol, forced_drop, info, W, tstamp);
+             nz, nkeep, drop_tol, forced_drop, info, dinfo, W, tstamp);
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH("k_rr_values", k_rr_values, dim3(nkeep + 1), dim3(kValThreads), 0, st, W.dd, W.ee,
              nkeep, floor_val, info, W.lam, theta, dinfo, tstamp);

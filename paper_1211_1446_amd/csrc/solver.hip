@@ -49,7 +49,7 @@ template <typename T> struct Blocks {
 struct Solver {
   Blocks<double> b64;
   Blocks<float> b32;
-  DevBuf gS, gA, Vz, Vp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2, tst;
+  DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2, tst;
   Workspace ws;   // H.X scratch of this solver's applies
 };
 
@@ -140,6 +140,15 @@ static double active_level(const std::vector<double> &r, double tol, int &nact) 
 }
 
 constexpr int kStallFp64 = 20;     // iterations without a new best residual before stopping
+// FP64: iterations without a new best residual before a filtered restart, and
+// how many such restarts a stage makes before the stall test above may stop it
+constexpr int kStallRestartFp64 = 8;
+constexpr int kStallRestarts = 3;
+// P is made orthogonal to X after an FP64 Rayleigh-Ritz step whose basis had a
+// Cholesky pivot (unit-diagonal scaling) below this, and after every FP32 one
+// (where rounding, 2^-24 of each column, swamps P's part outside span X long
+// before such a pivot shows)
+constexpr double kOrthoPivot = 1e-4;
 constexpr int kMaxRollbacks = 8;   // discarded broken-down steps before a stage gives up
 constexpr int kStallFp32 = 4;
 constexpr int kPolishFilters = 2;  // filter applications on the block entering the FP64 polish
@@ -158,6 +167,7 @@ template <typename T> struct LoopState {
   std::vector<double> lam, res;
   bool converged = false;
   int iters = 0;
+  double min_piv = 1.0;   // smallest Cholesky pivot of the last Rayleigh-Ritz basis
   int dropped = 0;   // directions the last Rayleigh-Ritz removed as dependent
 };
 
@@ -226,6 +236,7 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
                    (int)sizeof(T), nz, n, s.m, mp, info[0], info[1], dinfo[0]);
     if (info[1] == 0) {
       s.dropped = info[2];
+      s.min_piv = dinfo[1];
       if (x.info) {
         x.info->basis_drops += info[2];
         x.info->neg_ritz_discarded += info[3];
@@ -295,6 +306,25 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
                bk.K, bk.z(nxt, 2 * n), bk.K, 0.0, x.st);
     gemm_up<T>(bk.HZ[s.cur].template as<cplx<T>>(), offyp, nyp, sv.Vp.as<double2>(), mnew, mnew,
                bk.K, bk.hz(nxt, 2 * n), bk.K, 0.0, x.st);
+    // P against the new X: P -= X (X^H P), HP -= HX (X^H P), in FP32 and,
+    // in FP64, once the last basis was ill-conditioned.  The directions of P formed above can lie
+    // mostly inside span X (the Rayleigh-Ritz rotates near-degenerate Ritz
+    // vectors into each other from one step to the next, and P carries those
+    // rotations along), so that its useful part, the part outside span X, is
+    // a small fraction of each column: the Cholesky pivots of P's columns are
+    // then small.  Left in, the overlaps of that part are resolved only to
+    // rounding relative to the whole column, and close clusters stop
+    // converging at ~1e-7 in FP64.  Removing the span-X part keeps P, in the
+    // Rayleigh-Ritz basis, the new direction that it stands for.
+    if (sizeof(T) == 4 || s.min_piv < kOrthoPivot) {
+      sv.Wxp.ensure(sizeof(double2) * (size_t)n * mnew);
+      gemm_ip<T>(bk.z(nxt, 0), nullptr, n, bk.z(nxt, 2 * n), nullptr, mnew, nullptr, bk.K,
+                 sv.Wxp.as<double2>(), nullptr, mnew, sv.part, x.st);
+      gemm_up<T>(bk.z(nxt, 0), nullptr, n, sv.Wxp.as<double2>(), mnew, mnew, bk.K,
+                 bk.z(nxt, 2 * n), bk.K, 1.0, x.st, -1.0);
+      gemm_up<T>(bk.hz(nxt, 0), nullptr, n, sv.Wxp.as<double2>(), mnew, mnew, bk.K,
+                 bk.hz(nxt, 2 * n), bk.K, 1.0, x.st, -1.0);
+    }
     DKS_HIP(hipStreamSynchronize(x.st));   // vp must outlive the copy
   }
   s.mp = (mnew > 0 && s.m + s.mp > 0) ? mnew : 0;
@@ -307,7 +337,8 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
 // n_init: filter applications on the start block before the first Rayleigh-Ritz.
 template <typename T>
 static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n_init,
-                            double tol, int max_iter, double drop_tol, int stall_window) {
+                            double tol, int max_iter, double drop_tol, int stall_window,
+                            int restart_window) {
   Solver &sv = *x.sv;
   const bool filt = x.o->use_filter != 0;
   s.cur = 0;
@@ -329,6 +360,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
       active_level(std::vector<double>(s.res.begin(), s.res.begin() + (n - x.o->n_buffer)), tol, best_nact);
   int stall = 0;
   int rollbacks = 0;
+  int stall_restarts = 0;
   // Restart from the current X after a discarded step: the filter, applied
   // twice, removes the negative-band content the broken-down step let in (each
   // pass damps it by ~(w/2c^2)^2, as for the block entering the FP64 polish);
@@ -443,10 +475,12 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     if (x.bf16_gram && !(residual_level(s.res) > kBf16GramExit * x.o->mixed_tol))
       x.bf16_gram = false;
     // stagnation: neither a column newly below tol nor a new low of the median
-    // residual of the remaining columns for `stall_window` iterations means the
-    // iteration sits on its rounding floor; stop instead of iterating on noise.
-    // (The worst residual is gap-limited and not monotone in the first
-    // iterations; columns already converged no longer move the level.)
+    // residual of the remaining columns for `restart_window` iterations starts
+    // a filtered restart (FP64, a few times); after those, `stall_window` such
+    // iterations mean the iteration sits on its rounding floor: stop instead
+    // of iterating on noise.  (The worst residual is gap-limited and not
+    // monotone in the first iterations; columns already converged no longer
+    // move the level.)
     int nact = 0;
     const double level =
         active_level(std::vector<double>(s.res.begin(), s.res.begin() + (n - x.o->n_buffer)), tol, nact);
@@ -457,8 +491,22 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     } else if (level < 0.95 * best) {
       best = level;
       stall = 0;
-    } else if (stall_window > 0 && ++stall >= stall_window) {
-      break;
+    } else {
+      ++stall;
+      const bool can_restart = restart_window > 0 && stall_restarts < kStallRestarts;
+      if (can_restart && stall >= restart_window) {
+        // A stall well above the rounding floor of the operator is, in FP64,
+        // negative-band content that X has gathered from the rounding of its
+        // updates: Y and P are filtered, so that no Rayleigh-Ritz over
+        // [X, Y, P] can take it out again, and the residual carries it times
+        // ~2c^2.  A restart filters X itself (and drops P).
+        ++stall_restarts;
+        restart();
+        stall = 0;
+        best = active_level(std::vector<double>(s.res.begin(), s.res.begin() + nwant), tol, best_nact);
+      } else if (!can_restart && stall_window > 0 && stall >= stall_window) {
+        break;
+      }
     }
   }
   keep_best();
@@ -510,7 +558,8 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
     if (o.mode == DKS_MODE_FP64) {
       x.sv->b64.ensure(n, x.K);
       DKS_HIP(hipMemcpyAsync(x.sv->b64.z(0, 0), Xu, sizeof(double2) * x.K * n, hipMemcpyDeviceToDevice, st));
-      rc = run_stage<double>(x, x.sv->b64, s64, n, o.n_init, o.tol, o.n_iter, 1e-10, kStallFp64);
+      rc = run_stage<double>(x, x.sv->b64, s64, n, o.n_init, o.tol, o.n_iter, 1e-10, kStallFp64,
+                              kStallRestartFp64);
     } else {
       // reduced-precision stage
       x.sv->b32.ensure(n, x.K);
@@ -519,7 +568,7 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
       const bool fixed = !(o.mixed_tol > 0);   // mixed_tol <= 0: exactly mixed_iter iterations
       x.bf16_gram = (o.mode == DKS_MODE_MIXED_BF16GRAM);
       run_stage<float>(x, x.sv->b32, s32, n, o.n_init, fixed ? 0.0 : o.mixed_tol, o.mixed_iter, 1e-5,
-                       fixed ? 0 : kStallFp32);
+                       fixed ? 0 : kStallFp32, 0);
       inf.iters_reduced = s32.iters;
       x.bf16_gram = false;
       // FP64 polish.  The reduced-precision block carries rounding noise of
@@ -531,7 +580,8 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
       x.sv->b64.ensure(n, x.K);
       convert<float, double>(x.sv->b32.z(s32.cur, 0), x.sv->b64.z(0, 0), x.K * n, st);
       s64.iters = 0;
-      rc = run_stage<double>(x, x.sv->b64, s64, n, kPolishFilters, o.tol, o.n_iter, 1e-10, kStallFp64);
+      rc = run_stage<double>(x, x.sv->b64, s64, n, kPolishFilters, o.tol, o.n_iter, 1e-10, kStallFp64,
+                              kStallRestartFp64);
     }
     Blocks<double> &bk = x.sv->b64;
     DKS_HIP(hipMemcpyAsync(Xu, bk.z(s64.cur, 0), sizeof(double2) * x.K * n, hipMemcpyDeviceToDevice, st));
