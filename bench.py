@@ -280,11 +280,11 @@ def main():
             tts[tag] = rec
             log(f"[bench] solve {tag}: {dt:.3f}s, {info['iterations']} it, max|r| {info['max_resnorm']:.2e}")
 
-    # ---- batched solves: 16 uneven independent systems (the shape of the 64-system
-    # batch), in one dks_lobpcgf_solve_batch call versus one solve after another
+    # ---- batched solves: the 64 uneven independent systems, in one
+    # dks_lobpcgf_solve_batch call versus one solve after another
     batch = None
     if not args.no_solve and not args.no_batch:
-        systems = sysgen.uneven_batch(seed=0, count=16)
+        systems = sysgen.uneven_batch(seed=0, count=64)
         bb = dk.init_basis(systems)
         # wanted bands per system from the generator, plus kBuf buffer columns
         # (n_buffer: iterated, not required to converge; one value for the whole
@@ -313,6 +313,8 @@ def main():
             torch.cuda.synchronize()
             batch[f"{tag}_batch_s"] = time.perf_counter() - t
             batch[f"{tag}_batch_converged"] = sum(int(i_["converged"]) for i_ in infos)
+            batch[f"{tag}_batch_worst_resnorm"] = max(i_["max_resnorm"] for i_ in infos)
+            batch[f"{tag}_batch_iterations"] = sum(i_["iterations"] for i_ in infos)
             log(f"[bench] batch of {len(systems)} uneven systems, {tag}: "
                 f"{batch[f'{tag}_batch_s']:.3f}s, {batch[f'{tag}_batch_converged']} converged")
         o = dk.default_opts(mode=dk.MODE_FP64, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=kbuf)
