@@ -46,10 +46,41 @@ template <typename T> struct Blocks {
   cplx<T> *hz(int i, int row) { return HZ[i].as<cplx<T>>() + (size_t)row * K; }
 };
 
+// Pinned host staging of the per-iteration transfers.  A copy between the
+// device and pageable memory holds the host until the stream reaches it, which
+// drains the GPU before the next launches; pinned ones stay asynchronous.
+// Grow-only, one buffer per use: each is rewritten by the host only after a
+// stream synchronisation has retired the copy that read it.
+struct HostBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  HostBuf() = default;
+  HostBuf(const HostBuf &) = delete;
+  HostBuf &operator=(const HostBuf &) = delete;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  template <typename U> U *as(size_t count) {
+    const size_t need = sizeof(U) * count;
+    if (need > bytes) {
+      if (p) {
+        DKS_HIP(hipDeviceSynchronize());   // no copy may still read the old buffer
+        (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+      }
+      DKS_HIP(hipHostMalloc(&p, need, hipHostMallocDefault));
+      bytes = need;
+    }
+    return static_cast<U *>(p);
+  }
+};
+
 struct Solver {
   Blocks<double> b64;
   Blocks<float> b32;
   DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2, tst;
+  HostBuf h_rr, h_lam, h_res, h_act, h_vp;
   Workspace ws;   // H.X scratch of this solver's applies
 };
 
@@ -225,10 +256,17 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
       for (int k = 1; k < 9; ++k) std::fprintf(stderr, "%s%.1f", k > 1 ? ", " : "", (ts[k] - ts[k - 1]) / 100.0);
       std::fprintf(stderr, "]}\n");
     }
-    int info[4];
-    double dinfo[2];
+    // status, Ritz values and vectors in one round trip: [info 4 x int |
+    // dinfo 2 x double | theta n | V nz x n]
+    double2 *hr = sv.h_rr.as<double2>(2 + (size_t)n + (size_t)nz * n);
+    int *info = reinterpret_cast<int *>(hr);
+    double *dinfo = reinterpret_cast<double *>(hr + 1);
+    double *hth = reinterpret_cast<double *>(hr + 2);
+    double2 *hvz = hr + 2 + (n + 1) / 2;
     DKS_HIP(hipMemcpyAsync(info, sv.rinfo.p, sizeof(int) * 4, hipMemcpyDeviceToHost, x.st));
     DKS_HIP(hipMemcpyAsync(dinfo, sv.rdinfo.p, sizeof(double) * 2, hipMemcpyDeviceToHost, x.st));
+    DKS_HIP(hipMemcpyAsync(hth, sv.theta.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
+    DKS_HIP(hipMemcpyAsync(hvz, sv.Vz.p, sizeof(double2) * nz * n, hipMemcpyDeviceToHost, x.st));
     DKS_HIP(hipStreamSynchronize(x.st));
     if (log_enabled())
       std::fprintf(stderr,
@@ -244,11 +282,8 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
         x.info->min_ritz = std::min(x.info->min_ritz, dinfo[0]);
       }
       s.mp = mp;
-      hV.resize((size_t)nz * n);
-      DKS_HIP(hipMemcpyAsync(hV.data(), sv.Vz.p, sizeof(double2) * nz * n, hipMemcpyDeviceToHost, x.st));
-      s.lam.resize(n);
-      DKS_HIP(hipMemcpyAsync(s.lam.data(), sv.theta.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
-      DKS_HIP(hipStreamSynchronize(x.st));
+      hV.assign(hvz, hvz + (size_t)nz * n);
+      s.lam.assign(hth, hth + n);
       return true;
     }
     if (mp == 0) return false;
@@ -270,13 +305,16 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
   gemm_up<T>(bk.HZ[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, sv.Vz.as<double2>(), n, n,
              bk.K, bk.hz(nxt, 0), bk.K, 0.0, x.st);
   sv.lam.ensure(sizeof(double) * n);
-  DKS_HIP(hipMemcpyAsync(sv.lam.p, s.lam.data(), sizeof(double) * n, hipMemcpyHostToDevice, x.st));
+  double *hl = sv.h_lam.as<double>(n);
+  std::copy(s.lam.begin(), s.lam.end(), hl);
+  DKS_HIP(hipMemcpyAsync(sv.lam.p, hl, sizeof(double) * n, hipMemcpyHostToDevice, x.st));
   sv.norms.ensure(sizeof(double) * n);
   residual<T>(bk.z(nxt, 0), bk.hz(nxt, 0), sv.lam.as<double>(), n, bk.K, bk.R.template as<cplx<T>>(),
               sv.norms.as<double>(), sv.part2, x.st);
-  s.res.resize(n);
-  DKS_HIP(hipMemcpyAsync(s.res.data(), sv.norms.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
+  double *hres = sv.h_res.as<double>(n);
+  DKS_HIP(hipMemcpyAsync(hres, sv.norms.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
   DKS_HIP(hipStreamSynchronize(x.st));
+  s.res.assign(hres, hres + n);
   for (auto &r : s.res) r = std::sqrt(std::max(r, 0.0));
   if (log_enabled()) {
     std::fprintf(stderr, "{\"prec\": %d, \"lam\": [", (int)sizeof(T));
@@ -297,11 +335,12 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
   if (mnew > 0 && s.m + s.mp > 0) {
     // conjugate directions P = [0, Y, P] V[:, act] (Algorithm 1), HP alike
     const int nyp = s.m + s.mp;
-    std::vector<double2> vp((size_t)nyp * mnew);
+    const size_t nvp = (size_t)nyp * mnew;
+    double2 *vp = sv.h_vp.as<double2>(nvp);
     for (int i = 0; i < nyp; ++i)
       for (int a = 0; a < mnew; ++a) vp[(size_t)i * mnew + a] = hV[(size_t)(n + i) * n + act[a]];
-    sv.Vp.ensure(sizeof(double2) * vp.size());
-    DKS_HIP(hipMemcpyAsync(sv.Vp.p, vp.data(), sizeof(double2) * vp.size(), hipMemcpyHostToDevice, x.st));
+    sv.Vp.ensure(sizeof(double2) * nvp);
+    DKS_HIP(hipMemcpyAsync(sv.Vp.p, vp, sizeof(double2) * nvp, hipMemcpyHostToDevice, x.st));
     const int64_t *offyp = sv.off.as<int64_t>() + n;
     gemm_up<T>(bk.Z[s.cur].template as<cplx<T>>(), offyp, nyp, sv.Vp.as<double2>(), mnew, mnew,
                bk.K, bk.z(nxt, 2 * n), bk.K, 0.0, x.st);
@@ -326,7 +365,6 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
       gemm_up<T>(bk.hz(nxt, 0), nullptr, n, sv.Wxp.as<double2>(), mnew, mnew, bk.K,
                  bk.hz(nxt, 2 * n), bk.K, 1.0, x.st, -1.0);
     }
-    DKS_HIP(hipStreamSynchronize(x.st));   // vp must outlive the copy
   }
   s.mp = (mnew > 0 && s.m + s.mp > 0) ? mnew : 0;
   s.m = mnew;
@@ -413,7 +451,9 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     const int m = s.m;
     // preconditioned residual (T = I): Y = R[:, active]
     sv.idx.ensure(sizeof(int) * n);
-    DKS_HIP(hipMemcpyAsync(sv.idx.p, s.act.data(), sizeof(int) * m, hipMemcpyHostToDevice, x.st));
+    int *ha = sv.h_act.as<int>(n);
+    std::copy(s.act.begin(), s.act.end(), ha);
+    DKS_HIP(hipMemcpyAsync(sv.idx.p, ha, sizeof(int) * m, hipMemcpyHostToDevice, x.st));
     gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
     // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
