@@ -175,7 +175,10 @@ constexpr int kStallFp64 = 20;     // iterations without a new best residual bef
 // how many such restarts a stage makes before the stall test above may stop it
 constexpr int kStallRestartFp64 = 8;
 constexpr int kStallRestarts = 3;
-constexpr int kRegressRestarts = 4;   // the same when converged columns come back
+// the same when converged columns come back, at least kRegressSpacing
+// iterations after the previous restart and at most kRegressRestarts times
+constexpr int kRegressRestarts = 16;
+constexpr int kRegressSpacing = 10;
 // P is made orthogonal to X after an FP64 Rayleigh-Ritz step whose basis had a
 // Cholesky pivot (unit-diagonal scaling) below this, and after every FP32 one
 // (where rounding, 2^-24 of each column, swamps P's part outside span X long
@@ -399,7 +402,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
       active_level(std::vector<double>(s.res.begin(), s.res.begin() + (n - x.o->n_buffer)), tol, best_nact);
   int stall = 0;
   int rollbacks = 0;
-  int stall_restarts = 0, regress_restarts = 0;
+  int stall_restarts = 0, regress_restarts = 0, last_restart = -kRegressSpacing;
   // Restart from the current X after a discarded step: the filter, applied
   // twice, removes the negative-band content the broken-down step let in (each
   // pass damps it by ~(w/2c^2)^2, as for the block entering the FP64 polish);
@@ -528,8 +531,10 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     // Wanted columns that had converged coming back above tol, more than a
     // Kramers pair at once, is the same negative-band content showing in the
     // columns no longer iterated on; left alone it ends in a broken-down step.
-    if (restart_window > 0 && regress_restarts < kRegressRestarts && nact > best_nact + 2) {
+    if (restart_window > 0 && regress_restarts < kRegressRestarts && nact > best_nact + 2 &&
+        s.iters - last_restart >= kRegressSpacing) {
       ++regress_restarts;
+      last_restart = s.iters;
       restart();
       stall = 0;
       best = active_level(std::vector<double>(s.res.begin(), s.res.begin() + nwant), tol, best_nact);
