@@ -478,15 +478,22 @@ constexpr int kUpICH = 64;   // rows of V staged in LDS at a time
 // Block update out_j[k] = sum_i V[i][j] A_i[k] (+ beta out_j[k]) on the matrix
 // cores: out (n x K) = V^T (n x m) A (m x K) as
 // 16 x 16 x 4 products, V^T the left operand (rows j, reduction over i) and the
-// rows of A the right one.  A workgroup of 4 waves covers kUpMK k values of
-// kUpMJ columns j: each wave 3 j-tiles x 2 k-tiles of 16, complex as four real
-// products.  V comes through LDS in chunks of kUpICH rows; the A fragments of
-// the next 4-row step are fetched while the current one is multiplied.
+// rows of A the right one.  A workgroup of 8 waves covers kUpMK k values of
+// kUpMJ columns j: each wave 3 j-tiles x kUpKT k-tile of 16, complex as four
+// real products.  One k-tile per wave keeps a wave at <= 80 VGPRs, so that
+// three workgroups (six waves per SIMD) share a CU, which the LDS also allows
+// (FP64 V chunks of 48 KB); two k-tiles per wave ran at two waves per SIMD in
+// FP64 and were 22 % slower.  V comes through LDS in chunks of kUpICH rows;
+// the A fragments of the next 4-row step are fetched while the current one is
+// multiplied.
 constexpr int kUpMJ = 48;
 constexpr int kUpMK = 128;
+constexpr int kUpKT = 1;
+constexpr int kUpThreads = 64 * kUpMK / (16 * kUpKT);
+constexpr int kUpWaves = 6;   // minimum waves per SIMD asked of the compiler
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *__restrict__ A,
+__global__ void __launch_bounds__(kUpThreads, kUpWaves) k_gemm_up_mfma(const typename CT<T>::c *__restrict__ A,
                                                       const int64_t *__restrict__ aoff, int m,
                                                       const double2 *__restrict__ V, int ldv,
                                                       int n, int64_t K,
@@ -498,14 +505,15 @@ __global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *_
   __shared__ T Vr[kUpICH * kUpMJ], Vi[kUpICH * kUpMJ];
   __shared__ int64_t offs[kUpICH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int KT = kUpKT;
   const int j0 = blockIdx.y * kUpMJ;
-  const int64_t k0 = (int64_t)blockIdx.x * kUpMK + wave * 32;
+  const int64_t k0 = (int64_t)blockIdx.x * kUpMK + wave * 16 * KT;
   const int li = lane >> 4, lc = lane & 15;
-  acc_t re[3][2], im[3][2];
+  acc_t re[3][KT], im[3][KT];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < KT; ++b) {
       re[a][b] = acc_t{0, 0, 0, 0};
       im[a][b] = acc_t{0, 0, 0, 0};
     }
@@ -521,11 +529,11 @@ __global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *_
       offs[e] = (e < ic) ? (aoff ? aoff[i0 + e] : (int64_t)(i0 + e) * K) : 0;
     __syncthreads();
     // A fragments of 4-row step s: row ii = 4 s + li, columns k0 + 16 kt + lc
-    C fa[2], nx[2];
+    C fa[KT], nx[KT];
     auto fetch = [&](int st, C *f) {
       const int ii = 4 * st + li;
 #pragma unroll
-      for (int kt = 0; kt < 2; ++kt) {
+      for (int kt = 0; kt < KT; ++kt) {
         const int64_t k = k0 + 16 * kt + lc;
         f[kt] = (ii < ic && k < K) ? A[offs[ii] + k] : C{0, 0};
       }
@@ -539,7 +547,7 @@ __global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *_
       for (int jt = 0; jt < 3; ++jt) {
         const T vr = Vr[ii * kUpMJ + jt * 16 + lc], vi = Vi[ii * kUpMJ + jt * 16 + lc];
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
+        for (int kt = 0; kt < KT; ++kt) {
           // v a: re += vr ar - vi ai, im += vr ai + vi ar
           re[jt][kt] = MF::mma(vr, fa[kt].x, re[jt][kt]);
           im[jt][kt] = MF::mma(vr, fa[kt].y, im[jt][kt]);
@@ -547,15 +555,15 @@ __global__ void __launch_bounds__(256) k_gemm_up_mfma(const typename CT<T>::c *_
           im[jt][kt] = MF::mma(vi, fa[kt].x, im[jt][kt]);
         }
       }
-      fa[0] = nx[0];
-      fa[1] = nx[1];
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) fa[kt] = nx[kt];
     }
     __syncthreads();
   }
 #pragma unroll
   for (int jt = 0; jt < 3; ++jt)
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
+    for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = j0 + jt * 16 + MF::row(lane, v);
@@ -579,8 +587,8 @@ void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int
   if (n <= 0 || K <= 0) return;
   const char *name = sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32";
   dim3 grid((unsigned)((K + kUpMK - 1) / kUpMK), (n + kUpMJ - 1) / kUpMJ);
-  DKS_LAUNCH(name, k_gemm_up_mfma<T>, grid, dim3(256), 0, st, A, aoff, m, V, ldv, n, K, out, ldo,
-             (T)beta, alpha);
+  DKS_LAUNCH(name, k_gemm_up_mfma<T>, grid, dim3(kUpThreads), 0, st, A, aoff, m, V, ldv, n, K,
+             out, ldo, (T)beta, alpha);
   DKS_HIP(hipGetLastError());
 }
 template void gemm_up<double>(const double2 *, const int64_t *, int, const double2 *, int, int,
