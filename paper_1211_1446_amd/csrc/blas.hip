@@ -51,7 +51,10 @@ __device__ __forceinline__ void ip_tile(int x, int tm, bool upper, int &ti, int 
   tj = ti + x;
 }
 
-template <typename T>
+// kTwo: B2 is given (the Gram pair S and A); without it the second set of
+// accumulators and its LDS tile are not there, which lets a single product
+// (projector coefficients, P against X) run at more waves per SIMD.
+template <typename T, bool kTwo>
 __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__restrict__ A,
                                                  const int64_t *__restrict__ aoff, int M,
                                                  const typename CT<T>::c *__restrict__ B,
@@ -66,8 +69,8 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
   constexpr int LD = kIpKT + 1;
   __shared__ C As[kIpTile * LD];
   __shared__ C Bs[kIpTile * LD];
-  __shared__ C B2s[kIpTile * LD];
-  const bool two = (B2 != nullptr);
+  __shared__ C B2s[kTwo ? kIpTile * LD : 1];
+  constexpr bool two = kTwo;
   int ti, tj;
   ip_tile(blockIdx.x, tm, upper != 0, ti, tj);
   const int tm0 = ti * kIpTile, tn0 = tj * kIpTile;
@@ -278,7 +281,8 @@ void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, con
   dim3 grid(tiles, 1, (unsigned)nsplit);
   const char *name = upper ? (sizeof(T) == 8 ? "k_gemm_ip.gram.f64" : "k_gemm_ip.gram.f32")
                            : (sizeof(T) == 8 ? "k_gemm_ip.f64" : "k_gemm_ip.f32");
-  DKS_LAUNCH(name, k_gemm_ip<T>, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk, tm,
+  auto kern = B2 ? k_gemm_ip<T, true> : k_gemm_ip<T, false>;
+  DKS_LAUNCH(name, kern, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk, tm,
              (int)upper, p1, p2);
   DKS_HIP(hipGetLastError());
   reduce_parts(p1, p2, (int)nsplit, M, Nn, upper, out, out2, ldo, st);
