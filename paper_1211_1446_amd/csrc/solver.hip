@@ -425,6 +425,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   // Once the basis has turned ill-conditioned (a dropped direction or a
   // discarded step) the iteration can degrade gradually; from then on the best
   // X so far (largest wanted residual) is kept and returned if the last is worse.
+  // A filtered restart marks the same trouble.
   const int nwant = n - x.o->n_buffer;
   auto wanted_max = [&]() {
     double mx = 0;
@@ -435,7 +436,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   double snap_mx = std::numeric_limits<double>::infinity();
   std::vector<double> snap_lam, snap_res;
   auto keep_best = [&]() {
-    risky = risky || s.dropped > 0 || rollbacks > 0;
+    risky = risky || s.dropped > 0 || rollbacks > 0 || stall_restarts > 0 || regress_restarts > 0;
     const double mx = wanted_max();
     if (!risky || !(mx < snap_mx)) return;
     bk.snap.ensure(sizeof(cplx<T>) * (size_t)bk.K * n);
