@@ -273,3 +273,44 @@ def test_lobpcgf_error_paths(dev):
     lam, res, info, rc = dk.lobpcgf_solve(b, 0, 4, Xd, dk.default_opts(n_iter=1, kinetic_balance=1))
     assert rc == 1 and np.all(np.isfinite(lam)) and info["iterations"] == 1
     b.close()
+
+
+def test_filter_damping_across_c(dev):
+    """The filter of Sec. 3.1 (f(E) = (E - C)^2 / Omega^2) on exact eigenvectors
+    of the small dimer (dense oracle) at c/2, c and 2c, the c-scan of the
+    filter's efficiency: in FP64 f(H)u = f(lambda)u for the lowest positive state
+    and the top of the negative band (to 1e-12 of |u| = 1), and the damping of
+    the negative band relative to the positive one, |F u_-| / |F u_+|, shrinks
+    as c grows (it goes as (w / 4c^2)^2).  FP32 reaches the same damping up to
+    its rounding floor (1e-6: rounding of terms ~2c^2 |u|, divided by Omega)."""
+    dk = _dk()
+    c0 = sysgen.C_LIGHT
+    ratios = []
+    for c in (0.5 * c0, c0, 2.0 * c0):
+        s = sysgen.tiny_dimer(0, c=c, ecut=2.5, grid=(16, 16, 16))
+        op = dks.DKSOperator(s)
+        w, V = np.linalg.eigh(op.dense())
+        ipos = int(np.argmax(w > -c * c))   # lowest positive-band state
+        ineg = ipos - 1                     # top of the negative band
+        b = dk.init_basis([s])
+        N, _, mil = dk.basis_info(b, 0)
+        p = perm_to_oracle(mil, op.miller)
+        C, Om = dk.filter_constants(b, 0)
+        U = np.stack([V[:, ipos].reshape(4, N), V[:, ineg].reshape(4, N)])
+        Ud = torch.from_numpy(to_lib(U, p)).to(dev)
+        print(f"[filter c-scan] c={c:.3f} N={N} lambda+={w[ipos]:.6f} lambda-={w[ineg]:.3f}", flush=True)
+        FUd = torch.empty_like(Ud)
+        dk.apply_filter(b, 0, Ud, FUd, C, Om)
+        got = to_orc(FUd.cpu().numpy(), p)
+        f = (w[[ipos, ineg]] - C) ** 2 / Om ** 2
+        for j in range(2):
+            assert np.linalg.norm(got[j] - f[j] * U[j]) < 1e-12, (c, j)
+        ratios.append(np.linalg.norm(got[1]) / np.linalg.norm(got[0]))
+        U32 = Ud.to(torch.complex64)
+        FU32 = torch.empty_like(U32)
+        dk.apply_filter(b, 0, U32, FU32, C, Om)
+        g32 = FU32.cpu().numpy()
+        r32 = np.linalg.norm(g32[1]) / np.linalg.norm(g32[0])
+        assert abs(r32 - ratios[-1]) < 1e-6, (c, r32, ratios[-1])
+        b.close()
+    assert ratios[0] > ratios[1] > ratios[2], ratios
