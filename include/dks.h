@@ -192,9 +192,10 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
  * start block, out: eigenvectors), eigenvalues into the host array lambda[i]
  * (n[i] doubles) and, when resnorms is not NULL, residual norms into
  * resnorms[i]; info, when not NULL, is an array of nsys records.  The same
- * options apply to every item; opts->iter_ms is ignored.  Items run on up to 4
- * library-owned streams (one host thread each, items i, i + 4, ... on lane
- * i mod 4), each lane with its own workspace, kept with the basis for reuse;
+ * options apply to every item; opts->iter_ms is ignored.  Items run on up to 8
+ * library-owned streams (one host thread each; a free lane takes the next item,
+ * largest 4N n^2 first), each lane with its own workspace, kept with the basis
+ * for reuse;
  * they start after the work queued on `stream` and `stream` waits for all of
  * them.  Returns the most severe item status (errors before DKS_WNOTCONV), with
  * dks_last_error naming the item; every item is attempted. */
