@@ -353,13 +353,13 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
                bk.K, bk.z(nxt, 2 * n), bk.K, 0.0, x.st);
     gemm_up<T>(bk.HZ[s.cur].template as<cplx<T>>(), offyp, nyp, sv.Vp.as<double2>(), mnew, mnew,
                bk.K, bk.hz(nxt, 2 * n), bk.K, 0.0, x.st);
-    // P against the new X: P -= X (X^H P), HP -= HX (X^H P), in FP32 and,
-    // in FP64, once the last basis was ill-conditioned.  The directions of P formed above can lie
-    // mostly inside span X (the Rayleigh-Ritz rotates near-degenerate Ritz
-    // vectors into each other from one step to the next, and P carries those
-    // rotations along), so that its useful part, the part outside span X, is
-    // a small fraction of each column: the Cholesky pivots of P's columns are
-    // then small.  Left in, the overlaps of that part are resolved only to
+    // P against the new X: P -= X (X^H P), HP -= HX (X^H P), in FP32 and, in
+    // FP64, once the last basis was ill-conditioned.  The directions of P
+    // formed above can lie mostly inside span X (the Rayleigh-Ritz rotates
+    // near-degenerate Ritz vectors into each other from one step to the next,
+    // and P carries those rotations along), so that its useful part, the part
+    // outside span X, is a small fraction of each column: the Cholesky pivots
+    // of P's columns are then small.  Left in, the overlaps of that part are resolved only to
     // rounding relative to the whole column, and close clusters stop
     // converging at ~1e-7 in FP64.  Removing the span-X part keeps P, in the
     // Rayleigh-Ritz basis, the new direction that it stands for.
