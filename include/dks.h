@@ -140,7 +140,7 @@ typedef struct {
   int mode;             /* dks_mode */
   double mixed_tol;     /* mixed modes: residual at which the reduced-precision stage stops
                            (it also stops when its residual stagnates); <= 0 runs exactly
-                           mixed_iter reduced-precision iterations */
+                           mixed_iter reduced-precision iterations.  Default 3e-4 */
   int mixed_iter;       /* mixed modes: cap on reduced-precision iterations */
   int kinetic_balance;  /* 1: rebuild the small components of X0 from the large ones,
                            chi = c sigma.q phi / (E_q + c^2) (Eq. (RKB)) */

@@ -693,7 +693,7 @@ void dks_default_opts(dks_solve_opts *o) {
   o->n_iter = 200;
   o->tol = 1e-8;
   o->mode = DKS_MODE_FP64;
-  o->mixed_tol = 1e-4;
+  o->mixed_tol = 3e-4;
   o->mixed_iter = 200;
   o->kinetic_balance = 0;
   o->use_filter = 1;
