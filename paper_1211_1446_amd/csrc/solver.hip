@@ -256,11 +256,13 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
                   sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
                   sv.rdinfo.as<double>(), sv.rrs, x.st, stamps ? sv.tst.as<long long>() : nullptr);
     if (stamps) {
-      long long ts[9];
+      // reduction phases: scaling, Cholesky, L^-1, products + Hermitian part,
+      // tridiagonal reduction (stamps 0-5 of k_rr_reduce)
+      long long ts[6];
       DKS_HIP(hipMemcpyAsync(ts, sv.tst.p, sizeof(ts), hipMemcpyDeviceToHost, x.st));
       DKS_HIP(hipStreamSynchronize(x.st));
       std::fprintf(stderr, "{\"rr_phase_us\": [");
-      for (int k = 1; k < 9; ++k) std::fprintf(stderr, "%s%.1f", k > 1 ? ", " : "", (ts[k] - ts[k - 1]) / 100.0);
+      for (int k = 1; k < 6; ++k) std::fprintf(stderr, "%s%.1f", k > 1 ? ", " : "", (ts[k] - ts[k - 1]) / 100.0);
       std::fprintf(stderr, "]}\n");
     }
     // status, Ritz values and vectors in one round trip: [info 4 x int |
