@@ -244,7 +244,9 @@ void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st);
 // info[2] = dropped columns, info[3] = Ritz values below floor_val; dinfo[0] = smallest
 // Ritz value, dinfo[1] = smallest Cholesky pivot kept (S scaled to unit diagonal: the
 // squared sine of the angle between a basis column and the span of the columns before it).
-// `forced_drop` (nz ints or null): 1 marks a column to skip.
+// `forced_drop` (nz ints or null): 1 marks a column to skip.  `tstamp` (optional,
+// device, kRRStamps entries): wall-clock stamps of the phases, for tuning.
+constexpr int kRRStamps = 24;
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
                    DevBuf &scratch, hipStream_t st, long long *tstamp = nullptr);

@@ -248,7 +248,7 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
     sv.rinfo.ensure(sizeof(int) * 4);
     sv.rdinfo.ensure(sizeof(double) * 2);
     const bool stamps = log_enabled();
-    if (stamps) sv.tst.ensure(sizeof(long long) * 16);
+    if (stamps) sv.tst.ensure(sizeof(long long) * kRRStamps);
     // BF16-split Gram products carry relative errors of a few 1e-6: directions
     // whose scaled overlap pivot is not well above that are dropped
     const double dtol = (sizeof(T) == 4 && x.bf16_gram) ? std::max(drop_tol, kBf16DropTol) : drop_tol;
