@@ -186,74 +186,122 @@ struct FullLower {
   __device__ __forceinline__ void set(int i, int j, double2 v) const { p[(size_t)i * ld + j] = v; }
 };
 
-// Left-looking Cholesky with column dropping on the lower triangle of M (n x n).
-// Column j: pivot S_jj - sum_{k<j} |L_jk|^2 and L_ij = (S_ij - sum_{k<j} L_ik
-// conj(L_jk)) / L_jj.  The dot products of all rows i >= j are formed at once,
-// kRowG lanes per row over strided k and reduced inside the lane group; row j's
-// is the pivot, passed on through LDS (`sc`).  keep[j] = 0 marks a dropped
-// column, whose L column is zero.  Two barriers per column.  Returns, in
-// thread 0, the smallest pivot kept (1 in the other threads).
+// Left-looking Cholesky with column dropping on the lower triangle of M (n x n),
+// two columns per step.  For columns j and j + 1 the dot products
+//   a_i = sum_{k<j} L_ik conj(L_jk),  b_i = sum_{k<j} L_ik conj(L_{j+1,k})
+// of all rows i >= j are formed in one pass (kRowG lanes per row over strided
+// k, reduced inside the lane group).  Thread 0 takes both pivots:
+//   L_jj = sqrt(S_jj - a_j),  L_{j+1,j} = (S_{j+1,j} - a_{j+1}) / L_jj,
+//   L_{j+1,j+1} = sqrt(S_{j+1,j+1} - b_{j+1} - |L_{j+1,j}|^2),
+// passed on through LDS (`sc`), and every row i > j + 1 forms
+//   L_ij = (S_ij - a_i) / L_jj,  L_{i,j+1} = (S_{i,j+1} - b_i - L_ij conj(L_{j+1,j})) / L_{j+1,j+1}.
+// A pivot not above drop_tol (or a column of zero scale) drops its column: its
+// L column is zero and keep[] = 0.  Three barriers per two columns.  Returns,
+// in thread 0, the smallest pivot kept (1 in the other threads).
 template <typename Mat>
 __device__ double cholesky_drop(const Mat M, int n, double drop_tol, const double *dsc, int *keep,
-                                double *sc, double2 *rowj) {
-  // rows in global memory (n_Z > 120): row j, read by every row group, is
-  // staged in LDS first (one more barrier per column)
+                                double *sc, double2 *rowj, double2 *rowj1) {
+  // rows in global memory (n_Z > 120): rows j and j + 1, read by every row
+  // group, are staged in LDS first (one more barrier per step)
   constexpr bool kStage = std::is_same<Mat, FullLower>::value;
   const int tid = threadIdx.x, nt = blockDim.x, g = tid % kRowG, rl = tid / kRowG;
   double pmin = 1.0;
-  for (int j = 0; j < n; ++j) {
+  for (int j = 0; j < n; j += 2) {
     const int m = n - j;   // rows j..n-1
+    const bool two = m > 1;
     if constexpr (kStage) {
-      for (int k = tid; k < j; k += nt) rowj[k] = M.lo(j, k);
+      for (int k = tid; k < j; k += nt) {
+        rowj[k] = M.lo(j, k);
+        if (two) rowj1[k] = M.lo(j + 1, k);
+      }
       __syncthreads();
     }
-    auto rowv = [&](int k) {
+    auto rowa = [&](int k) {
       if constexpr (kStage) return rowj[k]; else return M.lo(j, k);
     };
-    double2 dot[kPasses];
+    auto rowb = [&](int k) {
+      if constexpr (kStage) return rowj1[k]; else return M.lo(j + 1, k);
+    };
+    double2 da[kPasses], db[kPasses];
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
-      dot[p] = make_double2(0, 0);
+      da[p] = db[p] = make_double2(0, 0);
       if (p * kRowsPass < m) {   // uniform
         const int ii = p * kRowsPass + rl;
-        double2 s = make_double2(0, 0), s1 = make_double2(0, 0);
+        double2 sa = make_double2(0, 0), sb = make_double2(0, 0);
         if (ii < m) {
           const int i = j + ii;
-          int k = g;
-#pragma unroll 2
-          for (; k + kRowG < j; k += 2 * kRowG) {   // two chains in flight
-            s = zfma(M.lo(i, k), zconj(rowv(k)), s);
-            s1 = zfma(M.lo(i, k + kRowG), zconj(rowv(k + kRowG)), s1);
+          if (two) {
+            for (int k = g; k < j; k += kRowG) {
+              const double2 l = M.lo(i, k);
+              sa = zfma(l, zconj(rowa(k)), sa);
+              sb = zfma(l, zconj(rowb(k)), sb);
+            }
+          } else {
+            for (int k = g; k < j; k += kRowG) sa = zfma(M.lo(i, k), zconj(rowa(k)), sa);
           }
-          if (k < j) s = zfma(M.lo(i, k), zconj(rowv(k)), s);
         }
-        dot[p] = gsum2<kRowG>(zadd(s, s1));
+        da[p] = gsum2<kRowG>(sa);
+        db[p] = gsum2<kRowG>(sb);
       }
     }
-    // the pivot, its square root and reciprocal by one thread (all 1024
+    // row j + 1's products to thread 0 (row j's are its own)
+    if (two && rl == 1 && g == 0) {
+      sc[2] = da[0].x;
+      sc[3] = da[0].y;
+      sc[4] = db[0].x;
+    }
+    __syncthreads();
+    // the pivots, square roots and reciprocals by one thread (all 1024
     // repeating the FP64 square root and division cost more than the barrier)
     if (tid == 0) {
-      const double piv = M.lo(j, j).x - dot[0].x;
+      const double piv = M.lo(j, j).x - da[0].x;
       const bool dr = (dsc[j] == 0.0) || !(piv > drop_tol);
       if (!dr) pmin = fmin(pmin, piv);
       const double l = dr ? 0.0 : sqrt(piv);
+      const double inv = dr ? 0.0 : 1.0 / l;
       sc[0] = l;
-      sc[1] = dr ? 0.0 : 1.0 / l;
+      sc[1] = inv;
+      if (two) {
+        const double2 s10 = M.lo(j + 1, j);
+        const double2 l10 = dr ? make_double2(0, 0)
+                               : zscale(make_double2(s10.x - sc[2], s10.y - sc[3]), inv);
+        const double piv1 = M.lo(j + 1, j + 1).x - sc[4] - (l10.x * l10.x + l10.y * l10.y);
+        const bool dr1 = (dsc[j + 1] == 0.0) || !(piv1 > drop_tol);
+        if (!dr1) pmin = fmin(pmin, piv1);
+        const double l1 = dr1 ? 0.0 : sqrt(piv1);
+        sc[5] = l10.x;
+        sc[6] = l10.y;
+        sc[7] = l1;
+        sc[8] = dr1 ? 0.0 : 1.0 / l1;
+      }
     }
     __syncthreads();
     const double ljj = sc[0], inv = sc[1];
     const bool drop = !(ljj > 0.0);
+    const double2 l10 = two ? make_double2(sc[5], sc[6]) : make_double2(0, 0);
+    const double l11 = two ? sc[7] : 0.0, inv1 = two ? sc[8] : 0.0;
+    const bool drop1 = !(l11 > 0.0);
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
       const int ii = p * kRowsPass + rl;
       if (g == 0 && ii >= 1 && ii < m) {
         const int i = j + ii;
-        M.set(i, j, drop ? make_double2(0, 0) : zscale(zsub(M.lo(i, j), dot[p]), inv));
+        const double2 lij = drop ? make_double2(0, 0) : zscale(zsub(M.lo(i, j), da[p]), inv);
+        M.set(i, j, lij);
+        if (ii >= 2) {
+          const double2 t = zsub(zsub(M.lo(i, j + 1), db[p]), zmul(lij, zconj(l10)));
+          M.set(i, j + 1, drop1 ? make_double2(0, 0) : zscale(t, inv1));
+        }
       }
     }
     if (tid == 0) {
       M.set(j, j, make_double2(ljj, 0.0));
       keep[j] = drop ? 0 : 1;
+      if (two) {
+        M.set(j + 1, j + 1, make_double2(l11, 0.0));
+        keep[j + 1] = drop1 ? 0 : 1;
+      }
     }
     __syncthreads();
   }
@@ -829,8 +877,8 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
   DKS_RR_STAMP(1);
 
   // ---- 2. Cholesky with column dropping
-  const double pmin = packed ? cholesky_drop(PackedLower{big}, nz, drop_tol, dsc, kept, red + 4, vv)
-                             : cholesky_drop(FullLower{Sg, nz}, nz, drop_tol, dsc, kept, red + 4, vv);
+  const double pmin = packed ? cholesky_drop(PackedLower{big}, nz, drop_tol, dsc, kept, red + 4, vv, xv)
+                             : cholesky_drop(FullLower{Sg, nz}, nz, drop_tol, dsc, kept, red + 4, vv, xv);
   if (tid == 0) {
     dinfo[1] = pmin;
     int r = 0;
