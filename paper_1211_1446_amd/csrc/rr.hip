@@ -309,50 +309,86 @@ __device__ double cholesky_drop(const Mat M, int n, double drop_tol, const doubl
 }
 
 // In-place inverse of the lower-triangular n x n matrix in M (nonzero real
-// diagonal), column by column from the right: for L = [l 0; x L2],
-// L^-1 = [1/l 0; -L2^-1 x / l  L2^-1].  Row groups as in the Cholesky; two
-// barriers per column.
+// diagonal), two columns per step from the right: for the columns a = j - 1,
+// b = j and L = [D 0; X L2] with D = [l_a 0; l_ba l_b] and X = [x_a x_b],
+//   L^-1 = [D^-1 0; -L2^-1 X D^-1  L2^-1],  D^-1 = [1/l_a 0; -l_ba/(l_a l_b) 1/l_b],
+// so that with Y = L2^-1 X (both columns in one pass over the inverted L2)
+// column b becomes -Y_b / l_b below the diagonal and column a
+// (Y_b l_ba / l_b - Y_a) / l_a.  Row groups as in the Cholesky; two barriers
+// per two columns.  `cola`, `colb`: LDS staging of x_a, x_b (n entries each);
+// `sl`: two doubles of LDS for l_ba.
 template <typename Mat>
-__device__ void trtri_lower(const Mat M, int n, double2 *col, double *dinv) {
+__device__ void trtri_lower(const Mat M, int n, double2 *cola, double2 *colb, double *dinv,
+                            double *sl) {
   const int tid = threadIdx.x, nt = blockDim.x, g = tid % kRowG, rl = tid / kRowG;
   // reciprocals of the diagonal, all at once (column j only changes its own)
   for (int j = tid; j < n; j += nt) dinv[j] = 1.0 / M.lo(j, j).x;
+  // the columns of the first step below their diagonal block: read across rows
+  // they are strided accesses, in global memory for large n
+  auto stage = [&](int jb) {   // pair (jb - 1, jb), or the single column 0
+    const int m = n - jb - 1;
+    if (jb >= 1) {
+      for (int k = tid; k < m; k += nt) {
+        cola[k] = M.lo(jb + 1 + k, jb - 1);
+        colb[k] = M.lo(jb + 1 + k, jb);
+      }
+      if (tid == 0) {
+        const double2 v = M.lo(jb, jb - 1);
+        sl[0] = v.x;
+        sl[1] = v.y;
+      }
+    } else {
+      for (int k = tid; k < m; k += nt) colb[k] = M.lo(jb + 1 + k, jb);
+    }
+  };
+  stage(n - 1);
   __syncthreads();
-  // column j below the diagonal (still L's) goes to LDS one step ahead: read
-  // across rows it is a strided access, in global memory for large n
-  // (the last column has nothing below its diagonal)
-  for (int j = n - 1; j >= 0; --j) {
-    const int m = n - j - 1;
-    const double inv = dinv[j];
-    double2 y[kPasses];
+  for (int j = n - 1; j >= 0; j -= 2) {
+    const bool two = j >= 1;
+    const int m = n - j - 1;   // rows of the inverted trailing block L2
+    const double ib = dinv[j], ia = two ? dinv[j - 1] : 0.0;
+    const double2 lba = two ? make_double2(sl[0], sl[1]) : make_double2(0, 0);
+    double2 ya[kPasses], yb[kPasses];
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
-      y[p] = make_double2(0, 0);
+      ya[p] = yb[p] = make_double2(0, 0);
       if (p * kRowsPass < m) {   // uniform
         const int ii = p * kRowsPass + rl;
-        double2 s = make_double2(0, 0), s1 = make_double2(0, 0);
+        double2 sa = make_double2(0, 0), sb = make_double2(0, 0);
         if (ii < m) {
-          int k = g;
-#pragma unroll 2
-          for (; k + kRowG <= ii; k += 2 * kRowG) {   // two chains in flight
-            s = zfma(M.lo(j + 1 + ii, j + 1 + k), col[k], s);
-            s1 = zfma(M.lo(j + 1 + ii, j + 1 + k + kRowG), col[k + kRowG], s1);
+          if (two) {
+            for (int k = g; k <= ii; k += kRowG) {
+              const double2 l = M.lo(j + 1 + ii, j + 1 + k);
+              sa = zfma(l, cola[k], sa);
+              sb = zfma(l, colb[k], sb);
+            }
+          } else {
+            for (int k = g; k <= ii; k += kRowG) sb = zfma(M.lo(j + 1 + ii, j + 1 + k), colb[k], sb);
           }
-          if (k <= ii) s = zfma(M.lo(j + 1 + ii, j + 1 + k), col[k], s);
         }
-        y[p] = gsum2<kRowG>(zadd(s, s1));
+        ya[p] = gsum2<kRowG>(sa);
+        yb[p] = gsum2<kRowG>(sb);
       }
     }
-    __syncthreads();   // column j and its diagonal are read everywhere
+    __syncthreads();   // the staged columns and l_ba are read everywhere
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
       const int ii = p * kRowsPass + rl;
-      if (g == 0 && ii < m) M.set(j + 1 + ii, j, zscale(y[p], -inv));
+      if (g == 0 && ii < m) {
+        M.set(j + 1 + ii, j, zscale(yb[p], -ib));
+        if (two) M.set(j + 1 + ii, j - 1, zscale(zsub(zscale(zmul(yb[p], lba), ib), ya[p]), ia));
+      }
     }
-    if (tid == 0) M.set(j, j, make_double2(inv, 0.0));
-    // the next column (j - 1) below its diagonal: rows j..n-1, untouched so far
-    if (j > 0)
-      for (int k = tid; k < n - j; k += nt) col[k] = M.lo(j + k, j - 1);
+    if (tid == 0) {
+      M.set(j, j, make_double2(ib, 0.0));
+      if (two) {
+        M.set(j - 1, j - 1, make_double2(ia, 0.0));
+        M.set(j, j - 1, zscale(lba, -ia * ib));
+      }
+    }
+    // the next pair's columns below their diagonal block: rows j - 1.. of
+    // columns j - 3, j - 2, untouched so far
+    if (j >= 2) stage(j - 2);
     __syncthreads();
   }
 }
@@ -912,7 +948,8 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     __syncthreads();
   }
   // (dd: free until the tridiagonalisation)
-  if (packed) trtri_lower(PackedLower{big}, r, vv, dd); else trtri_lower(FullLower{Sg, r}, r, vv, dd);
+  if (packed) trtri_lower(PackedLower{big}, r, vv, xv, dd, red + 16);
+  else trtri_lower(FullLower{Sg, r}, r, vv, xv, dd, red + 16);
   for (int e = tid; e < r * r; e += nt) {
     const int c = e / r, b = e - (e / r) * r;   // Lc[c r + b] = Li[b][c]
     Lc[e] = (b >= c) ? (packed ? PackedLower{big}.lo(b, c) : FullLower{Sg, r}.lo(b, c))
