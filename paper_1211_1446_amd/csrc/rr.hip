@@ -897,16 +897,20 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     dsc[i] = (!f && s > 0 && isfinite(s)) ? 1.0 / sqrt(s) : 0.0;
   }
   __syncthreads();
-#pragma unroll 4
-  for (int e = tid; e < (int)nn; e += nt) {
-    const int i = e / nz, j = e - (e / nz) * nz;
-    const double f = dsc[i] * dsc[j];
-    const double2 a1 = Ain[e], a2 = Ain[(size_t)j * nz + i];
-    Am[e] = make_double2(0.5 * f * (a1.x + a2.x), 0.5 * f * (a1.y - a2.y));
-    if (j <= i) {
-      const double2 s1 = Sin[e], s2 = Sin[(size_t)j * nz + i];
-      const double2 h = make_double2(0.5 * f * (s1.x + s2.x), 0.5 * f * (s1.y - s2.y));
-      if (packed) PackedLower{big}.set(i, j, h); else FullLower{Sg, nz}.set(i, j, h);
+  // one wave per row, lanes along it (no division of the flat index)
+  for (int i = tid >> 6; i < nz; i += nt >> 6) {
+    const double di = dsc[i];
+#pragma unroll 2
+    for (int j = tid & 63; j < nz; j += 64) {
+      const size_t e = (size_t)i * nz + j;
+      const double f = di * dsc[j];
+      const double2 a1 = Ain[e], a2 = Ain[(size_t)j * nz + i];
+      Am[e] = make_double2(0.5 * f * (a1.x + a2.x), 0.5 * f * (a1.y - a2.y));
+      if (j <= i) {
+        const double2 s1 = Sin[e], s2 = Sin[(size_t)j * nz + i];
+        const double2 h = make_double2(0.5 * f * (s1.x + s2.x), 0.5 * f * (s1.y - s2.y));
+        if (packed) PackedLower{big}.set(i, j, h); else FullLower{Sg, nz}.set(i, j, h);
+      }
     }
   }
   __syncthreads();
