@@ -227,7 +227,8 @@ def main():
         a, c = profiled(mode, 2), profiled(mode, 8)
         per_it = {
             f"k_gemm_ip.gram.{sfx}": (1, 8.0 * 2 * ip_pairs(nz) * K4),
-            f"k_gemm_up.{sfx}": (4, 8.0 * K4 * n * (2 * nz + 2 * (2 * n)) / 4),
+            # X and H X (m = n_Z rows), P and H P (2n rows): one paired launch each
+            f"k_gemm_up.{sfx}": (2, 8.0 * K4 * n * (2 * nz + 2 * (2 * n)) / 2),
             f"k_gemm_ip.{sfx}": (3, 8.0 * nproj * 4 * n * N),
         }
         for kname, spec in per_it.items():

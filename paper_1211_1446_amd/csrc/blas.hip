@@ -497,13 +497,18 @@ constexpr int kUpThreads = 64 * kUpMK / (16 * kUpKT);
 constexpr int kUpWaves = 6;   // minimum waves per SIMD asked of the compiler
 
 template <typename T>
-__global__ void __launch_bounds__(kUpThreads, kUpWaves) k_gemm_up_mfma(const typename CT<T>::c *__restrict__ A,
+__global__ void __launch_bounds__(kUpThreads, kUpWaves) k_gemm_up_mfma(const typename CT<T>::c *__restrict__ A1,
+                                                      const typename CT<T>::c *__restrict__ A2,
                                                       const int64_t *__restrict__ aoff, int m,
                                                       const double2 *__restrict__ V, int ldv,
                                                       int n, int64_t K,
-                                                      typename CT<T>::c *__restrict__ out,
+                                                      typename CT<T>::c *__restrict__ out1,
+                                                      typename CT<T>::c *__restrict__ out2,
                                                       int64_t ldo, T beta, double alpha) {
   using C = typename CT<T>::c;
+  // blockIdx.z selects one of two products with the same V (X and H X alike)
+  const typename CT<T>::c *__restrict__ A = blockIdx.z ? A2 : A1;
+  typename CT<T>::c *__restrict__ out = blockIdx.z ? out2 : out1;
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
   __shared__ T Vr[kUpICH * kUpMJ], Vi[kUpICH * kUpMJ];
@@ -588,17 +593,31 @@ __global__ void __launch_bounds__(kUpThreads, kUpWaves) k_gemm_up_mfma(const typ
 template <typename T>
 void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int ldv, int n,
              int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st, double alpha) {
+  gemm_up2<T>(A, nullptr, aoff, m, V, ldv, n, K, out, nullptr, ldo, beta, st, alpha, nullptr);
+}
+
+template <typename T>
+void gemm_up2(const cplx<T> *A1, const cplx<T> *A2, const int64_t *aoff, int m, const double2 *V,
+              int ldv, int n, int64_t K, cplx<T> *out1, cplx<T> *out2, int64_t ldo, double beta,
+              hipStream_t st, double alpha, const char *tag) {
   if (n <= 0 || K <= 0) return;
-  const char *name = sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32";
-  dim3 grid((unsigned)((K + kUpMK - 1) / kUpMK), (n + kUpMJ - 1) / kUpMJ);
-  DKS_LAUNCH(name, k_gemm_up_mfma<T>, grid, dim3(kUpThreads), 0, st, A, aoff, m, V, ldv, n, K,
-             out, ldo, (T)beta, alpha);
+  const char *name = tag ? tag : (sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32");
+  const bool two = A2 != nullptr;
+  dim3 grid((unsigned)((K + kUpMK - 1) / kUpMK), (n + kUpMJ - 1) / kUpMJ, two ? 2 : 1);
+  DKS_LAUNCH(name, k_gemm_up_mfma<T>, grid, dim3(kUpThreads), 0, st, A1, two ? A2 : A1, aoff, m, V,
+             ldv, n, K, out1, two ? out2 : out1, ldo, (T)beta, alpha);
   DKS_HIP(hipGetLastError());
 }
 template void gemm_up<double>(const double2 *, const int64_t *, int, const double2 *, int, int,
                               int64_t, double2 *, int64_t, double, hipStream_t, double);
 template void gemm_up<float>(const float2 *, const int64_t *, int, const double2 *, int, int,
                              int64_t, float2 *, int64_t, double, hipStream_t, double);
+template void gemm_up2<double>(const double2 *, const double2 *, const int64_t *, int,
+                               const double2 *, int, int, int64_t, double2 *, double2 *, int64_t,
+                               double, hipStream_t, double, const char *);
+template void gemm_up2<float>(const float2 *, const float2 *, const int64_t *, int, const double2 *,
+                              int, int, int64_t, float2 *, float2 *, int64_t, double, hipStream_t,
+                              double, const char *);
 
 // ---------------------------------------------------------------------------
 // residuals and norms

@@ -214,6 +214,13 @@ void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, 
 template <typename T>
 void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int ldv, int n,
              int64_t K, cplx<T> *out, int64_t ldo, double beta, hipStream_t st, double alpha = 1.0);
+// The same V applied to two row sets in one launch: out1 from A1 and out2 from
+// A2 (X and H X, P and H P); A2 = null is gemm_up.  `tag`: profiling name of the
+// launch (default k_gemm_up.f64 / .f32).
+template <typename T>
+void gemm_up2(const cplx<T> *A1, const cplx<T> *A2, const int64_t *aoff, int m, const double2 *V,
+              int ldv, int n, int64_t K, cplx<T> *out1, cplx<T> *out2, int64_t ldo, double beta,
+              hipStream_t st, double alpha = 1.0, const char *tag = nullptr);
 
 // R_j = HX_j - lambda_j X_j and ||R_j||^2 (FP64) for n columns of length K.
 template <typename T>

@@ -309,10 +309,9 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
   Solver &sv = *x.sv;
   const int nz = n + s.m + s.mp;
   const int nxt = 1 - s.cur;
-  gemm_up<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, sv.Vz.as<double2>(), n, n,
-             bk.K, bk.z(nxt, 0), bk.K, 0.0, x.st);
-  gemm_up<T>(bk.HZ[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, sv.Vz.as<double2>(), n, n,
-             bk.K, bk.hz(nxt, 0), bk.K, 0.0, x.st);
+  gemm_up2<T>(bk.Z[s.cur].template as<cplx<T>>(), bk.HZ[s.cur].template as<cplx<T>>(),
+              sv.off.as<int64_t>(), nz, sv.Vz.as<double2>(), n, n, bk.K, bk.z(nxt, 0),
+              bk.hz(nxt, 0), bk.K, 0.0, x.st);
   sv.lam.ensure(sizeof(double) * n);
   double *hl = sv.h_lam.as<double>(n);
   std::copy(s.lam.begin(), s.lam.end(), hl);
@@ -351,10 +350,9 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
     sv.Vp.ensure(sizeof(double2) * nvp);
     DKS_HIP(hipMemcpyAsync(sv.Vp.p, vp, sizeof(double2) * nvp, hipMemcpyHostToDevice, x.st));
     const int64_t *offyp = sv.off.as<int64_t>() + n;
-    gemm_up<T>(bk.Z[s.cur].template as<cplx<T>>(), offyp, nyp, sv.Vp.as<double2>(), mnew, mnew,
-               bk.K, bk.z(nxt, 2 * n), bk.K, 0.0, x.st);
-    gemm_up<T>(bk.HZ[s.cur].template as<cplx<T>>(), offyp, nyp, sv.Vp.as<double2>(), mnew, mnew,
-               bk.K, bk.hz(nxt, 2 * n), bk.K, 0.0, x.st);
+    gemm_up2<T>(bk.Z[s.cur].template as<cplx<T>>(), bk.HZ[s.cur].template as<cplx<T>>(), offyp,
+                nyp, sv.Vp.as<double2>(), mnew, mnew, bk.K, bk.z(nxt, 2 * n), bk.hz(nxt, 2 * n),
+                bk.K, 0.0, x.st);
     // P against the new X: P -= X (X^H P), HP -= HX (X^H P), in FP32 and, in
     // FP64, once the last basis was ill-conditioned.  The directions of P
     // formed above can lie mostly inside span X (the Rayleigh-Ritz rotates
@@ -369,10 +367,9 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
       sv.Wxp.ensure(sizeof(double2) * (size_t)n * mnew);
       gemm_ip<T>(bk.z(nxt, 0), nullptr, n, bk.z(nxt, 2 * n), nullptr, mnew, nullptr, bk.K,
                  sv.Wxp.as<double2>(), nullptr, mnew, sv.part, x.st);
-      gemm_up<T>(bk.z(nxt, 0), nullptr, n, sv.Wxp.as<double2>(), mnew, mnew, bk.K,
-                 bk.z(nxt, 2 * n), bk.K, 1.0, x.st, -1.0);
-      gemm_up<T>(bk.hz(nxt, 0), nullptr, n, sv.Wxp.as<double2>(), mnew, mnew, bk.K,
-                 bk.hz(nxt, 2 * n), bk.K, 1.0, x.st, -1.0);
+      gemm_up2<T>(bk.z(nxt, 0), bk.hz(nxt, 0), nullptr, n, sv.Wxp.as<double2>(), mnew, mnew, bk.K,
+                  bk.z(nxt, 2 * n), bk.hz(nxt, 2 * n), bk.K, 1.0, x.st, -1.0,
+                  sizeof(T) == 8 ? "k_gemm_up.portho.f64" : "k_gemm_up.portho.f32");
     }
   }
   s.mp = (mnew > 0 && s.m + s.mp > 0) ? mnew : 0;
