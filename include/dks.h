@@ -41,6 +41,7 @@ typedef int dks_status;
 #define DKS_EHIP       (-3)   /* a HIP runtime call failed */
 #define DKS_ECHOL      (-4)   /* Gram matrix of the start block not positive definite */
 #define DKS_ECOLLAPSE  (-5)   /* a Ritz value fell below -c^2 (variational collapse) */
+#define DKS_EINTERNAL  (-6)   /* unexpected host-side failure (e.g. a thread could not start) */
 #define DKS_WNOTCONV    1     /* iteration limit reached; outputs valid, residuals reported */
 
 typedef enum { DKS_FP64 = 0, DKS_FP32 = 1 } dks_prec;

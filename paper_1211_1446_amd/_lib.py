@@ -19,7 +19,7 @@ DKS_FP64, DKS_FP32 = 0, 1
 MODE_FP64, MODE_MIXED_FP32, MODE_MIXED_BF16GRAM = 0, 1, 2
 
 _STATUS = {0: "DKS_OK", -1: "DKS_EINVAL", -2: "DKS_ENOMEM", -3: "DKS_EHIP", -4: "DKS_ECHOL",
-           -5: "DKS_ECOLLAPSE", 1: "DKS_WNOTCONV"}
+           -5: "DKS_ECOLLAPSE", -6: "DKS_EINTERNAL", 1: "DKS_WNOTCONV"}
 
 
 class DksError(RuntimeError):

@@ -7,6 +7,8 @@
 #include <complex>
 #include <cstring>
 #include <map>
+#include <new>
+#include <stdexcept>
 
 #include "dks_internal.h"
 #include "fft_split.h"
@@ -16,6 +18,24 @@ namespace dks {
 static thread_local std::string g_err;
 void set_error(const std::string &m) { g_err = m; }
 const char *get_error() { return g_err.c_str(); }
+
+dks_status status_of_current_exception(std::string &msg) {
+  try {
+    throw;
+  } catch (const Error &e) {
+    msg = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    msg = "host allocation failed";
+    return DKS_ENOMEM;
+  } catch (const std::exception &e) {
+    msg = std::string("internal error: ") + e.what();
+    return DKS_EINTERNAL;
+  } catch (...) {
+    msg = "internal error: unknown exception";
+    return DKS_EINTERNAL;
+  }
+}
 
 void upload(DevBuf &b, const void *host, size_t bytes) {
   b.ensure(bytes);
@@ -393,14 +413,12 @@ dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, d
     }
     *out = B;
     return DKS_OK;
-  } catch (const Error &e) {
-    set_error(e.msg);
+  } catch (...) {
+    std::string msg;
+    const dks_status rc = status_of_current_exception(msg);
+    set_error(msg);
     delete B;
-    return e.code;
-  } catch (const std::exception &e) {
-    set_error(e.what());
-    delete B;
-    return DKS_ENOMEM;
+    return rc;
   }
 }
 

@@ -36,6 +36,24 @@ struct Error {
     if (!(cond)) throw ::dks::Error{(code), std::string(msg)}; \
   } while (0)
 
+// Status and message of the exception being handled (call inside a catch
+// block): dks::Error keeps its code, a failed host allocation is DKS_ENOMEM,
+// anything else DKS_EINTERNAL.
+dks_status status_of_current_exception(std::string &msg);
+
+// Runs f() (returning dks_status) and turns any exception into a status, with
+// the message recorded for dks_last_error: no exception leaves an entry point.
+template <typename F> dks_status guarded(F &&f) {
+  try {
+    return f();
+  } catch (...) {
+    std::string msg;
+    const dks_status rc = status_of_current_exception(msg);
+    set_error(msg);
+    return rc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // complex helpers
 // ---------------------------------------------------------------------------

@@ -476,8 +476,12 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     // value of X).  A larger fall means the projected pencil is no longer a
     // compression of H: the recurrences for HX and HP have drifted in an
     // ill-conditioned basis.  The step is then discarded (X is still that of
-    // the previous step) and the iteration restarts from X.
-    {
+    // the previous step) and the iteration restarts from X.  The argument holds
+    // for the positive band only (the Ritz values must stay above the negative
+    // band to be compared with its eigenvalues), so it guards LOBPCG-F; plain
+    // LOBPCG on the Dirac operator is left unguarded, and its fall into the
+    // negative band, the variational collapse of Sec. 3.1, is reported as such.
+    if (filt) {
       double rf = 0;
       for (double r : s.res) rf += r * r;
       rf = std::sqrt(rf);
@@ -504,7 +508,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
       double mx_prev = 0, mx = 0;
       for (double r : res_prev) mx_prev = std::max(mx_prev, r);
       for (double r : s.res) mx = std::max(mx, r);
-      if (!(mx <= 1e3 * mx_prev)) {
+      if (filt && !(mx <= 1e3 * mx_prev)) {
         s.cur = cur_prev;
         s.lam = lam_prev;
         s.res = res_prev;
@@ -701,7 +705,7 @@ void dks_default_opts(dks_solve_opts *o) {
 
 dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb, dks_prec prec,
                        void *stream) {
-  try {
+  return guarded([&]() -> dks_status {
     DKS_REQUIRE(b && X && HX && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
                 "bad argument");
     DKS_REQUIRE(X != HX, DKS_EINVAL, "X and HX must not overlap");
@@ -712,15 +716,12 @@ dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb, d
     else
       apply_h<float>(b, sys, (const float2 *)X, (float2 *)HX, nb, 0.0, 1.0, st, b->ws);
     return DKS_OK;
-  } catch (const Error &e) {
-    set_error(e.msg);
-    return e.code;
-  }
+  });
 }
 
 dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int nb, double C,
                             double Omega, dks_prec prec, void *stream) {
-  try {
+  return guarded([&]() -> dks_status {
     DKS_REQUIRE(b && Y && FY && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
                 "bad argument");
     DKS_REQUIRE(Y != FY, DKS_EINVAL, "Y and FY must not overlap");
@@ -742,16 +743,13 @@ dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int 
                      b->ws);
     }
     return DKS_OK;
-  } catch (const Error &e) {
-    set_error(e.msg);
-    return e.code;
-  }
+  });
 }
 
 dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lambda,
                              double *resnorms, const dks_solve_opts *opts, dks_solve_info *info,
                              void *stream) {
-  try {
+  return guarded([&]() -> dks_status {
     DKS_REQUIRE(b && X && lambda && sys >= 0 && sys < (int)b->sys.size(), DKS_EINVAL, "bad argument");
     dks_solve_opts o;
     if (opts) o = *opts; else dks_default_opts(&o);
@@ -761,17 +759,14 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
                                     (hipStream_t)stream, &solvers_of(b)->main, msg);
     if (rc != DKS_OK) set_error(msg);
     return rc;
-  } catch (const Error &e) {
-    set_error(e.msg);
-    return e.code;
-  }
+  });
 }
 
 dks_status dks_lobpcgf_solve_batch(dks_basis *b, int nsys, const int *sys, const int *n,
                                    void *const *X, double *const *lambda,
                                    double *const *resnorms, const dks_solve_opts *opts,
                                    dks_solve_info *info, void *stream) {
-  try {
+  return guarded([&]() -> dks_status {
     DKS_REQUIRE(b && nsys >= 0 && (nsys == 0 || (sys && n && X && lambda)), DKS_EINVAL,
                 "bad argument");
     for (int i = 0; i < nsys; ++i)
@@ -823,14 +818,20 @@ dks_status dks_lobpcgf_solve_batch(dks_basis *b, int nsys, const int *sys, const
           rc[i] = solve_one(b, sys[i], n[i], (double2 *)X[i], lambda[i],
                             resnorms ? resnorms[i] : nullptr, o, info ? &info[i] : nullptr,
                             bl.lane[l].st, &bl.lane[l].sv, msg[i]);
-        } catch (const Error &e) {
-          rc[i] = e.code;
-          msg[i] = e.msg;
+        } catch (...) {   // nothing may escape a lane thread
+          rc[i] = status_of_current_exception(msg[i]);
         }
       }
     };
+    // a lane thread that cannot start leaves its items to the running lanes
     std::vector<std::thread> th;
-    for (int l = 1; l < L; ++l) th.emplace_back(run_lane, l);
+    for (int l = 1; l < L; ++l) {
+      try {
+        th.emplace_back(run_lane, l);
+      } catch (...) {
+        break;
+      }
+    }
     run_lane(0);
     for (auto &t : th) t.join();
     // the caller's stream waits for every lane
@@ -850,10 +851,7 @@ dks_status dks_lobpcgf_solve_batch(dks_basis *b, int nsys, const int *sys, const
       }
     }
     return worst;
-  } catch (const Error &e) {
-    set_error(e.msg);
-    return e.code;
-  }
+  });
 }
 
 }  // extern "C"

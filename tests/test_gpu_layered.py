@@ -1,0 +1,143 @@
+"""The layered-crystal shape on the GPU: the 48 x 48 x 320 grid of the hexagonal
+five-atom cell (Sec. 4.1's layered Bi2Se3 stand-in) through apply_H, and the
+Rayleigh-Ritz at the subspace size of its 120-band block (n_Z = 360).
+
+* apply_H: the full 120-band block of one k-point in one call, as the solver
+  launches it, with sampled bands compared row by row against the oracle
+  (the 320-point z transform is split 16 x 20 and the 48-point plane axes 6 x 8);
+* n_Z = 360: a 120-column block (112 wanted + 8 buffer columns) on a system small
+  enough for the dense oracle, so that the 360 x 360 Rayleigh-Ritz of every
+  iteration is checked through the eigenvalues it produces;
+* the 120-band solve of k-point 0 against the oracle's matrix-free Algorithm 1
+  golden (tests/golden/layered_crystal_seed0_k0.json), and its time-reversal
+  partner -k, which must give the same spectrum.
+"""
+import dataclasses
+import json
+import os
+
+import numpy as np
+import pytest
+
+import sysgen
+from oracle import dks, lobpcgf
+from tests.gpu_helpers import perm_to_oracle, to_orc
+from tests.test_gpu_parity import TOL, _dk, free_dirac_part, row_errors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "layered_crystal_seed0_k0.json")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _layered(kidx):
+    s = sysgen.layered_crystal(0)
+    return dataclasses.replace(s, kpts=s.kpts[list(kidx)])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_h_layered_full_block_sampled(dev, prec):
+    """120 bands of k-point 5 of the 4 x 4 x 1 grid (k != 0, N ~ 17.0k)."""
+    dk = _dk()
+    s = _layered([5])
+    op = dks.DKSOperator(s)
+    b = dk.init_basis([s])
+    N, grid, mil = dk.basis_info(b, 0)
+    assert N == op.N and tuple(grid) == (48, 48, 320)
+    p = perm_to_oracle(mil, op.miller)
+    rng = np.random.default_rng(21)
+    n = 120
+    X = rng.standard_normal((n, 4, N)) + 1j * rng.standard_normal((n, 4, N))
+    ctype = torch.complex128 if prec == "fp64" else torch.complex64
+    Xd = torch.from_numpy(X).to(dev, ctype)
+    HXd = torch.empty_like(Xd)
+    print(f"[apply_H layered] nb={n} N={N} grid={grid} {prec}", flush=True)
+    dk.apply_H(b, 0, Xd, HXd)
+    torch.cuda.synchronize()
+    got = HXd.cpu().numpy().astype(np.complex128)
+    b.close()
+    Xs = Xd.cpu().numpy().astype(np.complex128)   # the block as the library saw it
+    for band in (0, 61, 119):
+        Xo = to_orc(Xs[band:band + 1], p)
+        ref = op.apply(Xo)
+        g = to_orc(got[band:band + 1], p)
+        kin = free_dirac_part(s, Xo)
+        err, errv = row_errors(g, ref), row_errors(g - kin, ref - kin)
+        print(f"  band {band}: row error {err:.2e}, potential part {errv:.2e}", flush=True)
+        assert err < TOL[prec][0], (band, err)
+        assert errv < TOL[prec][1], (band, errv)
+
+
+def _dense_case():
+    """Small dimer at Ecut 10 Ha (N ~ 1.5k): dense reference of 128 states."""
+    s = sysgen.tiny_dimer(1, ecut=10.0, grid=(24, 24, 24), n_bands=112)
+    op = dks.DKSOperator(s)
+    w = lobpcgf.lowest_positive(op.dense(), 128, s.c)[0]
+    return s, w
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rayleigh_ritz_at_nz_360(dev, mode):
+    """112 wanted bands + 8 buffer columns: every Rayleigh-Ritz step of the
+    solve works on n_Z = 360 (global-memory paths of the Cholesky, L^-1 and
+    the tridiagonal reduction); the 112 eigenvalues must match the dense
+    oracle to 1e-8 Ha."""
+    dk = _dk()
+    s, ref = _dense_case()
+    nw, buf = 112, 8
+    nb = nw + buf
+    b = dk.init_basis([s])
+    N, _, mil = dk.basis_info(b, 0)
+    X0 = np.zeros((nb, 4, N), dtype=np.complex128)
+    X0[:, :2] = sysgen.start_block(mil, s.lattice, s.kpts[0], nb, 17)
+    Xd = torch.from_numpy(X0).to(dev)
+    o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=buf)
+    print(f"[n_Z = 360] mode={mode} N={N} n={nb} buffer={buf}", flush=True)
+    lam, res, info, rc = dk.lobpcgf_solve(b, 0, nb, Xd, o)
+    b.close()
+    print(f"  iterations {info['iterations']}, max|r| {info['max_resnorm']:.2e}", flush=True)
+    assert rc == 0 and info["converged"] == 1, info
+    err = np.abs(np.asarray(lam[:nw]) - ref[:nw])
+    assert err.max() < 1e-8, err.max()
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden of the layered crystal not written")
+@pytest.mark.parametrize("mode", [0, 1])
+def test_layered_kpoint_solve_matches_golden(dev, mode):
+    """k-point 0 and its partner -k (k-point 15 of the shifted 4 x 4 x 1 grid)
+    solved in one batched call to 1e-8 Ha with 120 wanted bands (+ buffer):
+    eigenvalues against the oracle's golden, and E(k) = E(-k)."""
+    g = json.load(open(GOLDEN))
+    ref = np.array(g["eigenvalues"])
+    nw, buf = g["n_bands"], g["buffer_columns"]
+    nb = nw + buf
+    dk = _dk()
+    s0 = sysgen.layered_crystal(0)
+    assert np.allclose(s0.kpts[15], -s0.kpts[0])
+    s = _layered([0, 15])
+    b = dk.init_basis([s])
+    Xs = []
+    for i in range(2):
+        N, _, mil = dk.basis_info(b, i)
+        X0 = np.zeros((nb, 4, N), dtype=np.complex128)
+        X0[:, :2] = sysgen.start_block(mil, s.lattice, s.kpts[i], nb, 40 + i)
+        Xs.append(torch.from_numpy(X0).to(dev))
+    o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=buf)
+    print(f"[layered k, -k solve] mode={mode} n={nb} buffer={buf}", flush=True)
+    lams, ress, infos, rc = dk.lobpcgf_solve_batch(b, [0, 1], [nb, nb], Xs, o)
+    b.close()
+    for i in range(2):
+        print(f"  k {i}: iterations {infos[i]['iterations']}, max|r| {infos[i]['max_resnorm']:.2e}",
+              flush=True)
+    assert rc == 0, infos
+    for i in range(2):
+        err = np.abs(np.asarray(lams[i][:nw]) - ref[:nw])
+        assert err.max() < 1e-8, (i, err.max())
