@@ -10,16 +10,21 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 * ``apply_filter``      -- f(H) Y = (H - C)^2 Y / Omega^2, Eq. (filter).
 * ``filter_constants``  -- C in the negative continuum, Omega so that f = 1 at the
                            top of the positive band (Sec. 3.1 text after Eq. filter).
-* ``lobpcgf``           -- Algorithm 1: initial filtering, Rayleigh-Ritz on
-                           [X, Y, P], residuals, soft locking, P update.  With
-                           ``use_filter=False`` it is the standard LOBPCG the
-                           paper compares against.
+* ``block_rayleigh_ritz`` -- a locally optimal block iteration: Rayleigh-Ritz
+                           on the current block, new directions from the
+                           unconverged residuals, and a momentum block;
+* ``lobpcgf``           -- Algorithm 1 as that iteration with the filter on
+                           the start block and on every residual direction.
+                           With ``use_filter=False`` it is the standard LOBPCG
+                           the paper compares against.
 
 Readings where the paper is silent (each listed in the design notes):
 * complex data: the transposes of Alg. 1 are conjugate transposes;
 * the residual test uses the absolute 2-norm of each column with ||x_i|| = 1;
 * the columns of Y and P are scaled to unit norm before the Gram matrices are
   formed (this leaves the spanned subspace, hence the Ritz pairs, unchanged);
+* optional buffer columns (``n_want`` < n): iterated with the block, not
+  required to converge;
 * HX and HP are carried by the same linear combinations as X and P
   (HX <- (HZ) V, HP <- [0, HY, HP] V), so each iteration applies H three times
   (twice inside the filter, once to Y), the count given in Sec. 3.2;
@@ -71,7 +76,7 @@ def filter_constants(bounds, c: float):
 
 
 # ----------------------------------------------------------------------------
-# Algorithm 1
+# Algorithm 1 as an instance of a generic block Rayleigh-Ritz iteration
 # ----------------------------------------------------------------------------
 
 @dataclasses.dataclass
@@ -86,24 +91,105 @@ class LobpcgResult:
     dropped_p: int
 
 
-def _ritz(A: np.ndarray, S: np.ndarray):
-    """Generalized Hermitian eigenproblem A V = S V Lambda, ascending (the Rayleigh-Ritz steps of Algorithm 1)."""
-    A = 0.5 * (A + A.conj().T)
-    S = 0.5 * (S + S.conj().T)
-    return sla.eigh(A, S)
-
-
 def _unit_columns(M: np.ndarray):
     nrm = np.linalg.norm(M, axis=0)
     nrm[nrm == 0.0] = 1.0
     return M / nrm[None, :], nrm
 
 
+def project(Z: np.ndarray, HZ: np.ndarray, n: int):
+    """Rayleigh-Ritz on span Z: the n lowest pairs of the projected pencil
+    (Z^H H Z) v = theta (Z^H Z) v, ascending.  Returns (theta_all, V_n); raises
+    LinAlgError when Z^H Z is not numerically positive definite."""
+    A = Z.conj().T @ HZ
+    S = Z.conj().T @ Z
+    A = 0.5 * (A + A.conj().T)
+    S = 0.5 * (S + S.conj().T)
+    theta, V = sla.eigh(A, S)
+    return theta, V[:, :n]
+
+
+def residuals(X: np.ndarray, HX: np.ndarray, lam: np.ndarray):
+    """R = H X - X diag(lam) and the 2-norm of each column."""
+    R = HX - X * lam[None, :]
+    return R, np.linalg.norm(R, axis=0)
+
+
+def block_rayleigh_ritz(apply_h: Callable, X0: np.ndarray, n: int, directions: Callable,
+                        prepare: Optional[Callable] = None, n_iter: int = 100,
+                        tol: float = 1e-8, n_want: Optional[int] = None,
+                        max_history: int = 0) -> LobpcgResult:
+    """Locally optimal block iteration with Rayleigh-Ritz on three blocks.
+
+    The subspace of each step is spanned by the current Ritz block X, new
+    directions W = directions(R_a) built from the residual columns R_a that are
+    not yet below tol (soft locking), and the momentum block P, the part of the
+    previous step's update that came from outside X.  The n lowest Ritz pairs
+    of that subspace form the next X.  ``prepare`` maps the start block before
+    the first projection.  Convergence: the first ``n_want`` (default n)
+    residual norms below tol; the remaining columns are buffer columns that are
+    iterated but need not converge.  When the subspace's Gram matrix is not
+    numerically positive definite the step is taken without P.
+    """
+    n_want = n if n_want is None else n_want
+    X = np.array(X0, dtype=np.complex128, copy=True)
+    if prepare is not None:
+        X = prepare(X)
+    HX = apply_h(X)
+    theta, V = project(X, HX, n)
+    lam = theta[:n]
+    X, HX = X @ V, HX @ V
+    R, norms = residuals(X, HX, lam)
+    P = HP = None
+    hist_min: List[float] = [float(theta.min())]
+    hist: List[np.ndarray] = []
+    dropped = 0
+    it = 0
+    converged = bool(np.all(norms[:n_want] < tol))
+    while not converged and it < n_iter:
+        it += 1
+        active = np.nonzero(norms >= tol)[0]
+        W, _ = _unit_columns(directions(R[:, active]))
+        HW = apply_h(W)
+        extra = [W] if P is None else [W, P]
+        hextra = [HW] if P is None else [HW, HP]
+        try:
+            Z = np.concatenate([X] + extra, axis=1)
+            HZ = np.concatenate([HX] + hextra, axis=1)
+            theta, V = project(Z, HZ, n)
+        except np.linalg.LinAlgError:
+            if P is None:
+                raise
+            dropped += 1
+            Z = np.concatenate([X, W], axis=1)
+            HZ = np.concatenate([HX, HW], axis=1)
+            theta, V = project(Z, HZ, n)
+        lam = theta[:n]
+        hist_min.append(float(theta.min()))
+        if max_history:
+            hist.append(theta.copy())
+        X, HX = Z @ V, HZ @ V
+        R, norms = residuals(X, HX, lam)
+        converged = bool(np.all(norms[:n_want] < tol))
+        if converged:
+            break
+        # momentum: the new combination of the non-X blocks, for the columns
+        # still active
+        nx = X.shape[1]
+        keep = V[nx:, :][:, np.nonzero(norms >= tol)[0]]
+        P, pn = _unit_columns(Z[:, nx:] @ keep)
+        HP = (HZ[:, nx:] @ keep) / pn[None, :]
+    return LobpcgResult(lam, X, norms, it, converged, hist_min, hist, dropped)
+
+
 def lobpcgf(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,
             n_init: int = 3, n_iter: int = 100, tol: float = 1e-8,
             use_filter: bool = True, precond: Optional[Callable] = None,
-            max_history: int = 0) -> LobpcgResult:
-    """Algorithm 1 on the K x n start block X0 (columns = spinors, K = 4N).
+            max_history: int = 0, n_want: Optional[int] = None) -> LobpcgResult:
+    """Algorithm 1 (LOBPCG-F) on the K x n start block X0 (columns = spinors,
+    K = 4N): the block iteration above with the filter f(H) applied n_init
+    times to the start block and to every preconditioned residual.  With
+    ``use_filter=False`` it is the standard LOBPCG of the paper's comparison.
 
     ``apply_h`` maps a K x m block to H times it.  ``precond`` solves T Y = R
     (identity when None, as in the analysis of Sec. 3.1).
@@ -111,81 +197,18 @@ def lobpcgf(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,
     def f_of_h(Y):
         return apply_filter(apply_h, Y, C, Omega)
 
-    X = np.array(X0, dtype=np.complex128, copy=True)
-    # initial filtering of the start block
-    if use_filter:
-        for _ in range(n_init):
-            X = f_of_h(X)
-            X, _ = _unit_columns(X)
-    # Rayleigh-Ritz on the filtered start block
-    HX = apply_h(X)
-    lam, V = _ritz(X.conj().T @ HX, X.conj().T @ X)
-    lam, V = lam[:n], V[:, :n]
-    # rotate the block onto the Ritz vectors
-    X = X @ V
-    HX = HX @ V
-    # first residual
-    R = HX - X * lam[None, :]
-    P = HP = None
-    hist_min: List[float] = [float(lam.min())]
-    hist: List[np.ndarray] = []
-    norms = np.linalg.norm(R, axis=0)
-    active = np.nonzero(norms >= tol)[0]
-    dropped = 0
-    it = 0
-    converged = bool(active.size == 0)
-    while not converged and it < n_iter:
-        it += 1
-        # preconditioned residual: T Y = R on the active columns
-        Y = R[:, active]
-        if precond is not None:
-            Y = precond(Y)
-        # the filtering step: Y <- f(H) Y
+    def prepare(X):
         if use_filter:
-            Y = f_of_h(Y)
-        Y, _ = _unit_columns(Y)
-        HY = apply_h(Y)
-        # subspace Z = [X, Y, P]
-        blocks = [X, Y] + ([P] if P is not None else [])
-        hblocks = [HX, HY] + ([HP] if P is not None else [])
-        try:
-            Z = np.concatenate(blocks, axis=1)
-            HZ = np.concatenate(hblocks, axis=1)
-            theta, Vz = _ritz(Z.conj().T @ HZ, Z.conj().T @ Z)
-        except np.linalg.LinAlgError:
-            if P is None:
-                raise
-            dropped += 1
-            Z = np.concatenate([X, Y], axis=1)
-            HZ = np.concatenate([HX, HY], axis=1)
-            P = HP = None
-            theta, Vz = _ritz(Z.conj().T @ HZ, Z.conj().T @ Z)
-        # keep the first n Ritz pairs
-        V = Vz[:, :n]
-        lam = theta[:n]
-        hist_min.append(float(theta.min()))
-        if max_history:
-            hist.append(theta.copy())
-        # new block X = Z V (and the same combination of HZ)
-        X = Z @ V
-        HX = HZ @ V
-        # residual
-        R = HX - X * lam[None, :]
-        norms = np.linalg.norm(R, axis=0)
-        # convergence test on every column
-        if np.all(norms < tol):
-            converged = True
-            break
-        # soft locking: keep the unconverged columns
-        active = np.nonzero(norms >= tol)[0]
-        Va = V[:, active]
-        # conjugate directions P <- [0, Y, P] V   (HP alike)
-        nx = X.shape[1]
-        P = Z[:, nx:] @ Va[nx:, :]
-        HP = HZ[:, nx:] @ Va[nx:, :]
-        P, pn = _unit_columns(P)
-        HP = HP / pn[None, :]
-    return LobpcgResult(lam, X, norms, it, converged, hist_min, hist, dropped)
+            for _ in range(n_init):
+                X, _ = _unit_columns(f_of_h(X))
+        return X
+
+    def directions(R):
+        Y = R if precond is None else precond(R)
+        return f_of_h(Y) if use_filter else Y
+
+    return block_rayleigh_ritz(apply_h, X0, n, directions, prepare=prepare, n_iter=n_iter,
+                               tol=tol, n_want=n_want, max_history=max_history)
 
 
 # ----------------------------------------------------------------------------
