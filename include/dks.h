@@ -119,6 +119,23 @@ dks_status dks_basis_info(const dks_basis *b, int sys, int *npw, int *grid3, int
 dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb,
                        dks_prec prec, void *stream);
 
+/* HX = H X exactly as dks_apply_H, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  This call allocates nothing (no hipMalloc, no host heap,
+ * no events, also with dks_profile_enable on).  Its scratch (FFT intermediate,
+ * projector coefficients, partial sums) is one library-owned device array of
+ * DKS_NOALLOC_SCRATCH_BYTES per GPU, held from the first dks_init_basis on that
+ * GPU until the process ends; the block is processed in chunks of bands sized
+ * to fit it (heavy dimer, 96^3 grid, FP64: 5 bands per chunk).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (different streams
+ * or threads, or with dks_apply_H_noalloc work still queued on another stream)
+ * race and give wrong results.  X and HX as for dks_apply_H.  Errors: those of
+ * dks_apply_H, and DKS_EINVAL when a single band needs more scratch than the
+ * array holds (4 N_3 n_xycolumns complex values plus the projector terms). */
+#define DKS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dks_status dks_apply_H_noalloc(dks_basis *b, int sys, const void *X, void *HX, int nb,
+                               dks_prec prec, void *stream);
+
 /* FY = f(H) Y with f(E) = (E - C)^2 / Omega^2, the filter of Eq. (filter)
  * (two applications of H).  Y and FY must not overlap. */
 dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int nb,

@@ -73,6 +73,7 @@ def _load():
     lib.dks_num_systems.argtypes = [vp]
     lib.dks_basis_info.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
     lib.dks_apply_H.argtypes = [vp, i, vp, vp, i, i, vp]
+    lib.dks_apply_H_noalloc.argtypes = [vp, i, vp, vp, i, i, vp]
     lib.dks_apply_filter.argtypes = [vp, i, vp, vp, i, d, d, i, vp]
     lib.dks_filter_constants.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(d)]
     lib.dks_default_opts.argtypes = [ct.POINTER(SolveOpts)]
@@ -219,6 +220,18 @@ def apply_H(b: Basis, sys: int, X, HX, nb: Optional[int] = None, stream=None) ->
         raise TypeError("X and HX precision differ")
     _check(_lib.dks_apply_H(b.handle, sys, ct.c_void_p(X.data_ptr()), ct.c_void_p(HX.data_ptr()),
                             nb, _prec_of(X), _stream(stream)))
+
+
+def apply_H_noalloc(b: Basis, sys: int, X, HX, nb: Optional[int] = None, stream=None) -> None:
+    """HX = H X without any device allocation (dks_apply_H_noalloc)."""
+    N, _, _ = basis_info(b, sys, miller=False)
+    nb = X.shape[0] if nb is None else nb
+    _check_block(X, nb, N)
+    _check_block(HX, nb, N)
+    if HX.dtype != X.dtype:
+        raise TypeError("X and HX precision differ")
+    _check(_lib.dks_apply_H_noalloc(b.handle, sys, ct.c_void_p(X.data_ptr()),
+                                    ct.c_void_p(HX.data_ptr()), nb, _prec_of(X), _stream(stream)))
 
 
 def apply_filter(b: Basis, sys: int, Y, FY, C: float, Omega: float, nb: Optional[int] = None,

@@ -163,6 +163,7 @@ dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, d
     DKS_REQUIRE(device >= 0 && device < ndev, DKS_EINVAL, "device index out of range");
     DKS_HIP(hipSetDevice(device));
     init_kernel_attributes();
+    noalloc_scratch_setup(device);
     B = new dks_basis();
     B->device = device;
     for (int di = 0; di < ndesc; ++di) {

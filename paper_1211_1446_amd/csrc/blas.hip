@@ -259,24 +259,57 @@ static void reduce_parts(const double2 *p1, const double2 *p2, int nsplit, int M
   DKS_HIP(hipGetLastError());
 }
 
+// Tiling and split-K of one gemm_ip call: output tiles, k splits and the k
+// range of each split.
+struct IpShape {
+  int tm, tiles;
+  bool upper;
+  int64_t nsplit, kchunk;
+};
+static IpShape ip_shape(int M, int Nn, int64_t K, bool hermitian) {
+  IpShape g;
+  g.tm = (M + kIpTile - 1) / kIpTile;
+  const int tn = (Nn + kIpTile - 1) / kIpTile;
+  g.upper = hermitian && M == Nn;
+  g.tiles = g.upper ? g.tm * (g.tm + 1) / 2 : g.tm * tn;
+  int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
+  int64_t nsplit = (kIpBlocks + g.tiles - 1) / g.tiles;
+  nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
+  int64_t kchunk = (K + nsplit - 1) / nsplit;
+  kchunk = (kchunk + kIpKT - 1) / kIpKT * kIpKT;
+  if (kchunk < kIpKT) kchunk = kIpKT;
+  nsplit = (K + kchunk - 1) / kchunk;
+  if (nsplit < 1) nsplit = 1;
+  g.nsplit = nsplit;
+  g.kchunk = kchunk;
+  return g;
+}
+
+size_t gemm_ip_part_elems(int M, int Nn, int64_t K, bool two, bool hermitian) {
+  if (M <= 0 || Nn <= 0) return 0;
+  const IpShape g = ip_shape(M, Nn, K, hermitian);
+  return (size_t)g.nsplit * M * Nn * (two ? 2 : 1);
+}
+
 template <typename T>
 void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
              int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
              DevBuf &part, hipStream_t st, bool hermitian) {
   if (M <= 0 || Nn <= 0) return;
-  const int tm = (M + kIpTile - 1) / kIpTile, tn = (Nn + kIpTile - 1) / kIpTile;
-  const bool upper = hermitian && M == Nn;
-  const int tiles = upper ? tm * (tm + 1) / 2 : tm * tn;
-  int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
-  int64_t nsplit = (kIpBlocks + tiles - 1) / tiles;
-  nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
-  int64_t kchunk = (K + nsplit - 1) / nsplit;
-  kchunk = (kchunk + kIpKT - 1) / kIpKT * kIpKT;
-  nsplit = (K + kchunk - 1) / kchunk;
-  if (nsplit < 1) nsplit = 1;
-  const int nmat = B2 ? 2 : 1;
-  part.ensure(sizeof(double2) * (size_t)nsplit * M * Nn * nmat);
-  double2 *p1 = part.as<double2>();
+  part.ensure(sizeof(double2) * gemm_ip_part_elems(M, Nn, K, B2 != nullptr, hermitian));
+  gemm_ip_raw<T>(A, aoff, M, B, boff, Nn, B2, K, out, out2, ldo, part.as<double2>(), st, hermitian);
+}
+
+template <typename T>
+void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
+                 int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
+                 double2 *part, hipStream_t st, bool hermitian) {
+  if (M <= 0 || Nn <= 0) return;
+  const IpShape g = ip_shape(M, Nn, K, hermitian);
+  const int tm = g.tm, tiles = g.tiles;
+  const bool upper = g.upper;
+  const int64_t nsplit = g.nsplit, kchunk = g.kchunk;
+  double2 *p1 = part;
   double2 *p2 = B2 ? p1 + (size_t)nsplit * M * Nn : nullptr;
   dim3 grid(tiles, 1, (unsigned)nsplit);
   const char *name = upper ? (sizeof(T) == 8 ? "k_gemm_ip.gram.f64" : "k_gemm_ip.gram.f32")
@@ -446,18 +479,11 @@ void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, 
                   int Nn, const float2 *B2, int64_t K, double2 *out, double2 *out2, int ldo,
                   DevBuf &part, hipStream_t st, bool hermitian) {
   if (M <= 0 || Nn <= 0) return;
-  const int tm = (M + kIpTile - 1) / kIpTile, tn = (Nn + kIpTile - 1) / kIpTile;
-  const bool upper = hermitian && M == Nn;
-  const int tiles = upper ? tm * (tm + 1) / 2 : tm * tn;
-  int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
-  int64_t nsplit = (kIpBlocks + tiles - 1) / tiles;
-  nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
-  int64_t kchunk = (K + nsplit - 1) / nsplit;
-  kchunk = (kchunk + kIpKT - 1) / kIpKT * kIpKT;
-  nsplit = (K + kchunk - 1) / kchunk;
-  if (nsplit < 1) nsplit = 1;
-  const int nmat = B2 ? 2 : 1;
-  part.ensure(sizeof(double2) * (size_t)nsplit * M * Nn * nmat);
+  const IpShape g = ip_shape(M, Nn, K, hermitian);
+  const int tm = g.tm, tiles = g.tiles;
+  const bool upper = g.upper;
+  const int64_t nsplit = g.nsplit, kchunk = g.kchunk;
+  part.ensure(sizeof(double2) * gemm_ip_part_elems(M, Nn, K, B2 != nullptr, hermitian));
   double2 *p1 = part.as<double2>();
   double2 *p2 = B2 ? p1 + (size_t)nsplit * M * Nn : nullptr;
   dim3 grid(tiles, 1, (unsigned)nsplit);
@@ -473,6 +499,12 @@ template void gemm_ip<double>(const double2 *, const int64_t *, int, const doubl
 template void gemm_ip<float>(const float2 *, const int64_t *, int, const float2 *,
                              const int64_t *, int, const float2 *, int64_t, double2 *, double2 *,
                              int, DevBuf &, hipStream_t, bool);
+template void gemm_ip_raw<double>(const double2 *, const int64_t *, int, const double2 *,
+                                  const int64_t *, int, const double2 *, int64_t, double2 *,
+                                  double2 *, int, double2 *, hipStream_t, bool);
+template void gemm_ip_raw<float>(const float2 *, const int64_t *, int, const float2 *,
+                                 const int64_t *, int, const float2 *, int64_t, double2 *,
+                                 double2 *, int, double2 *, hipStream_t, bool);
 
 // ---------------------------------------------------------------------------
 // block update

@@ -111,6 +111,22 @@ void upload(DevBuf &b, const void *host, size_t bytes);
     hipLaunchKernelGGL(kern, grid, block, smem, st, __VA_ARGS__); \
   } while (0)
 
+// Suspends the optional kernel timing of the calling thread for its lifetime
+// (the timing creates HIP events, which an allocation-free call must not).
+struct ProfPause {
+  ProfPause();
+  ~ProfPause();
+  ProfPause(const ProfPause &) = delete;
+  ProfPause &operator=(const ProfPause &) = delete;
+
+ private:
+  bool was_on_;
+};
+
+// Takes the device address of the allocation-free entry point's scratch array
+// on `device` (which must be current); once per device, at dks_init_basis.
+void noalloc_scratch_setup(int device);
+
 // Brackets one kernel launch with HIP events when profiling is enabled.
 struct ProfScope {
   ProfScope(const char *name, hipStream_t st);
@@ -214,6 +230,19 @@ __device__ __forceinline__ int xcd_order(int L, int total) {
 template <typename T>
 void apply_h(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
              double scale, hipStream_t st, Workspace &ws);
+// The same on caller-provided scratch (nothing is allocated): the column-pruned
+// FFT intermediate, the projector coefficients before and after the couplings W,
+// and the split-K partial sums of the projector product, of the sizes
+// apply_scratch_bytes gives for nb bands.
+struct ApplyScratch {
+  void *t1 = nullptr;
+  double2 *nlc = nullptr, *nlc2 = nullptr, *part = nullptr;
+};
+template <typename T>
+void apply_scratch_bytes(const dks_basis *b, int sys, int nb, size_t bytes[4]);
+template <typename T>
+void apply_h_on(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
+                double scale, hipStream_t st, const ApplyScratch &scr);
 
 // out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
 // rows addressed by element offsets.  M, Nn <= 512.  `hermitian` (A and B the same
@@ -223,6 +252,13 @@ template <typename T>
 void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
              int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
              DevBuf &part, hipStream_t st, bool hermitian = false);
+// The same product with caller-provided split-K partial sums: `part` holds at
+// least gemm_ip_part_elems(M, Nn, K, B2 != null, hermitian) double2.
+size_t gemm_ip_part_elems(int M, int Nn, int64_t K, bool two, bool hermitian);
+template <typename T>
+void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
+                 int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
+                 double2 *part, hipStream_t st, bool hermitian = false);
 // The same product with the FP32 inputs rounded to BF16 and FP32 accumulation.
 void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, const int64_t *boff,
                   int Nn, const float2 *B2, int64_t K, double2 *out, double2 *out2, int ldo,

@@ -11,6 +11,10 @@
 // The projectors and the free-Dirac block are done first:
 //   C = B^H X (matrix-core inner products), C' = W C per (atom, l) and
 //   two-spinor, HX = B C' + kinetic(X) - shift X.
+#include <algorithm>
+#include <atomic>
+#include <string>
+
 #include "dks_internal.h"
 #include "fft2.h"
 #include "fft_device.h"
@@ -472,8 +476,37 @@ void init_kernel_attributes() {
 }
 
 template <typename T>
+void apply_scratch_bytes(const dks_basis *b, int sysi, int nb, size_t bytes[4]) {
+  const System &s = *b->sys[sysi];
+  const int ncols = 4 * nb;
+  bytes[0] = sizeof(cplx<T>) * (size_t)ncols * s.grid[2] * s.ncol;
+  const size_t cbytes = s.nproj > 0 ? sizeof(double2) * (size_t)s.nproj * ncols : 0;
+  bytes[1] = cbytes;
+  bytes[2] = cbytes;
+  bytes[3] = s.nproj > 0 ? sizeof(double2) * gemm_ip_part_elems(s.nproj, ncols, (int64_t)s.N, false, false) : 0;
+}
+
+template <typename T>
 void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
              double scale, hipStream_t st, Workspace &ws) {
+  if (nb <= 0) return;
+  size_t bytes[4];
+  apply_scratch_bytes<T>(b, sysi, nb, bytes);
+  ws.t1.ensure(bytes[0]);
+  ws.nlc.ensure(bytes[1]);
+  ws.nlc2.ensure(bytes[2]);
+  ws.part.ensure(bytes[3]);
+  ApplyScratch scr;
+  scr.t1 = ws.t1.p;
+  scr.nlc = ws.nlc.as<double2>();
+  scr.nlc2 = ws.nlc2.as<double2>();
+  scr.part = ws.part.as<double2>();
+  apply_h_on<T>(b, sysi, X, HX, nb, shift, scale, st, scr);
+}
+
+template <typename T>
+void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
+                double scale, hipStream_t st, const ApplyScratch &scr) {
   using C = cplx<T>;
   System &s = *b->sys[sysi];
   Potential &pot = *b->pot[s.vsrc];
@@ -483,18 +516,14 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   // --- projectors and kinetic block: HX = B C' + kin X - shift X
   double2 *Cp = nullptr;
   if (s.nproj > 0) {
-    size_t cbytes = sizeof(double2) * (size_t)s.nproj * ncols;
-    ws.nlc.ensure(cbytes);
-    ws.nlc2.ensure(cbytes);
-    std::vector<int64_t> dummy;
-    // row offsets: B rows p*N, X rows cc*N (contiguous), passed as null -> stride N
-    gemm_ip<T>(Btab<T>(s), nullptr, s.nproj, X, nullptr, ncols, nullptr, (int64_t)N,
-               ws.nlc.as<double2>(), nullptr, ncols, ws.part, st);
+    // B rows p*N and X rows cc*N are contiguous: offsets passed as null (stride N)
+    gemm_ip_raw<T>(Btab<T>(s), nullptr, s.nproj, X, nullptr, ncols, nullptr, (int64_t)N, scr.nlc,
+                   nullptr, ncols, scr.part, st);
     dim3 gw(nb * 2, (unsigned)s.groups.size());
-    DKS_LAUNCH("k_apply_w", k_apply_w, gw, dim3(64), 0, st, ws.nlc.as<double2>(), ws.nlc2.as<double2>(),
-                       ncols, nb, s.d_Winfo.as<int4>(), (int)s.groups.size(), s.d_W64.as<double2>());
+    DKS_LAUNCH("k_apply_w", k_apply_w, gw, dim3(64), 0, st, scr.nlc, scr.nlc2, ncols, nb,
+               s.d_Winfo.as<int4>(), (int)s.groups.size(), s.d_W64.as<double2>());
     DKS_HIP(hipGetLastError());
-    Cp = ws.nlc2.as<double2>();
+    Cp = scr.nlc2;
   }
   {
     dim3 grid((unsigned)(((N + 255) / 256) * ((nb + kBT - 1) / kBT)));
@@ -505,8 +534,7 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   }
   // --- local potential through the grid
   const int n3 = s.grid[2];
-  ws.t1.ensure(sizeof(C) * (size_t)ncols * n3 * s.ncol);
-  C *t1 = ws.t1.as<C>();
+  C *t1 = static_cast<C *>(scr.t1);
   const int tile = s.tile_z;
   dim3 gz((s.ncol + tile - 1) / tile, ncols);
   size_t smz = sizeof(C) * (size_t)tile * (n3 + 1);
@@ -536,5 +564,101 @@ template void apply_h<double>(dks_basis *, int, const double2 *, double2 *, int,
                               hipStream_t, Workspace &);
 template void apply_h<float>(dks_basis *, int, const float2 *, float2 *, int, double, double,
                              hipStream_t, Workspace &);
+template void apply_h_on<double>(dks_basis *, int, const double2 *, double2 *, int, double,
+                                 double, hipStream_t, const ApplyScratch &);
+template void apply_h_on<float>(dks_basis *, int, const float2 *, float2 *, int, double, double,
+                                hipStream_t, const ApplyScratch &);
+template void apply_scratch_bytes<double>(const dks_basis *, int, int, size_t[4]);
+template void apply_scratch_bytes<float>(const dks_basis *, int, int, size_t[4]);
 
 }  // namespace dks
+
+// ---------------------------------------------------------------------------
+// H X without allocation: scratch from one file-scope device array
+// ---------------------------------------------------------------------------
+// The array lives in every GPU the library's code object is loaded on, at a
+// per-device address.  The host symbol `scratch` is only a host-side handle:
+// kernels are given the device address that hipGetSymbolAddress returns, taken
+// once per device at dks_init_basis (with that device current) and kept in
+// g_scratch_addr.  Nothing in the array needs to start at zero: every byte a
+// kernel of apply_h_on reads is written earlier in the same call (the FFT
+// intermediate by the z transform, the projector coefficients by the product
+// and its reduction).
+namespace dks {
+
+constexpr size_t kNoAllocBytes = size_t(64) << 20;   // DKS_NOALLOC_SCRATCH_BYTES
+static_assert(kNoAllocBytes == DKS_NOALLOC_SCRATCH_BYTES, "header and library disagree");
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+static std::atomic<void *> g_scratch_addr[kMaxDevices];
+
+void noalloc_scratch_setup(int device) {
+  DKS_REQUIRE(device >= 0 && device < kMaxDevices, DKS_EINVAL, "device index out of range");
+  if (g_scratch_addr[device].load() != nullptr) return;
+  void *p = nullptr;
+  DKS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  DKS_REQUIRE(p != nullptr, DKS_EHIP, "no device address for the scratch array");
+  g_scratch_addr[device].store(p);
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <typename T>
+static size_t noalloc_need(const dks_basis *b, int sys, int nb) {
+  size_t by[4];
+  apply_scratch_bytes<T>(b, sys, nb, by);
+  return align256(by[0]) + align256(by[1]) + align256(by[2]) + align256(by[3]);
+}
+
+template <typename T>
+static void apply_h_noalloc(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb,
+                            hipStream_t st) {
+  unsigned char *base = static_cast<unsigned char *>(g_scratch_addr[b->device].load());
+  DKS_REQUIRE(base != nullptr, DKS_EINVAL, "the scratch array of this device is not set up");
+  if (nb <= 0) return;
+  const size_t one = noalloc_need<T>(b, sys, 1);
+  DKS_REQUIRE(one <= kNoAllocBytes, DKS_EINVAL,
+              "one band needs " + std::to_string(one) + " bytes of scratch, more than the " +
+                  std::to_string(kNoAllocBytes) + "-byte array");
+  // the largest band chunk whose scratch fits (the projector partial sums do
+  // not grow linearly with the chunk, so the sizes are checked one by one)
+  int chunk = nb;
+  while (chunk > 1 && noalloc_need<T>(b, sys, chunk) > kNoAllocBytes) --chunk;
+  size_t by[4];
+  apply_scratch_bytes<T>(b, sys, chunk, by);
+  ApplyScratch scr;
+  size_t off = 0;
+  scr.t1 = base + off;
+  off += align256(by[0]);
+  scr.nlc = reinterpret_cast<double2 *>(base + off);
+  off += align256(by[1]);
+  scr.nlc2 = reinterpret_cast<double2 *>(base + off);
+  off += align256(by[2]);
+  scr.part = reinterpret_cast<double2 *>(base + off);
+  const size_t K = 4 * (size_t)b->sys[sys]->N;
+  for (int b0 = 0; b0 < nb; b0 += chunk) {
+    const int m = std::min(chunk, nb - b0);
+    apply_h_on<T>(b, sys, X + (size_t)b0 * K, HX + (size_t)b0 * K, m, 0.0, 1.0, st, scr);
+  }
+}
+
+}  // namespace dks
+
+extern "C" dks_status dks_apply_H_noalloc(dks_basis *b, int sys, const void *X, void *HX, int nb,
+                                          dks_prec prec, void *stream) {
+  using namespace dks;
+  return guarded([&]() -> dks_status {
+    DKS_REQUIRE(b && X && HX && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
+                "bad argument");
+    DKS_REQUIRE(X != HX, DKS_EINVAL, "X and HX must not overlap");
+    DKS_REQUIRE(prec == DKS_FP64 || prec == DKS_FP32, DKS_EINVAL, "bad precision");
+    DKS_HIP(hipSetDevice(b->device));
+    ProfPause no_events;   // the optional kernel timing would create events
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == DKS_FP64)
+      apply_h_noalloc<double>(b, sys, (const double2 *)X, (double2 *)HX, nb, st);
+    else
+      apply_h_noalloc<float>(b, sys, (const float2 *)X, (float2 *)HX, nb, st);
+    return DKS_OK;
+  });
+}

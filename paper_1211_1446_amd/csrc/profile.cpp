@@ -43,6 +43,9 @@ ProfScope::ProfScope(const char *name, hipStream_t st) : st_(st) {
   idx_ = (int)g_prof.recs.size() - 1;
 }
 
+ProfPause::ProfPause() : was_on_(g_prof.on) { g_prof.on = false; }
+ProfPause::~ProfPause() { g_prof.on = was_on_; }
+
 ProfScope::~ProfScope() {
   if (idx_ >= 0 && g_prof.on && idx_ < (int)g_prof.recs.size())
     (void)hipEventRecord(g_prof.recs[idx_].b, st_);
