@@ -313,6 +313,35 @@ class DKSOperator:
                 out[:, pair[1]] += v[:, :, 1] @ bm.T
         return out
 
+    def apply_ksso(self, X: np.ndarray) -> np.ndarray:
+        """Two-component Kohn-Sham operator with spin-orbit coupling (the KSSO
+        module of the paper's Table 1, solved there with standard LOBPCG):
+        |k+G|^2/2 + V_loc + V_2 on a block X of shape (n, 2, N) (band,
+        spin, planewave), matrix-free.  V_2 is the same separable spin-orbit
+        operator that acts on each two-spinor of the DKS operator (Eq. HGH);
+        densely this is ``pauli_dense``."""
+        X = np.asarray(X, dtype=np.complex128)
+        kin = 0.5 * np.einsum("ij,ij->i", self.q, self.q)
+        out = X * kin[None, None, :]
+        F = np.zeros((2,) + self.grid, dtype=np.complex128)
+        for b in range(X.shape[0]):
+            F[...] = 0.0
+            for s in range(2):
+                F[s][self.slot] = X[b, s]
+            f = sfft.ifftn(F, axes=(1, 2, 3), norm="forward", workers=_WORKERS)
+            f *= self.v[None]
+            G = sfft.fftn(f, axes=(1, 2, 3), norm="forward", workers=_WORKERS)
+            for s in range(2):
+                out[b, s] += G[s][self.slot]
+        for g, bm, w in self.groups:
+            np_ = bm.shape[1]
+            coef = np.einsum("gp,bsg->bsp", bm.conj(), X)        # (n, 2, np)
+            v = np.stack([coef[:, 0, :], coef[:, 1, :]], axis=-1).reshape(X.shape[0], 2 * np_)
+            v = (v @ w.T).reshape(X.shape[0], np_, 2)
+            out[:, 0] += v[:, :, 0] @ bm.T
+            out[:, 1] += v[:, :, 1] @ bm.T
+        return out
+
     # ---- bounds for the filter constants ----------------------------------
     def spectrum_bounds(self):
         """Analytic bounds used to place the filter (reading of Sec. 3.1, no value given).

@@ -28,6 +28,10 @@ Readings where the paper is silent (each listed in the design notes):
 * HX and HP are carried by the same linear combinations as X and P
   (HX <- (HZ) V, HP <- [0, HY, HP] V), so each iteration applies H three times
   (twice inside the filter, once to Y), the count given in Sec. 3.2;
+* the n Ritz pairs kept are the n lowest above the mid-gap -c^2 (Alg. 1's
+  output is the lowest part of the positive band; in exact arithmetic every
+  Ritz value of the filtered subspace lies there, and the selection keeps a
+  rounding-level negative-band direction from entering X);
 * if the Gram matrix of [X, Y, P] is not numerically positive definite, the
   iteration retries the Rayleigh-Ritz step without P.
 """
@@ -97,16 +101,20 @@ def _unit_columns(M: np.ndarray):
     return M / nrm[None, :], nrm
 
 
-def project(Z: np.ndarray, HZ: np.ndarray, n: int):
-    """Rayleigh-Ritz on span Z: the n lowest pairs of the projected pencil
-    (Z^H H Z) v = theta (Z^H Z) v, ascending.  Returns (theta_all, V_n); raises
-    LinAlgError when Z^H Z is not numerically positive definite."""
+def project(Z: np.ndarray, HZ: np.ndarray, n: int, floor: float = -math.inf):
+    """Rayleigh-Ritz on span Z: the n lowest pairs above ``floor`` of the
+    projected pencil (Z^H H Z) v = theta (Z^H Z) v, ascending.  Returns
+    (theta_all, theta_n, V_n); raises LinAlgError when Z^H Z is not numerically
+    positive definite or fewer than n Ritz values lie above the floor."""
     A = Z.conj().T @ HZ
     S = Z.conj().T @ Z
     A = 0.5 * (A + A.conj().T)
     S = 0.5 * (S + S.conj().T)
     theta, V = sla.eigh(A, S)
-    return theta, V[:, :n]
+    keep = np.nonzero(theta > floor)[0][:n]
+    if keep.size < n:
+        raise np.linalg.LinAlgError("fewer than n Ritz values above the floor")
+    return theta, theta[keep], V[:, keep]
 
 
 def residuals(X: np.ndarray, HX: np.ndarray, lam: np.ndarray):
@@ -118,7 +126,7 @@ def residuals(X: np.ndarray, HX: np.ndarray, lam: np.ndarray):
 def block_rayleigh_ritz(apply_h: Callable, X0: np.ndarray, n: int, directions: Callable,
                         prepare: Optional[Callable] = None, n_iter: int = 100,
                         tol: float = 1e-8, n_want: Optional[int] = None,
-                        max_history: int = 0) -> LobpcgResult:
+                        max_history: int = 0, floor: float = -math.inf) -> LobpcgResult:
     """Locally optimal block iteration with Rayleigh-Ritz on three blocks.
 
     The subspace of each step is spanned by the current Ritz block X, new
@@ -129,15 +137,15 @@ def block_rayleigh_ritz(apply_h: Callable, X0: np.ndarray, n: int, directions: C
     the first projection.  Convergence: the first ``n_want`` (default n)
     residual norms below tol; the remaining columns are buffer columns that are
     iterated but need not converge.  When the subspace's Gram matrix is not
-    numerically positive definite the step is taken without P.
+    numerically positive definite the step is taken without P.  Only Ritz
+    values above ``floor`` are kept.
     """
     n_want = n if n_want is None else n_want
     X = np.array(X0, dtype=np.complex128, copy=True)
     if prepare is not None:
         X = prepare(X)
     HX = apply_h(X)
-    theta, V = project(X, HX, n)
-    lam = theta[:n]
+    theta, lam, V = project(X, HX, n, floor)
     X, HX = X @ V, HX @ V
     R, norms = residuals(X, HX, lam)
     P = HP = None
@@ -156,15 +164,14 @@ def block_rayleigh_ritz(apply_h: Callable, X0: np.ndarray, n: int, directions: C
         try:
             Z = np.concatenate([X] + extra, axis=1)
             HZ = np.concatenate([HX] + hextra, axis=1)
-            theta, V = project(Z, HZ, n)
+            theta, lam, V = project(Z, HZ, n, floor)
         except np.linalg.LinAlgError:
             if P is None:
                 raise
             dropped += 1
             Z = np.concatenate([X, W], axis=1)
             HZ = np.concatenate([HX, HW], axis=1)
-            theta, V = project(Z, HZ, n)
-        lam = theta[:n]
+            theta, lam, V = project(Z, HZ, n, floor)
         hist_min.append(float(theta.min()))
         if max_history:
             hist.append(theta.copy())
@@ -185,14 +192,17 @@ def block_rayleigh_ritz(apply_h: Callable, X0: np.ndarray, n: int, directions: C
 def lobpcgf(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,
             n_init: int = 3, n_iter: int = 100, tol: float = 1e-8,
             use_filter: bool = True, precond: Optional[Callable] = None,
-            max_history: int = 0, n_want: Optional[int] = None) -> LobpcgResult:
+            max_history: int = 0, n_want: Optional[int] = None,
+            half_gap: Optional[float] = None) -> LobpcgResult:
     """Algorithm 1 (LOBPCG-F) on the K x n start block X0 (columns = spinors,
     K = 4N): the block iteration above with the filter f(H) applied n_init
     times to the start block and to every preconditioned residual.  With
     ``use_filter=False`` it is the standard LOBPCG of the paper's comparison.
 
     ``apply_h`` maps a K x m block to H times it.  ``precond`` solves T Y = R
-    (identity when None, as in the analysis of Sec. 3.1).
+    (identity when None, as in the analysis of Sec. 3.1).  ``half_gap`` (c^2 in
+    the shifted units) places the mid-gap below which LOBPCG-F keeps no Ritz
+    value; None keeps the n lowest.
     """
     def f_of_h(Y):
         return apply_filter(apply_h, Y, C, Omega)
@@ -207,8 +217,12 @@ def lobpcgf(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,
         Y = R if precond is None else precond(R)
         return f_of_h(Y) if use_filter else Y
 
+    # LOBPCG-F keeps the n lowest Ritz pairs of the positive band, above the
+    # mid-gap -c^2 (in exact arithmetic every Ritz value of the filtered
+    # subspace is there); plain LOBPCG keeps the n lowest of all
+    floor = -half_gap if use_filter and half_gap is not None else -math.inf
     return block_rayleigh_ritz(apply_h, X0, n, directions, prepare=prepare, n_iter=n_iter,
-                               tol=tol, n_want=n_want, max_history=max_history)
+                               tol=tol, n_want=n_want, max_history=max_history, floor=floor)
 
 
 # ----------------------------------------------------------------------------
@@ -253,4 +267,5 @@ def solve(op, n: int, X0: Optional[np.ndarray] = None, phi0: Optional[np.ndarray
     X0 = np.asarray(X0).reshape(X0.shape[0], -1).T
     if C is None or Omega is None:
         C, Omega = filter_constants(op.spectrum_bounds(), op.c)
+    kw.setdefault("half_gap", op.c * op.c)
     return lobpcgf(block_apply(op), X0, n, C, Omega, **kw)

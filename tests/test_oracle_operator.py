@@ -346,3 +346,19 @@ def test_spectrum_bounds_enclose_the_bands():
     neg = w[w <= -s.c ** 2]
     assert pos.max() <= C_ + Om + 1e-9
     assert neg.min() < C_ < neg.max() or abs(C_ - 0.5 * (neg.min() + neg.max())) < 50
+
+
+def test_ksso_apply_matches_its_dense_form():
+    """The two-component KSSO operator (Table 1), matrix-free, equals its dense
+    form |q|^2/2 + V_loc + V_2 (pauli_dense, itself pinned by the
+    nonrelativistic limit of the DKS operator) on random blocks, and is
+    Hermitian."""
+    s = _tiny_with_everything(c=sysgen.C_LIGHT)
+    op = dks.DKSOperator(s)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((3, 2, op.N)) + 1j * rng.standard_normal((3, 2, op.N))
+    H2 = op.pauli_dense()
+    ref = (H2 @ X.reshape(3, -1).T).T.reshape(3, 2, op.N)
+    got = op.apply_ksso(X)
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref))
+    assert np.max(np.abs(H2 - H2.conj().T)) < 1e-12
