@@ -56,6 +56,15 @@ typedef enum {
                                  the matrix cores */
 } dks_mode;
 
+/* Which operator a solve works on (the modules of the paper's Table 1). */
+typedef enum {
+  DKS_MODEL_DKS = 0,   /* four-component Dirac-Kohn-Sham, blocks [n][4][N] (LOBPCG-F) */
+  DKS_MODEL_KSSO = 1   /* two-component Kohn-Sham with spin-orbit coupling, |k+G|^2/2 +
+                          V_loc + V_2, blocks [n][2][N] (phi_up, phi_dn); solved by
+                          standard LOBPCG, the paper's comparison: use_filter and
+                          kinetic_balance are ignored */
+} dks_model;
+
 /* One (atom, l) block of separable projectors of Eq. (HGH): couplings of the
  * j = l + 1/2 channel (d_plus) and of the j = l - 1/2 channel (d_minus), each a
  * real symmetric n_rad x n_rad matrix (row-major, Ha).  Radial functions are
@@ -136,6 +145,15 @@ dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb,
 dks_status dks_apply_H_noalloc(dks_basis *b, int sys, const void *X, void *HX, int nb,
                                dks_prec prec, void *stream);
 
+/* HX = H_KSSO X for the two-component operator of the KSSO module (Table 1):
+ * |k+G|^2/2 per planewave, the local potential through the same zero-padded
+ * FFTs, and the same separable spin-orbit projectors V_2 that act on each
+ * two-spinor of the Dirac operator (Eq. (HGH)).  No energy shift (the
+ * nonrelativistic operator has no rest mass).  X and HX are device blocks
+ * [nb][2][N] of precision `prec` that must not overlap. */
+dks_status dks_apply_H_ksso(dks_basis *b, int sys, const void *X, void *HX, int nb,
+                            dks_prec prec, void *stream);
+
 /* FY = f(H) Y with f(E) = (E - C)^2 / Omega^2, the filter of Eq. (filter)
  * (two applications of H).  Y and FY must not overlap. */
 dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int nb,
@@ -173,6 +191,8 @@ typedef struct {
                            up the wanted columns when a near-degenerate group straddles
                            the wanted count (the rate of column i is set by the gap to
                            eigenvalue n + 1, not i + 1).  Default 0 */
+  int model;            /* dks_model: the operator solved; blocks are [n][4][N] for
+                           DKS_MODEL_DKS, [n][2][N] for DKS_MODEL_KSSO.  Default DKS */
 } dks_solve_opts;
 
 typedef struct {

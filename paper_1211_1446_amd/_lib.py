@@ -17,6 +17,7 @@ _LIBPATH = os.path.join(_HERE, "libdks.so")
 
 DKS_FP64, DKS_FP32 = 0, 1
 MODE_FP64, MODE_MIXED_FP32, MODE_MIXED_BF16GRAM = 0, 1, 2
+MODEL_DKS, MODEL_KSSO = 0, 1
 
 _STATUS = {0: "DKS_OK", -1: "DKS_EINVAL", -2: "DKS_ENOMEM", -3: "DKS_EHIP", -4: "DKS_ECHOL",
            -5: "DKS_ECOLLAPSE", -6: "DKS_EINTERNAL", 1: "DKS_WNOTCONV"}
@@ -46,7 +47,7 @@ class SolveOpts(ct.Structure):
                 ("n_iter", ct.c_int), ("tol", ct.c_double), ("mode", ct.c_int),
                 ("mixed_tol", ct.c_double), ("mixed_iter", ct.c_int),
                 ("kinetic_balance", ct.c_int), ("use_filter", ct.c_int),
-                ("iter_ms", ct.POINTER(ct.c_double)), ("n_buffer", ct.c_int)]
+                ("iter_ms", ct.POINTER(ct.c_double)), ("n_buffer", ct.c_int), ("model", ct.c_int)]
 
 
 class SolveInfo(ct.Structure):
@@ -74,6 +75,7 @@ def _load():
     lib.dks_basis_info.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
     lib.dks_apply_H.argtypes = [vp, i, vp, vp, i, i, vp]
     lib.dks_apply_H_noalloc.argtypes = [vp, i, vp, vp, i, i, vp]
+    lib.dks_apply_H_ksso.argtypes = [vp, i, vp, vp, i, i, vp]
     lib.dks_apply_filter.argtypes = [vp, i, vp, vp, i, d, d, i, vp]
     lib.dks_filter_constants.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(d)]
     lib.dks_default_opts.argtypes = [ct.POINTER(SolveOpts)]
@@ -203,11 +205,11 @@ def _prec_of(t) -> int:
     raise TypeError("blocks must be complex128 or complex64")
 
 
-def _check_block(t, nb, N):
+def _check_block(t, nb, N, ncomp=4):
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("blocks must be contiguous device tensors")
-    if t.numel() < nb * 4 * N:
-        raise ValueError("block smaller than nb x 4 x N")
+    if t.numel() < nb * ncomp * N:
+        raise ValueError(f"block smaller than nb x {ncomp} x N")
 
 
 def apply_H(b: Basis, sys: int, X, HX, nb: Optional[int] = None, stream=None) -> None:
@@ -232,6 +234,18 @@ def apply_H_noalloc(b: Basis, sys: int, X, HX, nb: Optional[int] = None, stream=
         raise TypeError("X and HX precision differ")
     _check(_lib.dks_apply_H_noalloc(b.handle, sys, ct.c_void_p(X.data_ptr()),
                                     ct.c_void_p(HX.data_ptr()), nb, _prec_of(X), _stream(stream)))
+
+
+def apply_H_ksso(b: Basis, sys: int, X, HX, nb: Optional[int] = None, stream=None) -> None:
+    """HX = H_KSSO X, the two-component operator (dks_apply_H_ksso); [nb][2][N]."""
+    N, _, _ = basis_info(b, sys, miller=False)
+    nb = X.shape[0] if nb is None else nb
+    _check_block(X, nb, N, 2)
+    _check_block(HX, nb, N, 2)
+    if HX.dtype != X.dtype:
+        raise TypeError("X and HX precision differ")
+    _check(_lib.dks_apply_H_ksso(b.handle, sys, ct.c_void_p(X.data_ptr()),
+                                 ct.c_void_p(HX.data_ptr()), nb, _prec_of(X), _stream(stream)))
 
 
 def apply_filter(b: Basis, sys: int, Y, FY, C: float, Omega: float, nb: Optional[int] = None,
@@ -286,11 +300,11 @@ def lobpcgf_solve(b: Basis, sys: int, n: int, X, opts: Optional[SolveOpts] = Non
     if X.dtype != torch.complex128:
         raise TypeError("X must be complex128")
     N, _, _ = basis_info(b, sys, miller=False)
-    _check_block(X, n, N)
+    o = opts if opts is not None else default_opts()
+    _check_block(X, n, N, 2 if o.model == MODEL_KSSO else 4)
     lam = np.zeros(n)
     res = np.zeros(n)
     info = SolveInfo()
-    o = opts if opts is not None else default_opts()
     if iter_ms is not None:
         need = o.n_iter + (o.mixed_iter if o.mode != MODE_FP64 else 0)
         if iter_ms.dtype != np.float64 or iter_ms.size < need or not iter_ms.flags.c_contiguous:
@@ -313,11 +327,12 @@ def lobpcgf_solve_batch(b: Basis, systems: Sequence[int], ns: Sequence[int], Xs:
     nsys = len(systems)
     if not (len(ns) == nsys and len(Xs) == nsys):
         raise ValueError("systems, ns and Xs must have the same length")
+    ncomp = 2 if (opts is not None and opts.model == MODEL_KSSO) else 4
     for s_, n_, X in zip(systems, ns, Xs):
         if X.dtype != torch.complex128:
             raise TypeError("every block must be complex128")
         N, _, _ = basis_info(b, int(s_), miller=False)
-        _check_block(X, int(n_), N)
+        _check_block(X, int(n_), N, ncomp)
     lams = [np.zeros(int(n_)) for n_ in ns]
     ress = [np.zeros(int(n_)) for n_ in ns]
     infos = (SolveInfo * max(nsys, 1))()

@@ -62,7 +62,9 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
                                                  const typename CT<T>::c *__restrict__ B2,
                                                  int64_t K, int64_t kchunk, int tm, int upper,
                                                  double2 *__restrict__ part,
-                                                 double2 *__restrict__ part2) {
+                                                 double2 *__restrict__ part2,
+                                                 const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
   using C = typename CT<T>::c;
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
@@ -220,8 +222,10 @@ constexpr int kRedWaves = 16;
 __global__ void __launch_bounds__(64 * kRedWaves)
     k_reduce_part(const double2 *__restrict__ part, const double2 *__restrict__ part2, int nsplit,
                   int M, int Nn, int upper, double2 *__restrict__ out, double2 *__restrict__ out2,
-                  int ldo) {
+                  int ldo, const int *__restrict__ skip) {
   __shared__ double2 red[kRedWaves][64];
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
+
   const int nel = M * Nn;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int e = blockIdx.x * 64 + lane;
@@ -252,10 +256,11 @@ __global__ void __launch_bounds__(64 * kRedWaves)
 }
 
 static void reduce_parts(const double2 *p1, const double2 *p2, int nsplit, int M, int Nn, bool upper,
-                         double2 *out, double2 *out2, int ldo, hipStream_t st) {
+                         double2 *out, double2 *out2, int ldo, hipStream_t st,
+                         const int *skip = nullptr) {
   const int nel = M * Nn * (p2 ? 2 : 1);
   DKS_LAUNCH("k_reduce_part", k_reduce_part, dim3((nel + 63) / 64), dim3(64 * kRedWaves), 0, st, p1,
-             p2, nsplit, M, Nn, (int)upper, out, out2, ldo);
+             p2, nsplit, M, Nn, (int)upper, out, out2, ldo, skip);
   DKS_HIP(hipGetLastError());
 }
 
@@ -294,16 +299,17 @@ size_t gemm_ip_part_elems(int M, int Nn, int64_t K, bool two, bool hermitian) {
 template <typename T>
 void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
              int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
-             DevBuf &part, hipStream_t st, bool hermitian) {
+             DevBuf &part, hipStream_t st, bool hermitian, const int *skip) {
   if (M <= 0 || Nn <= 0) return;
   part.ensure(sizeof(double2) * gemm_ip_part_elems(M, Nn, K, B2 != nullptr, hermitian));
-  gemm_ip_raw<T>(A, aoff, M, B, boff, Nn, B2, K, out, out2, ldo, part.as<double2>(), st, hermitian);
+  gemm_ip_raw<T>(A, aoff, M, B, boff, Nn, B2, K, out, out2, ldo, part.as<double2>(), st, hermitian,
+                 skip);
 }
 
 template <typename T>
 void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
                  int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
-                 double2 *part, hipStream_t st, bool hermitian) {
+                 double2 *part, hipStream_t st, bool hermitian, const int *skip) {
   if (M <= 0 || Nn <= 0) return;
   const IpShape g = ip_shape(M, Nn, K, hermitian);
   const int tm = g.tm, tiles = g.tiles;
@@ -316,9 +322,9 @@ void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B,
                            : (sizeof(T) == 8 ? "k_gemm_ip.f64" : "k_gemm_ip.f32");
   auto kern = B2 ? k_gemm_ip<T, true> : k_gemm_ip<T, false>;
   DKS_LAUNCH(name, kern, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk, tm,
-             (int)upper, p1, p2);
+             (int)upper, p1, p2, skip);
   DKS_HIP(hipGetLastError());
-  reduce_parts(p1, p2, (int)nsplit, M, Nn, upper, out, out2, ldo, st);
+  reduce_parts(p1, p2, (int)nsplit, M, Nn, upper, out, out2, ldo, st, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -495,16 +501,16 @@ void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, 
 
 template void gemm_ip<double>(const double2 *, const int64_t *, int, const double2 *,
                               const int64_t *, int, const double2 *, int64_t, double2 *,
-                              double2 *, int, DevBuf &, hipStream_t, bool);
+                              double2 *, int, DevBuf &, hipStream_t, bool, const int *);
 template void gemm_ip<float>(const float2 *, const int64_t *, int, const float2 *,
                              const int64_t *, int, const float2 *, int64_t, double2 *, double2 *,
-                             int, DevBuf &, hipStream_t, bool);
+                             int, DevBuf &, hipStream_t, bool, const int *);
 template void gemm_ip_raw<double>(const double2 *, const int64_t *, int, const double2 *,
                                   const int64_t *, int, const double2 *, int64_t, double2 *,
-                                  double2 *, int, double2 *, hipStream_t, bool);
+                                  double2 *, int, double2 *, hipStream_t, bool, const int *);
 template void gemm_ip_raw<float>(const float2 *, const int64_t *, int, const float2 *,
                                  const int64_t *, int, const float2 *, int64_t, double2 *,
-                                 double2 *, int, double2 *, hipStream_t, bool);
+                                 double2 *, int, double2 *, hipStream_t, bool, const int *);
 
 // ---------------------------------------------------------------------------
 // block update
@@ -536,7 +542,10 @@ __global__ void __launch_bounds__(kUpThreads, kUpWaves) k_gemm_up_mfma(const typ
                                                       int n, int64_t K,
                                                       typename CT<T>::c *__restrict__ out1,
                                                       typename CT<T>::c *__restrict__ out2,
-                                                      int64_t ldo, T beta, double alpha) {
+                                                      int64_t ldo, T beta, double alpha,
+                                                      const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
+
   using C = typename CT<T>::c;
   // blockIdx.z selects one of two products with the same V (X and H X alike)
   const typename CT<T>::c *__restrict__ A = blockIdx.z ? A2 : A1;
@@ -631,13 +640,13 @@ void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int
 template <typename T>
 void gemm_up2(const cplx<T> *A1, const cplx<T> *A2, const int64_t *aoff, int m, const double2 *V,
               int ldv, int n, int64_t K, cplx<T> *out1, cplx<T> *out2, int64_t ldo, double beta,
-              hipStream_t st, double alpha, const char *tag) {
+              hipStream_t st, double alpha, const char *tag, const int *skip) {
   if (n <= 0 || K <= 0) return;
   const char *name = tag ? tag : (sizeof(T) == 8 ? "k_gemm_up.f64" : "k_gemm_up.f32");
   const bool two = A2 != nullptr;
   dim3 grid((unsigned)((K + kUpMK - 1) / kUpMK), (n + kUpMJ - 1) / kUpMJ, two ? 2 : 1);
   DKS_LAUNCH(name, k_gemm_up_mfma<T>, grid, dim3(kUpThreads), 0, st, A1, two ? A2 : A1, aoff, m, V,
-             ldv, n, K, out1, two ? out2 : out1, ldo, (T)beta, alpha);
+             ldv, n, K, out1, two ? out2 : out1, ldo, (T)beta, alpha, skip);
   DKS_HIP(hipGetLastError());
 }
 template void gemm_up<double>(const double2 *, const int64_t *, int, const double2 *, int, int,
@@ -646,10 +655,10 @@ template void gemm_up<float>(const float2 *, const int64_t *, int, const double2
                              int64_t, float2 *, int64_t, double, hipStream_t, double);
 template void gemm_up2<double>(const double2 *, const double2 *, const int64_t *, int,
                                const double2 *, int, int, int64_t, double2 *, double2 *, int64_t,
-                               double, hipStream_t, double, const char *);
+                               double, hipStream_t, double, const char *, const int *);
 template void gemm_up2<float>(const float2 *, const float2 *, const int64_t *, int, const double2 *,
                               int, int, int64_t, float2 *, float2 *, int64_t, double, hipStream_t,
-                              double, const char *);
+                              double, const char *, const int *);
 
 // ---------------------------------------------------------------------------
 // residuals and norms
@@ -675,7 +684,9 @@ __global__ void __launch_bounds__(256) k_residual(const typename CT<T>::c *__res
                                                   const typename CT<T>::c *__restrict__ HX,
                                                   const double *__restrict__ lam, int64_t K,
                                                   typename CT<T>::c *__restrict__ R,
-                                                  double *__restrict__ part, int nchunk) {
+                                                  double *__restrict__ part, int nchunk,
+                                                  const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
   using C = typename CT<T>::c;
   const int j = blockIdx.y;
   const T l = (T)lam[j];
@@ -713,7 +724,8 @@ __global__ void __launch_bounds__(256) k_norm2(const typename CT<T>::c *__restri
 }
 
 __global__ void k_sum_rows(const double *__restrict__ part, int n, int nchunk,
-                           double *__restrict__ out) {
+                           double *__restrict__ out, const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double s = 0;
@@ -723,21 +735,21 @@ __global__ void k_sum_rows(const double *__restrict__ part, int n, int nchunk,
 
 template <typename T>
 void residual(const cplx<T> *X, const cplx<T> *HX, const double *lam, int n, int64_t K,
-              cplx<T> *R, double *norm2, DevBuf &part, hipStream_t st) {
+              cplx<T> *R, double *norm2, DevBuf &part, hipStream_t st, const int *skip) {
   if (n <= 0) return;
   int nchunk = (int)((K + kRedChunk - 1) / kRedChunk);
   part.ensure(sizeof(double) * (size_t)n * nchunk);
   DKS_LAUNCH((sizeof(T) == 8 ? "k_residual.f64" : "k_residual.f32"), k_residual<T>, dim3(nchunk, n), dim3(256), 0, st, X, HX, lam, K, R,
-                     part.as<double>(), nchunk);
+                     part.as<double>(), nchunk, skip);
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH("k_sum_rows", k_sum_rows, dim3((n + 63) / 64), dim3(64), 0, st, part.as<double>(), n,
-                     nchunk, norm2);
+                     nchunk, norm2, skip);
   DKS_HIP(hipGetLastError());
 }
 template void residual<double>(const double2 *, const double2 *, const double *, int, int64_t,
-                               double2 *, double *, DevBuf &, hipStream_t);
+                               double2 *, double *, DevBuf &, hipStream_t, const int *);
 template void residual<float>(const float2 *, const float2 *, const double *, int, int64_t,
-                              float2 *, double *, DevBuf &, hipStream_t);
+                              float2 *, double *, DevBuf &, hipStream_t, const int *);
 
 template <typename T>
 void col_norm2(const cplx<T> *X, int n, int64_t K, double *norm2, DevBuf &part, hipStream_t st) {
@@ -748,7 +760,7 @@ void col_norm2(const cplx<T> *X, int n, int64_t K, double *norm2, DevBuf &part, 
                      nchunk);
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH("k_sum_rows", k_sum_rows, dim3((n + 63) / 64), dim3(64), 0, st, part.as<double>(), n,
-                     nchunk, norm2);
+                     nchunk, norm2, nullptr);
   DKS_HIP(hipGetLastError());
 }
 template void col_norm2<double>(const double2 *, int, int64_t, double *, DevBuf &, hipStream_t);

@@ -226,10 +226,16 @@ __device__ __forceinline__ int xcd_order(int L, int total) {
 // ---------------------------------------------------------------------------
 // launchers (all asynchronous on `st`)
 // ---------------------------------------------------------------------------
-// HX = scale * ((H - shift) X) for nb bands, precision T.
+// HX = scale * ((H - shift) X) for nb bands, precision T.  ncomp = 4: the
+// four-component Dirac operator on blocks [nb][4][N]; ncomp = 2: the
+// two-component Kohn-Sham operator with spin-orbit coupling (|q|^2/2 + V_loc +
+// V_2) on blocks [nb][2][N].
+// `skip` (optional, device): every kernel of the call returns at once when
+// *skip != 0 (a finished system inside a graph-captured batch).
 template <typename T>
 void apply_h(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
-             double scale, hipStream_t st, Workspace &ws);
+             double scale, hipStream_t st, Workspace &ws, int ncomp = 4,
+             const int *skip = nullptr);
 // The same on caller-provided scratch (nothing is allocated): the column-pruned
 // FFT intermediate, the projector coefficients before and after the couplings W,
 // and the split-K partial sums of the projector product, of the sizes
@@ -239,10 +245,11 @@ struct ApplyScratch {
   double2 *nlc = nullptr, *nlc2 = nullptr, *part = nullptr;
 };
 template <typename T>
-void apply_scratch_bytes(const dks_basis *b, int sys, int nb, size_t bytes[4]);
+void apply_scratch_bytes(const dks_basis *b, int sys, int nb, size_t bytes[4], int ncomp = 4);
 template <typename T>
 void apply_h_on(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
-                double scale, hipStream_t st, const ApplyScratch &scr);
+                double scale, hipStream_t st, const ApplyScratch &scr, int ncomp = 4,
+                const int *skip = nullptr);
 
 // out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
 // rows addressed by element offsets.  M, Nn <= 512.  `hermitian` (A and B the same
@@ -251,14 +258,15 @@ void apply_h_on(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, do
 template <typename T>
 void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
              int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
-             DevBuf &part, hipStream_t st, bool hermitian = false);
+             DevBuf &part, hipStream_t st, bool hermitian = false, const int *skip = nullptr);
 // The same product with caller-provided split-K partial sums: `part` holds at
 // least gemm_ip_part_elems(M, Nn, K, B2 != null, hermitian) double2.
 size_t gemm_ip_part_elems(int M, int Nn, int64_t K, bool two, bool hermitian);
 template <typename T>
 void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
                  int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
-                 double2 *part, hipStream_t st, bool hermitian = false);
+                 double2 *part, hipStream_t st, bool hermitian = false,
+                 const int *skip = nullptr);
 // The same product with the FP32 inputs rounded to BF16 and FP32 accumulation.
 void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, const int64_t *boff,
                   int Nn, const float2 *B2, int64_t K, double2 *out, double2 *out2, int ldo,
@@ -274,12 +282,13 @@ void gemm_up(const cplx<T> *A, const int64_t *aoff, int m, const double2 *V, int
 template <typename T>
 void gemm_up2(const cplx<T> *A1, const cplx<T> *A2, const int64_t *aoff, int m, const double2 *V,
               int ldv, int n, int64_t K, cplx<T> *out1, cplx<T> *out2, int64_t ldo, double beta,
-              hipStream_t st, double alpha = 1.0, const char *tag = nullptr);
+              hipStream_t st, double alpha = 1.0, const char *tag = nullptr,
+              const int *skip = nullptr);
 
 // R_j = HX_j - lambda_j X_j and ||R_j||^2 (FP64) for n columns of length K.
 template <typename T>
 void residual(const cplx<T> *X, const cplx<T> *HX, const double *lam, int n, int64_t K,
-              cplx<T> *R, double *norm2, DevBuf &part, hipStream_t st);
+              cplx<T> *R, double *norm2, DevBuf &part, hipStream_t st, const int *skip = nullptr);
 
 // column squared norms of n rows of length K
 template <typename T>
@@ -310,6 +319,7 @@ void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st);
 constexpr int kRRStamps = 24;
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
-                   DevBuf &scratch, hipStream_t st, long long *tstamp = nullptr);
+                   DevBuf &scratch, hipStream_t st, long long *tstamp = nullptr,
+                   const int *skip = nullptr);
 
 }  // namespace dks

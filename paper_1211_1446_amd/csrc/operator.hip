@@ -34,7 +34,9 @@ __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__res
                                                   const int2 *__restrict__ gmap, int ncol,
                                                   int tile, const FftPlan *__restrict__ pzp,
                                                   const typename CT<T>::c *__restrict__ twz,
-                                                  typename CT<T>::c *__restrict__ T1) {
+                                                  typename CT<T>::c *__restrict__ T1,
+                                                  const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
   using C = typename CT<T>::c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *lines = reinterpret_cast<C *>(smem_raw);
@@ -96,7 +98,9 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
                                                   const int2 *__restrict__ gmap, int ncol,
                                                   int tile, const FftPlan *__restrict__ pzp,
                                                   const typename CT<T>::c *__restrict__ twz,
-                                                  T inv_ng, T scale) {
+                                                  T inv_ng, T scale,
+                                                  const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
   using C = typename CT<T>::c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *lines = reinterpret_cast<C *>(smem_raw);
@@ -201,7 +205,9 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
                                                 const FftPlan *__restrict__ pxy,
                                                 const typename CT<T>::c *__restrict__ twx,
                                                 const typename CT<T>::c *__restrict__ twy,
-                                                const T *__restrict__ V) {
+                                                const T *__restrict__ V,
+                                                const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
   using C = typename CT<T>::c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *pl = reinterpret_cast<C *>(smem_raw);
@@ -320,11 +326,15 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
 // C is [nproj][4 nb] (FP64); W blocks are (2 dim)^2, index (i m, s).
 // ---------------------------------------------------------------------------
 __global__ void k_apply_w(const double2 *__restrict__ Cin, double2 *__restrict__ Cout, int ldc,
-                          int nb, const int4 *__restrict__ winfo, int ngroups,
-                          const double2 *__restrict__ W) {
-  // grid: x -> band * 2 + pair, y -> group; threads -> output index (2 dim)
+                          int nb, int ncomp, const int4 *__restrict__ winfo, int ngroups,
+                          const double2 *__restrict__ W, const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
+  // grid: x -> band * (ncomp / 2) + pair, y -> group; threads -> output index (2 dim).
+  // ncomp = 4: the large and the small two-spinor of a Dirac spinor; ncomp = 2:
+  // the one two-spinor of the two-component (KSSO) operator.
+  const int npair = ncomp >> 1;
   const int bp = blockIdx.x;
-  const int band = bp >> 1, pair = bp & 1;
+  const int band = bp / npair, pair = bp - band * npair;
   const int4 gi = winfo[blockIdx.y];
   const int p0 = gi.x, dim = gi.y;
   const double2 *w = W + gi.z;
@@ -334,12 +344,12 @@ __global__ void k_apply_w(const double2 *__restrict__ Cin, double2 *__restrict__
     for (int k = 0; k < nd; ++k) {
       double2 wv = w[o * nd + k];
       int p = p0 + (k >> 1), s = k & 1;
-      double2 cv = Cin[(size_t)p * ldc + band * 4 + pair * 2 + s];
+      double2 cv = Cin[(size_t)p * ldc + band * ncomp + pair * 2 + s];
       re += wv.x * cv.x - wv.y * cv.y;
       im += wv.x * cv.y + wv.y * cv.x;
     }
     int p = p0 + (o >> 1), s = o & 1;
-    Cout[(size_t)p * ldc + band * 4 + pair * 2 + s] = make_double2(re, im);
+    Cout[(size_t)p * ldc + band * ncomp + pair * 2 + s] = make_double2(re, im);
   }
 }
 
@@ -349,31 +359,36 @@ __global__ void k_apply_w(const double2 *__restrict__ Cin, double2 *__restrict__
 // kPB rows at a time, all loads in flight together.
 constexpr int kBT = 4;
 constexpr int kPB = 6;
-template <typename T>
+// kPauli: the two-component operator (KSSO): kinetic |q|^2 / 2 on both spin
+// components instead of the 4 x 4 free-Dirac block.
+template <typename T, bool kPauli = false>
 __global__ void __launch_bounds__(256) k_nl_kin(const typename CT<T>::c *__restrict__ X,
                                                 typename CT<T>::c *__restrict__ HX, int N, int nb,
                                                 const typename CT<T>::c *__restrict__ B, int nproj,
                                                 const double2 *__restrict__ Cp, int ldc,
-                                                const T *__restrict__ q, T c, T shift) {
+                                                const T *__restrict__ q, T c, T shift,
+                                                const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
   using C = typename CT<T>::c;
+  constexpr int NC = kPauli ? 2 : 4;   // components per band
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  C *cs = reinterpret_cast<C *>(smem_raw);  // [nproj][4 kBT]
+  C *cs = reinterpret_cast<C *>(smem_raw);  // [nproj][NC kBT]
   const int ntb = (nb + kBT - 1) / kBT;
   const int w = xcd_order(blockIdx.x, gridDim.x);
   const int gb = w / ntb, tb = w - (w / ntb) * ntb;
   const int b0 = tb * kBT;
   const int bw = min(kBT, nb - b0);
-  for (int e = threadIdx.x; e < nproj * 4 * kBT; e += blockDim.x) {
-    int p = e / (4 * kBT), j = e - (e / (4 * kBT)) * (4 * kBT);
-    double2 v = (j < 4 * bw) ? Cp[(size_t)p * ldc + b0 * 4 + j] : make_double2(0, 0);
+  for (int e = threadIdx.x; e < nproj * NC * kBT; e += blockDim.x) {
+    int p = e / (NC * kBT), j = e - (e / (NC * kBT)) * (NC * kBT);
+    double2 v = (j < NC * bw) ? Cp[(size_t)p * ldc + b0 * NC + j] : make_double2(0, 0);
     cs[e] = C{(T)v.x, (T)v.y};
   }
   __syncthreads();
   const int g = gb * blockDim.x + threadIdx.x;
   if (g >= N) return;
-  C acc[4 * kBT];
+  C acc[NC * kBT];
 #pragma unroll
-  for (int j = 0; j < 4 * kBT; ++j) acc[j] = C{0, 0};
+  for (int j = 0; j < NC * kBT; ++j) acc[j] = C{0, 0};
   for (int p0 = 0; p0 < nproj; p0 += kPB) {
     C bv[kPB];
 #pragma unroll
@@ -381,9 +396,9 @@ __global__ void __launch_bounds__(256) k_nl_kin(const typename CT<T>::c *__restr
 #pragma unroll
     for (int u = 0; u < kPB; ++u) {
       if (p0 + u < nproj) {
-        const C *cr = cs + (p0 + u) * 4 * kBT;
+        const C *cr = cs + (p0 + u) * NC * kBT;
 #pragma unroll
-        for (int j = 0; j < 4 * kBT; ++j) {
+        for (int j = 0; j < NC * kBT; ++j) {
           const C cv = cr[j];
           acc[j].x += cv.x * bv[u].x - cv.y * bv[u].y;
           acc[j].y += cv.x * bv[u].y + cv.y * bv[u].x;
@@ -392,6 +407,21 @@ __global__ void __launch_bounds__(256) k_nl_kin(const typename CT<T>::c *__restr
     }
   }
   const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
+  if constexpr (kPauli) {
+    const T kin = T(0.5) * (qx * qx + qy * qy + qz * qz) - shift;
+#pragma unroll
+    for (int bb = 0; bb < kBT; ++bb) {
+      if (bb < bw) {
+        const C *x = X + (size_t)(b0 + bb) * 2 * N;
+        C *hx = HX + (size_t)(b0 + bb) * 2 * N;
+        const C pu = x[g], pd = x[N + g];
+        const C o0 = acc[bb * 2 + 0], o1 = acc[bb * 2 + 1];
+        hx[g] = C{o0.x + kin * pu.x, o0.y + kin * pu.y};
+        hx[N + g] = C{o1.x + kin * pd.x, o1.y + kin * pd.y};
+      }
+    }
+    return;
+  }
   const T twoc2 = T(2) * c * c;
 #pragma unroll
   for (int bb = 0; bb < kBT; ++bb) {
@@ -472,13 +502,15 @@ void init_kernel_attributes() {
     DKS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   done = true;
 }
 
 template <typename T>
-void apply_scratch_bytes(const dks_basis *b, int sysi, int nb, size_t bytes[4]) {
+void apply_scratch_bytes(const dks_basis *b, int sysi, int nb, size_t bytes[4], int ncomp) {
   const System &s = *b->sys[sysi];
-  const int ncols = 4 * nb;
+  const int ncols = ncomp * nb;
   bytes[0] = sizeof(cplx<T>) * (size_t)ncols * s.grid[2] * s.ncol;
   const size_t cbytes = s.nproj > 0 ? sizeof(double2) * (size_t)s.nproj * ncols : 0;
   bytes[1] = cbytes;
@@ -488,10 +520,10 @@ void apply_scratch_bytes(const dks_basis *b, int sysi, int nb, size_t bytes[4]) 
 
 template <typename T>
 void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
-             double scale, hipStream_t st, Workspace &ws) {
+             double scale, hipStream_t st, Workspace &ws, int ncomp, const int *skip) {
   if (nb <= 0) return;
   size_t bytes[4];
-  apply_scratch_bytes<T>(b, sysi, nb, bytes);
+  apply_scratch_bytes<T>(b, sysi, nb, bytes, ncomp);
   ws.t1.ensure(bytes[0]);
   ws.nlc.ensure(bytes[1]);
   ws.nlc2.ensure(bytes[2]);
@@ -501,35 +533,43 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   scr.nlc = ws.nlc.as<double2>();
   scr.nlc2 = ws.nlc2.as<double2>();
   scr.part = ws.part.as<double2>();
-  apply_h_on<T>(b, sysi, X, HX, nb, shift, scale, st, scr);
+  apply_h_on<T>(b, sysi, X, HX, nb, shift, scale, st, scr, ncomp, skip);
 }
 
 template <typename T>
 void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
-                double scale, hipStream_t st, const ApplyScratch &scr) {
+                double scale, hipStream_t st, const ApplyScratch &scr, int ncomp,
+                const int *skip) {
   using C = cplx<T>;
   System &s = *b->sys[sysi];
   Potential &pot = *b->pot[s.vsrc];
   if (nb <= 0) return;
+  DKS_REQUIRE(ncomp == 4 || ncomp == 2, DKS_EINVAL, "spinor components must be 4 or 2");
   const int N = s.N;
-  const int ncols = 4 * nb;
+  const int ncols = ncomp * nb;
   // --- projectors and kinetic block: HX = B C' + kin X - shift X
   double2 *Cp = nullptr;
   if (s.nproj > 0) {
     // B rows p*N and X rows cc*N are contiguous: offsets passed as null (stride N)
     gemm_ip_raw<T>(Btab<T>(s), nullptr, s.nproj, X, nullptr, ncols, nullptr, (int64_t)N, scr.nlc,
-                   nullptr, ncols, scr.part, st);
-    dim3 gw(nb * 2, (unsigned)s.groups.size());
-    DKS_LAUNCH("k_apply_w", k_apply_w, gw, dim3(64), 0, st, scr.nlc, scr.nlc2, ncols, nb,
-               s.d_Winfo.as<int4>(), (int)s.groups.size(), s.d_W64.as<double2>());
+                   nullptr, ncols, scr.part, st, false, skip);
+    dim3 gw(nb * (ncomp / 2), (unsigned)s.groups.size());
+    DKS_LAUNCH("k_apply_w", k_apply_w, gw, dim3(64), 0, st, scr.nlc, scr.nlc2, ncols, nb, ncomp,
+               s.d_Winfo.as<int4>(), (int)s.groups.size(), s.d_W64.as<double2>(), skip);
     DKS_HIP(hipGetLastError());
     Cp = scr.nlc2;
   }
   {
     dim3 grid((unsigned)(((N + 255) / 256) * ((nb + kBT - 1) / kBT)));
-    size_t sm = sizeof(C) * (size_t)s.nproj * 4 * kBT;
-    DKS_LAUNCH((sizeof(T) == 8 ? "k_nl_kin.f64" : "k_nl_kin.f32"), k_nl_kin<T>, grid, dim3(256), sm, st, X, HX, N, nb, Btab<T>(s), s.nproj, Cp,
-                       ncols, Qtab<T>(s), (T)s.c, (T)shift);
+    size_t sm = sizeof(C) * (size_t)s.nproj * ncomp * kBT;
+    if (ncomp == 4)
+      DKS_LAUNCH((sizeof(T) == 8 ? "k_nl_kin.f64" : "k_nl_kin.f32"), k_nl_kin<T>, grid, dim3(256),
+                 sm, st, X, HX, N, nb, Btab<T>(s), s.nproj, Cp, ncols, Qtab<T>(s), (T)s.c, (T)shift,
+                 skip);
+    else
+      DKS_LAUNCH((sizeof(T) == 8 ? "k_nl_kin.pauli.f64" : "k_nl_kin.pauli.f32"), (k_nl_kin<T, true>),
+                 grid, dim3(256), sm, st, X, HX, N, nb, Btab<T>(s), s.nproj, Cp, ncols, Qtab<T>(s),
+                 (T)s.c, (T)shift, skip);
     DKS_HIP(hipGetLastError());
   }
   // --- local potential through the grid
@@ -542,7 +582,8 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
   auto kzinv = ztab ? k_zfft_inv<T, true> : k_zfft_inv<T, false>;
   auto kzfwd = ztab ? k_zfft_fwd<T, true> : k_zfft_fwd<T, false>;
   DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_inv.f64" : "k_zfft_inv.f32"), kzinv, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
-                     s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2), t1);
+                     s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2), t1,
+                     skip);
   DKS_HIP(hipGetLastError());
   dim3 gp(n3, ncols);
   size_t smp = plane_lds_bytes<T>(s.grid[0], s.grid[1]);
@@ -552,24 +593,24 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
   const int pthr = small ? kSmallPlaneThreads : kPlaneThreads<T>;
   DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(pthr), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
                      s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(), Tw<T>(pot, 0),
-                     Tw<T>(pot, 1), Vtab<T>(pot));
+                     Tw<T>(pot, 1), Vtab<T>(pot), skip);
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_fwd.f64" : "k_zfft_fwd.f32"), kzfwd, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
                      s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2),
-                     (T)(1.0 / s.ng), (T)scale);
+                     (T)(1.0 / s.ng), (T)scale, skip);
   DKS_HIP(hipGetLastError());
 }
 
 template void apply_h<double>(dks_basis *, int, const double2 *, double2 *, int, double, double,
-                              hipStream_t, Workspace &);
+                              hipStream_t, Workspace &, int, const int *);
 template void apply_h<float>(dks_basis *, int, const float2 *, float2 *, int, double, double,
-                             hipStream_t, Workspace &);
+                             hipStream_t, Workspace &, int, const int *);
 template void apply_h_on<double>(dks_basis *, int, const double2 *, double2 *, int, double,
-                                 double, hipStream_t, const ApplyScratch &);
+                                 double, hipStream_t, const ApplyScratch &, int, const int *);
 template void apply_h_on<float>(dks_basis *, int, const float2 *, float2 *, int, double, double,
-                                hipStream_t, const ApplyScratch &);
-template void apply_scratch_bytes<double>(const dks_basis *, int, int, size_t[4]);
-template void apply_scratch_bytes<float>(const dks_basis *, int, int, size_t[4]);
+                                hipStream_t, const ApplyScratch &, int, const int *);
+template void apply_scratch_bytes<double>(const dks_basis *, int, int, size_t[4], int);
+template void apply_scratch_bytes<float>(const dks_basis *, int, int, size_t[4], int);
 
 }  // namespace dks
 

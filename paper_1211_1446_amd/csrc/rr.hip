@@ -820,7 +820,17 @@ struct RRScratch {
 __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     int phase, const double2 *__restrict__ Ain, const double2 *__restrict__ Sin, int nz, int nkeep,
     double drop_tol, const int *__restrict__ forced, int *__restrict__ info,
-    double *__restrict__ dinfo, RRScratch W, long long *__restrict__ tstamp) {
+    double *__restrict__ dinfo, RRScratch W, long long *__restrict__ tstamp,
+    const int *__restrict__ skip) {
+  // a finished system of a graph-captured batch: status 3 makes every later
+  // Rayleigh-Ritz kernel of the call return at once
+  if (phase == 0 && skip && *skip) {
+    if (threadIdx.x == 0) {
+      info[0] = 0;
+      info[1] = 3;
+    }
+    return;
+  }
   // no static LDS in this kernel: the dynamic arena then starts at offset 0,
   // 16-byte aligned, as the double2 accesses (ds_read_b128) need for speed
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1370,7 +1380,8 @@ static size_t rr_vec_lds_bytes(int nz) {
 
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info,
-                   double *dinfo, DevBuf &scratch, hipStream_t st, long long *tstamp) {
+                   double *dinfo, DevBuf &scratch, hipStream_t st, long long *tstamp,
+                   const int *skip) {
   DKS_REQUIRE(nz > 0 && nz <= kRRMax && nkeep > 0 && nkeep <= nz, DKS_EINVAL,
               "Rayleigh-Ritz size out of range (subspace dimension must be <= 512)");
   // once per process, also when batch lanes arrive here together
@@ -1394,7 +1405,7 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
   scratch.ensure(RRScratch::bytes(nz, nkeep));
   const RRScratch W = RRScratch::at(scratch.p, nz, nkeep);
   DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 0, A, S,
-             nz, nkeep, drop_tol, forced_drop, info, dinfo, W, tstamp);
+             nz, nkeep, drop_tol, forced_drop, info, dinfo, W, tstamp, skip);
   DKS_HIP(hipGetLastError());
   const unsigned tiles = (unsigned)((nz + kGT - 1) / kGT);
   for (int which = 1; which <= 2; ++which) {
@@ -1402,7 +1413,7 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
     DKS_HIP(hipGetLastError());
   }
   DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 1, A, S,
-             nz, nkeep, drop_tol, forced_drop, info, dinfo, W, tstamp);
+             nz, nkeep, drop_tol, forced_drop, info, dinfo, W, tstamp, skip);
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH("k_rr_values", k_rr_values, dim3(nkeep + 1), dim3(kValThreads), 0, st, W.dd, W.ee,
              nkeep, floor_val, info, W.lam, theta, dinfo, tstamp);

@@ -138,6 +138,9 @@ struct Ctx {
   double C, Om, c2;
   int64_t K;
   int N;
+  int ncomp = 4;                      // 4: Dirac spinors (DKS); 2: two-component (KSSO)
+  bool filt = true;                   // the filter of LOBPCG-F is applied
+  bool guard = true;                  // breakdown guard (Ritz values may not fall below predecessors)
   int iter_slot = 0, iter_cap = 0;   // entries written to / capacity of opts.iter_ms
   double floor = -1e300;              // Ritz values below are discarded (mid-gap -c^2 with F)
   bool bf16_gram = false;             // reduced-precision stage: Gram products from BF16 inputs
@@ -155,8 +158,8 @@ __global__ void k_offsets(int64_t *off, int n, int m, int mp, int64_t K) {
 template <typename T>
 static void filter_inplace(Ctx &x, cplx<T> *Y, cplx<T> *W, int m) {
   // W = (H - C) Y ; Y = (H - C) W / Omega^2   (Eq. filter)
-  apply_h<T>(x.b, x.sys, Y, W, m, x.C, 1.0, x.st, x.sv->ws);
-  apply_h<T>(x.b, x.sys, W, Y, m, x.C, 1.0 / (x.Om * x.Om), x.st, x.sv->ws);
+  apply_h<T>(x.b, x.sys, Y, W, m, x.C, 1.0, x.st, x.sv->ws, x.ncomp);
+  apply_h<T>(x.b, x.sys, W, Y, m, x.C, 1.0 / (x.Om * x.Om), x.st, x.sv->ws, x.ncomp);
   if (x.info) x.info->h_applies += 2 * m;
 }
 
@@ -385,7 +388,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
                             double tol, int max_iter, double drop_tol, int stall_window,
                             int restart_window) {
   Solver &sv = *x.sv;
-  const bool filt = x.o->use_filter != 0;
+  const bool filt = x.filt;
   s.cur = 0;
   s.m = 0;
   s.mp = 0;
@@ -394,7 +397,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   if (filt)
     for (int k = 0; k < n_init; ++k) filter_inplace<T>(x, bk.z(0, 0), bk.W.template as<cplx<T>>(), n);
   // Rayleigh-Ritz on the start block, first residual
-  apply_h<T>(x.b, x.sys, bk.z(0, 0), bk.hz(0, 0), n, 0.0, 1.0, x.st, x.sv->ws);
+  apply_h<T>(x.b, x.sys, bk.z(0, 0), bk.hz(0, 0), n, 0.0, 1.0, x.st, x.sv->ws, x.ncomp);
   if (x.info) x.info->h_applies += n;
   std::vector<double2> hV;
   if (!ritz<T>(x, bk, s, n, drop_tol, hV))
@@ -414,7 +417,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     if (filt)
       for (int k = 0; k < kPolishFilters; ++k)
         filter_inplace<T>(x, bk.z(s.cur, 0), bk.W.template as<cplx<T>>(), n);
-    apply_h<T>(x.b, x.sys, bk.z(s.cur, 0), bk.hz(s.cur, 0), n, 0.0, 1.0, x.st, x.sv->ws);
+    apply_h<T>(x.b, x.sys, bk.z(s.cur, 0), bk.hz(s.cur, 0), n, 0.0, 1.0, x.st, x.sv->ws, x.ncomp);
     if (x.info) {
       x.info->h_applies += n;
       x.info->p_restarts += 1;
@@ -464,7 +467,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
     // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
-    apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st, x.sv->ws);
+    apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st, x.sv->ws, x.ncomp);
     if (x.info) x.info->h_applies += m;
     // Rayleigh-Ritz on Z = [X, Y, P]
     const std::vector<double> lam_prev = s.lam;
@@ -481,7 +484,8 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     // band to be compared with its eigenvalues), so it guards LOBPCG-F; plain
     // LOBPCG on the Dirac operator is left unguarded, and its fall into the
     // negative band, the variational collapse of Sec. 3.1, is reported as such.
-    if (filt) {
+    // The two-component operator has no negative band and is guarded.
+    if (x.guard) {
       double rf = 0;
       for (double r : s.res) rf += r * r;
       rf = std::sqrt(rf);
@@ -508,7 +512,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
       double mx_prev = 0, mx = 0;
       for (double r : res_prev) mx_prev = std::max(mx_prev, r);
       for (double r : s.res) mx = std::max(mx, r);
-      if (filt && !(mx <= 1e3 * mx_prev)) {
+      if (x.guard && !(mx <= 1e3 * mx_prev)) {
         s.cur = cur_prev;
         s.lam = lam_prev;
         s.res = res_prev;
@@ -590,8 +594,10 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
                             hipStream_t st, Solver *sv, std::string &msg) {
   {
     const System &s = *b->sys[sys];
-    DKS_REQUIRE(n >= 1 && n <= 170 && n <= 4 * s.N, DKS_EINVAL,
-                "n must be in [1, min(170, 4N)] (subspace dimension 3n <= 512)");
+    DKS_REQUIRE(o.model == DKS_MODEL_DKS || o.model == DKS_MODEL_KSSO, DKS_EINVAL, "bad model");
+    const int ncomp = o.model == DKS_MODEL_KSSO ? 2 : 4;
+    DKS_REQUIRE(n >= 1 && n <= 170 && n <= ncomp * s.N, DKS_EINVAL,
+                "n must be in [1, min(170, ncomp N)] (subspace dimension 3n <= 512)");
     DKS_REQUIRE(o.n_init >= 0 && o.n_iter >= 0 && o.tol > 0, DKS_EINVAL, "bad options");
     DKS_REQUIRE(o.mode >= 0 && o.mode <= 2, DKS_EINVAL, "bad mode");
     DKS_REQUIRE(o.n_buffer >= 0 && o.n_buffer < n, DKS_EINVAL, "n_buffer must be in [0, n)");
@@ -605,7 +611,12 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
     x.o = &o;
     x.info = &inf;
     x.N = s.N;
-    x.K = 4 * (int64_t)s.N;
+    x.ncomp = ncomp;
+    x.K = ncomp * (int64_t)s.N;
+    // the KSSO operator is solved by standard LOBPCG (the paper's comparison):
+    // no filter, no kinetic balance, and (no negative band) the breakdown guard on
+    x.filt = o.use_filter != 0 && ncomp == 4;
+    x.guard = x.filt || ncomp == 2;
     x.c2 = s.c * s.c;
     double C0, O0;
     dks_filter_constants(b, sys, &C0, &O0);
@@ -615,8 +626,8 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
     inf.C = x.C;
     inf.Omega = x.Om;
     x.iter_cap = o.n_iter + (o.mode != DKS_MODE_FP64 ? o.mixed_iter : 0);
-    x.floor = o.use_filter ? -x.c2 : -std::numeric_limits<double>::infinity();
-    if (o.kinetic_balance) kinetic_balance(b, sys, Xu, n, st);
+    x.floor = x.filt ? -x.c2 : -std::numeric_limits<double>::infinity();
+    if (o.kinetic_balance && ncomp == 4) kinetic_balance(b, sys, Xu, n, st);
     dks_status rc = DKS_OK;
     LoopState<double> s64;
     if (o.mode == DKS_MODE_FP64) {
@@ -700,6 +711,7 @@ void dks_default_opts(dks_solve_opts *o) {
   o->mixed_iter = 200;
   o->kinetic_balance = 0;
   o->use_filter = 1;
+  o->model = DKS_MODEL_DKS;
   o->n_buffer = 0;
 }
 
@@ -715,6 +727,22 @@ dks_status dks_apply_H(dks_basis *b, int sys, const void *X, void *HX, int nb, d
       apply_h<double>(b, sys, (const double2 *)X, (double2 *)HX, nb, 0.0, 1.0, st, b->ws);
     else
       apply_h<float>(b, sys, (const float2 *)X, (float2 *)HX, nb, 0.0, 1.0, st, b->ws);
+    return DKS_OK;
+  });
+}
+
+dks_status dks_apply_H_ksso(dks_basis *b, int sys, const void *X, void *HX, int nb, dks_prec prec,
+                            void *stream) {
+  return guarded([&]() -> dks_status {
+    DKS_REQUIRE(b && X && HX && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
+                "bad argument");
+    DKS_REQUIRE(X != HX, DKS_EINVAL, "X and HX must not overlap");
+    DKS_HIP(hipSetDevice(b->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == DKS_FP64)
+      apply_h<double>(b, sys, (const double2 *)X, (double2 *)HX, nb, 0.0, 1.0, st, b->ws, 2);
+    else
+      apply_h<float>(b, sys, (const float2 *)X, (float2 *)HX, nb, 0.0, 1.0, st, b->ws, 2);
     return DKS_OK;
   });
 }
