@@ -193,6 +193,20 @@ typedef struct {
                            eigenvalue n + 1, not i + 1).  Default 0 */
   int model;            /* dks_model: the operator solved; blocks are [n][4][N] for
                            DKS_MODEL_DKS, [n][2][N] for DKS_MODEL_KSSO.  Default DKS */
+  int batch_graph;      /* dks_lobpcgf_solve_batch only.  0: every item on its own lane
+                           (a stream and a host thread deciding each iteration).  1: all
+                           items in lockstep inside one captured HIP graph per chunk of
+                           graph_chunk iterations: convergence, stagnation and the
+                           iteration cap are decided on the device, finished items become
+                           empty launches, the host waits once per chunk; the graph form
+                           iterates every column (no soft locking) and keeps P orthogonal
+                           to X; items that leave it unconverged (stall, a failed
+                           Rayleigh-Ritz, a broken-down step) are finished on the lanes
+                           from their last good block.  Default 0 */
+  int graph_chunk;      /* iterations per graph launch (even, >= 2).  Default 8 */
+  const int *item_buffer; /* dks_lobpcgf_solve_batch only: optional caller-owned host array
+                           of nsys buffer-column counts, item i taking item_buffer[i] in
+                           place of n_buffer (each in [0, n[i])).  Default NULL */
 } dks_solve_opts;
 
 typedef struct {
@@ -207,6 +221,11 @@ typedef struct {
   double min_ritz;      /* smallest Ritz value seen (collapse monitor) */
   double max_resnorm;   /* largest final residual norm */
   double C, Omega;      /* filter constants used */
+  int graph_iterations; /* batch_graph: iterations taken inside the captured graphs */
+  int graph_exit;       /* batch_graph: how the item left the last graph stage: 1 converged,
+                           2 Rayleigh-Ritz failed, 3 a Ritz value below the spectrum (broken-
+                           down step), 4 stalled, 5 iteration cap, 6 wanted residuals jumped
+                           a thousandfold (broken-down step); 0: no graph stage ran */
 } dks_solve_info;
 
 void dks_default_opts(dks_solve_opts *o);
@@ -241,6 +260,31 @@ dks_status dks_lobpcgf_solve_batch(dks_basis *b, int nsys, const int *sys, const
                                    void *const *X, double *const *lambda,
                                    double *const *resnorms, const dks_solve_opts *opts,
                                    dks_solve_info *info, void *stream);
+
+/* Launch-shape autotuner.  For each listed system, H X on nb[i] bands (precision
+ * `prec`) is timed with HIP events for each candidate of one launch shape at a
+ * time, the others held, and the fastest is kept in the basis for every later
+ * call on that system: the z-transform tile (xy-columns per workgroup, 2-64
+ * within the LDS), the plane kernel form (see dks_get_tuning), and the split-K
+ * target of the projector product (256-2048 workgroups).  Results do not change (only
+ * rounding order).  Synchronous; allocates two blocks of nb bands while it runs.
+ * Calls on the basis must not overlap it. */
+dks_status dks_autotune(dks_basis *b, int nsys, const int *sys, const int *nb, dks_prec prec,
+                        void *stream);
+
+/* The launch shapes in use for system `sys` (NULL pointers are skipped): z tile,
+ * plane kernel form (0: FP64 768 / FP32 512 threads, 1: 256 threads for planes
+ * within its LDS budget, 2 and 3: the same with each wave owning whole lines of
+ * every line pass), projector split-K target.  Host only. */
+dks_status dks_get_tuning(const dks_basis *b, int sys, int *tile_z, int *plane_form,
+                          int *ip_blocks);
+
+/* Set the launch shapes of system `sys` (a stored autotuner table):
+ * 1 <= tile_z <= 64 within the LDS for the grid's third axis, plane_form in
+ * [-1, 3] (-1: by size; a small form on a plane above its budget falls back to
+ * the large one), ip_blocks in [0, 65536] (0: default).  Host only; calls on the
+ * basis must not overlap it. */
+dks_status dks_set_tuning(dks_basis *b, int sys, int tile_z, int plane_form, int ip_blocks);
 
 /* Kernel timing (a diagnostic for roofline accounting).  When enabled, every
  * kernel the library launches on the calling thread is bracketed by a pair of

@@ -47,7 +47,9 @@ class SolveOpts(ct.Structure):
                 ("n_iter", ct.c_int), ("tol", ct.c_double), ("mode", ct.c_int),
                 ("mixed_tol", ct.c_double), ("mixed_iter", ct.c_int),
                 ("kinetic_balance", ct.c_int), ("use_filter", ct.c_int),
-                ("iter_ms", ct.POINTER(ct.c_double)), ("n_buffer", ct.c_int), ("model", ct.c_int)]
+                ("iter_ms", ct.POINTER(ct.c_double)), ("n_buffer", ct.c_int), ("model", ct.c_int),
+                ("batch_graph", ct.c_int), ("graph_chunk", ct.c_int),
+                ("item_buffer", ct.POINTER(ct.c_int))]
 
 
 class SolveInfo(ct.Structure):
@@ -55,7 +57,8 @@ class SolveInfo(ct.Structure):
                 ("n_converged", ct.c_int), ("h_applies", ct.c_int), ("basis_drops", ct.c_int),
                 ("p_restarts", ct.c_int), ("neg_ritz_discarded", ct.c_int),
                 ("min_ritz", ct.c_double), ("max_resnorm", ct.c_double),
-                ("C", ct.c_double), ("Omega", ct.c_double)]
+                ("C", ct.c_double), ("Omega", ct.c_double),
+                ("graph_iterations", ct.c_int), ("graph_exit", ct.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -76,6 +79,9 @@ def _load():
     lib.dks_apply_H.argtypes = [vp, i, vp, vp, i, i, vp]
     lib.dks_apply_H_noalloc.argtypes = [vp, i, vp, vp, i, i, vp]
     lib.dks_apply_H_ksso.argtypes = [vp, i, vp, vp, i, i, vp]
+    lib.dks_autotune.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), i, vp]
+    lib.dks_get_tuning.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
+    lib.dks_set_tuning.argtypes = [vp, i, i, i, i]
     lib.dks_apply_filter.argtypes = [vp, i, vp, vp, i, d, d, i, vp]
     lib.dks_filter_constants.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(d)]
     lib.dks_default_opts.argtypes = [ct.POINTER(SolveOpts)]
@@ -266,6 +272,29 @@ def filter_constants(b: Basis, sys: int = 0):
     return C.value, Om.value
 
 
+def autotune(b: Basis, systems: Sequence[int], nbs: Sequence[int], prec: int = DKS_FP64,
+             stream=None) -> None:
+    """Time and pick the launch shapes of H X for each system (dks_autotune)."""
+    n = len(systems)
+    if len(nbs) != n:
+        raise ValueError("one band count per system")
+    sa = (ct.c_int * max(n, 1))(*[int(v) for v in systems])
+    na = (ct.c_int * max(n, 1))(*[int(v) for v in nbs])
+    _check(_lib.dks_autotune(b.handle, n, sa, na, int(prec), _stream(stream)))
+
+
+def get_tuning(b: Basis, sys: int) -> dict:
+    """The launch shapes in use for system `sys` (dks_get_tuning)."""
+    t, p, k = ct.c_int(), ct.c_int(), ct.c_int()
+    _check(_lib.dks_get_tuning(b.handle, sys, ct.byref(t), ct.byref(p), ct.byref(k)))
+    return {"tile_z": t.value, "plane_form": p.value, "ip_blocks": k.value}
+
+
+def set_tuning(b: Basis, sys: int, tile_z: int, plane_form: int, ip_blocks: int) -> None:
+    """Apply stored launch shapes to system `sys` (dks_set_tuning)."""
+    _check(_lib.dks_set_tuning(b.handle, sys, int(tile_z), int(plane_form), int(ip_blocks)))
+
+
 def default_opts(**kw) -> SolveOpts:
     o = SolveOpts()
     _lib.dks_default_opts(ct.byref(o))
@@ -317,8 +346,10 @@ def lobpcgf_solve(b: Basis, sys: int, n: int, X, opts: Optional[SolveOpts] = Non
 
 
 def lobpcgf_solve_batch(b: Basis, systems: Sequence[int], ns: Sequence[int], Xs: Sequence,
-                        opts: Optional[SolveOpts] = None, stream=None, allow_notconv: bool = True):
+                        opts: Optional[SolveOpts] = None, stream=None, allow_notconv: bool = True,
+                        item_buffer: Optional[Sequence[int]] = None):
     """Algorithm 1 on several systems of one basis (dks_lobpcgf_solve_batch).
+    ``item_buffer``: optional buffer-column count per item (overrides n_buffer).
 
     ``Xs[i]``: complex128 device block [ns[i]][4][N_i] (in: start block, out:
     eigenvectors).  Returns (list of eigenvalue arrays, list of residual arrays,
@@ -343,7 +374,13 @@ def lobpcgf_solve_batch(b: Basis, systems: Sequence[int], ns: Sequence[int], Xs:
     l_a = (dp * max(nsys, 1))(*[a.ctypes.data_as(dp) for a in lams])
     r_a = (dp * max(nsys, 1))(*[a.ctypes.data_as(dp) for a in ress])
     o = opts if opts is not None else default_opts()
+    if item_buffer is not None:
+        if len(item_buffer) != nsys:
+            raise ValueError("item_buffer needs one entry per item")
+        buf_a = (ct.c_int * max(nsys, 1))(*[int(v) for v in item_buffer])
+        o.item_buffer = ct.cast(buf_a, ct.POINTER(ct.c_int))
     rc = _lib.dks_lobpcgf_solve_batch(b.handle, nsys, sys_a, n_a, x_a, l_a, r_a, ct.byref(o),
                                       infos, _stream(stream))
+    o.item_buffer = ct.POINTER(ct.c_int)()
     _check(rc, allow_warning=allow_notconv)
     return lams, ress, [infos[i].as_dict() for i in range(nsys)], rc

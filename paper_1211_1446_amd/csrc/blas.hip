@@ -271,14 +271,15 @@ struct IpShape {
   bool upper;
   int64_t nsplit, kchunk;
 };
-static IpShape ip_shape(int M, int Nn, int64_t K, bool hermitian) {
+static IpShape ip_shape(int M, int Nn, int64_t K, bool hermitian, int blocks) {
   IpShape g;
   g.tm = (M + kIpTile - 1) / kIpTile;
   const int tn = (Nn + kIpTile - 1) / kIpTile;
   g.upper = hermitian && M == Nn;
   g.tiles = g.upper ? g.tm * (g.tm + 1) / 2 : g.tm * tn;
   int64_t maxsplit = (K + kIpKT * 16 - 1) / (kIpKT * 16);
-  int64_t nsplit = (kIpBlocks + g.tiles - 1) / g.tiles;
+  const int target = blocks > 0 ? blocks : kIpBlocks;
+  int64_t nsplit = (target + g.tiles - 1) / g.tiles;
   nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, maxsplit));
   int64_t kchunk = (K + nsplit - 1) / nsplit;
   kchunk = (kchunk + kIpKT - 1) / kIpKT * kIpKT;
@@ -290,9 +291,9 @@ static IpShape ip_shape(int M, int Nn, int64_t K, bool hermitian) {
   return g;
 }
 
-size_t gemm_ip_part_elems(int M, int Nn, int64_t K, bool two, bool hermitian) {
+size_t gemm_ip_part_elems(int M, int Nn, int64_t K, bool two, bool hermitian, int blocks) {
   if (M <= 0 || Nn <= 0) return 0;
-  const IpShape g = ip_shape(M, Nn, K, hermitian);
+  const IpShape g = ip_shape(M, Nn, K, hermitian, blocks);
   return (size_t)g.nsplit * M * Nn * (two ? 2 : 1);
 }
 
@@ -309,9 +310,9 @@ void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, con
 template <typename T>
 void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
                  int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
-                 double2 *part, hipStream_t st, bool hermitian, const int *skip) {
+                 double2 *part, hipStream_t st, bool hermitian, const int *skip, int blocks) {
   if (M <= 0 || Nn <= 0) return;
-  const IpShape g = ip_shape(M, Nn, K, hermitian);
+  const IpShape g = ip_shape(M, Nn, K, hermitian, blocks);
   const int tm = g.tm, tiles = g.tiles;
   const bool upper = g.upper;
   const int64_t nsplit = g.nsplit, kchunk = g.kchunk;
@@ -485,7 +486,7 @@ void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, 
                   int Nn, const float2 *B2, int64_t K, double2 *out, double2 *out2, int ldo,
                   DevBuf &part, hipStream_t st, bool hermitian) {
   if (M <= 0 || Nn <= 0) return;
-  const IpShape g = ip_shape(M, Nn, K, hermitian);
+  const IpShape g = ip_shape(M, Nn, K, hermitian, 0);
   const int tm = g.tm, tiles = g.tiles;
   const bool upper = g.upper;
   const int64_t nsplit = g.nsplit, kchunk = g.kchunk;
@@ -507,10 +508,10 @@ template void gemm_ip<float>(const float2 *, const int64_t *, int, const float2 
                              int, DevBuf &, hipStream_t, bool, const int *);
 template void gemm_ip_raw<double>(const double2 *, const int64_t *, int, const double2 *,
                                   const int64_t *, int, const double2 *, int64_t, double2 *,
-                                  double2 *, int, double2 *, hipStream_t, bool, const int *);
+                                  double2 *, int, double2 *, hipStream_t, bool, const int *, int);
 template void gemm_ip_raw<float>(const float2 *, const int64_t *, int, const float2 *,
                                  const int64_t *, int, const float2 *, int64_t, double2 *,
-                                 double2 *, int, double2 *, hipStream_t, bool, const int *);
+                                 double2 *, int, double2 *, hipStream_t, bool, const int *, int);
 
 // ---------------------------------------------------------------------------
 // block update

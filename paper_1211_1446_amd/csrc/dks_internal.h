@@ -177,7 +177,15 @@ struct System {
   DevBuf d_Winfo;                                 // per (group): int4 {p0, dim, woff, 0}
   FftPlan plan[3];
   DevBuf d_plan;                                  // the three plans, for the kernels
+  // launch shapes (defaults from the sizes; dks_autotune measures and sets them)
   int tile_z;                                     // xy-columns per z-FFT workgroup
+  int plane_form = -1;                            // plane kernel: 0 FP64 768 / FP32 512
+                                                  // threads, 1 256 threads (small planes),
+                                                  // 2 and 3 the same with the line passes
+                                                  // split by whole lines per wave; -1: 1 if
+                                                  // the plane fits the small LDS budget, else 0
+  int ip_blocks = 0;                              // projector product: split-K target
+                                                  // (workgroups per launch; 0: the default)
 };
 
 struct Potential {
@@ -261,12 +269,13 @@ void gemm_ip(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, con
              DevBuf &part, hipStream_t st, bool hermitian = false, const int *skip = nullptr);
 // The same product with caller-provided split-K partial sums: `part` holds at
 // least gemm_ip_part_elems(M, Nn, K, B2 != null, hermitian) double2.
-size_t gemm_ip_part_elems(int M, int Nn, int64_t K, bool two, bool hermitian);
+// `blocks`: split-K target (about this many workgroups per launch; 0: the default).
+size_t gemm_ip_part_elems(int M, int Nn, int64_t K, bool two, bool hermitian, int blocks = 0);
 template <typename T>
 void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B, const int64_t *boff,
                  int Nn, const cplx<T> *B2, int64_t K, double2 *out, double2 *out2, int ldo,
                  double2 *part, hipStream_t st, bool hermitian = false,
-                 const int *skip = nullptr);
+                 const int *skip = nullptr, int blocks = 0);
 // The same product with the FP32 inputs rounded to BF16 and FP32 accumulation.
 void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, const int64_t *boff,
                   int Nn, const float2 *B2, int64_t K, double2 *out, double2 *out2, int ldo,
@@ -317,6 +326,8 @@ void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st);
 // `forced_drop` (nz ints or null): 1 marks a column to skip.  `tstamp` (optional,
 // device, kRRStamps entries): wall-clock stamps of the phases, for tuning.
 constexpr int kRRStamps = 24;
+// device scratch bytes rayleigh_ritz needs for an nz x nz problem keeping nkeep
+size_t rr_scratch_bytes(int nz, int nkeep);
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
                    DevBuf &scratch, hipStream_t st, long long *tstamp = nullptr,

@@ -137,11 +137,12 @@ __device__ __forceinline__ C twt(const C *tw, int e) {
 
 // inverse step 1 on nl lines (in place)
 template <int A, int B, typename T>
-__device__ __forceinline__ void inv_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
+__device__ __forceinline__ void inv_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
+                                          int tid = threadIdx.x, int nthr = blockDim.x) {
   using C = typename CT<T>::c;
   if constexpr (A > 1) {
     const int tasks = nl * B;
-    for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+    for (int t = tid; t < tasks; t += nthr) {
       const int b = t / nl, l = t - (t / nl) * nl;
       const int base = L.base(l) + b * L.stride;
       C v[A];
@@ -158,11 +159,12 @@ __device__ __forceinline__ void inv_step1(typename CT<T>::c *buf, int nl, Lines 
 
 // forward step 1' on nl lines (in place): DFT_A over k_a, natural output
 template <int A, int B, typename T>
-__device__ __forceinline__ void fwd_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
+__device__ __forceinline__ void fwd_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
+                                          int tid = threadIdx.x, int nthr = blockDim.x) {
   using C = typename CT<T>::c;
   if constexpr (A > 1) {
     const int tasks = nl * B;
-    for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+    for (int t = tid; t < tasks; t += nthr) {
       const int b = t / nl, l = t - (t / nl) * nl;
       const int base = L.base(l) + b * L.stride;
       C v[A];
@@ -177,10 +179,11 @@ __device__ __forceinline__ void fwd_step1(typename CT<T>::c *buf, int nl, Lines 
 
 // inverse step 2 on the blocks (in place)
 template <int A, int B, typename T>
-__device__ __forceinline__ void inv_step2(typename CT<T>::c *buf, int nl, Lines L) {
+__device__ __forceinline__ void inv_step2(typename CT<T>::c *buf, int nl, Lines L, int tid = threadIdx.x,
+                                          int nthr = blockDim.x) {
   using C = typename CT<T>::c;
   const int tasks = nl * A;
-  for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+  for (int t = tid; t < tasks; t += nthr) {
     const int ka = t / nl, l = t - (t / nl) * nl;
     const int base = L.base(l) + B * ka * L.stride;
     C v[B];
@@ -194,10 +197,11 @@ __device__ __forceinline__ void inv_step2(typename CT<T>::c *buf, int nl, Lines 
 
 // forward step 2' on the blocks (in place), including the w_n^{-b k_a} twiddle
 template <int A, int B, typename T>
-__device__ __forceinline__ void fwd_step2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw) {
+__device__ __forceinline__ void fwd_step2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
+                                          int tid = threadIdx.x, int nthr = blockDim.x) {
   using C = typename CT<T>::c;
   const int tasks = nl * A;
-  for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+  for (int t = tid; t < tasks; t += nthr) {
     const int ka = t / nl, l = t - (t / nl) * nl;
     const int base = L.base(l) + B * ka * L.stride;
     C v[B];
@@ -217,10 +221,11 @@ __device__ __forceinline__ void fwd_step2(typename CT<T>::c *buf, int nl, Lines 
 // V for line l, position p is Vp[l * vls + p * vps].
 template <int A, int B, typename T>
 __device__ __forceinline__ void inv2_mul_fwd2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
-                              const T *__restrict__ Vp, int vls, int vps) {
+                              const T *__restrict__ Vp, int vls, int vps, int tid = threadIdx.x,
+                              int nthr = blockDim.x) {
   using C = typename CT<T>::c;
   const int tasks = nl * A;
-  for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+  for (int t = tid; t < tasks; t += nthr) {
     const int ka = t / nl, l = t - (t / nl) * nl;
     const int base = L.base(l) + B * ka * L.stride;
     const T *vl = Vp + (size_t)l * vls + (size_t)(B * ka) * vps;

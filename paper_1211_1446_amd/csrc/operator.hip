@@ -198,7 +198,9 @@ size_t plane_lds_bytes(int n1, int n2) {
 // kTab: both plane axes have a compiled two-step split (fft2.h); otherwise the
 // generic radix transforms run, in a kernel of their own so that their calls
 // and registers stay out of the table kernel.
-template <typename T, bool kTab, bool kSmall = false>
+// kWaveLines: the line passes of the plane are split between waves by whole
+// lines instead of between all threads by tasks (fewer workgroup barriers).
+template <typename T, bool kTab, bool kSmall = false, bool kWaveLines = false>
 __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
                                                 const int4 *__restrict__ col_info,
                                                 const int *__restrict__ rows, int nrows,
@@ -260,6 +262,40 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   const T *v = V + (size_t)z * n1 * n2;   // potential of this plane, [p1][p2] scrambled
   const fft2::Lines Ly{rows_s, ld, 1};       // rows holding sphere columns, along a2
   const fft2::Lines Lx{nullptr, 1, ld};    // every a2 position, along a1
+  if constexpr (kTab && kWaveLines) {
+    // Each wave owns whole lines of every axis pass (rows along a2, columns
+    // along a1), so the two steps of one axis exchange data only within a
+    // wave: a wave-level fence between them, a workgroup barrier only where
+    // the axis changes.  Waves drift apart and overlap their LDS waits.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int r0 = nrows * wave / nw, r1 = nrows * (wave + 1) / nw;
+    const int c0 = n2 * wave / nw, c1 = n2 * (wave + 1) / nw;
+    const fft2::Lines Lyw{rows_s + r0, ld, 1};
+    auto wave_sync = [] {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+    };
+    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+      fft2::inv_step1<A, B, T>(pl, r1 - r0, Lyw, ty, lane, 64);
+      wave_sync();
+      fft2::inv_step2<A, B, T>(pl, r1 - r0, Lyw, lane, 64);
+    });
+    __syncthreads();
+    fft2::dispatch_plane(n1, [&]<int A, int B>() {
+      fft2::inv_step1<A, B, T>(pl + c0, c1 - c0, Lx, tx, lane, 64);
+      wave_sync();
+      fft2::inv2_mul_fwd2<A, B, T>(pl + c0, c1 - c0, Lx, tx, v + c0, 1, n2, lane, 64);
+      wave_sync();
+      fft2::fwd_step1<A, B, T>(pl + c0, c1 - c0, Lx, tx, lane, 64);
+    });
+    __syncthreads();
+    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+      fft2::fwd_step2<A, B, T>(pl, r1 - r0, Lyw, ty, lane, 64);
+      wave_sync();
+      fft2::fwd_step1<A, B, T>(pl, r1 - r0, Lyw, ty, lane, 64);
+    });
+    __syncthreads();
+  } else {
   // inverse along a2
   if constexpr (kTab) {
     fft2::dispatch_plane(n2, [&]<int A, int B>() {
@@ -303,6 +339,7 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
     fft_lines<-1, T>(pl, nrows, rows, ld, 1, py, twy);
   }
   __syncthreads();
+  }
   for (int c0 = 0; c0 < ncol; c0 += kPre * nthr) {
     T vr[kPre], vi[kPre];
 #pragma unroll
@@ -493,6 +530,10 @@ void init_kernel_attributes() {
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, true, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, true, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   const void *big_lds[] = {
       (const void *)k_zfft_inv<double, true>, (const void *)k_zfft_inv<double, false>,
       (const void *)k_zfft_inv<float, true>,  (const void *)k_zfft_inv<float, false>,
@@ -515,7 +556,9 @@ void apply_scratch_bytes(const dks_basis *b, int sysi, int nb, size_t bytes[4], 
   const size_t cbytes = s.nproj > 0 ? sizeof(double2) * (size_t)s.nproj * ncols : 0;
   bytes[1] = cbytes;
   bytes[2] = cbytes;
-  bytes[3] = s.nproj > 0 ? sizeof(double2) * gemm_ip_part_elems(s.nproj, ncols, (int64_t)s.N, false, false) : 0;
+  bytes[3] = s.nproj > 0 ? sizeof(double2) * gemm_ip_part_elems(s.nproj, ncols, (int64_t)s.N, false,
+                                                                 false, s.ip_blocks)
+                         : 0;
 }
 
 template <typename T>
@@ -552,7 +595,7 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
   if (s.nproj > 0) {
     // B rows p*N and X rows cc*N are contiguous: offsets passed as null (stride N)
     gemm_ip_raw<T>(Btab<T>(s), nullptr, s.nproj, X, nullptr, ncols, nullptr, (int64_t)N, scr.nlc,
-                   nullptr, ncols, scr.part, st, false, skip);
+                   nullptr, ncols, scr.part, st, false, skip, s.ip_blocks);
     dim3 gw(nb * (ncomp / 2), (unsigned)s.groups.size());
     DKS_LAUNCH("k_apply_w", k_apply_w, gw, dim3(64), 0, st, scr.nlc, scr.nlc2, ncols, nb, ncomp,
                s.d_Winfo.as<int4>(), (int)s.groups.size(), s.d_W64.as<double2>(), skip);
@@ -588,8 +631,13 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
   dim3 gp(n3, ncols);
   size_t smp = plane_lds_bytes<T>(s.grid[0], s.grid[1]);
   const bool tab = fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]);
-  const bool small = tab && smp <= kSmallPlaneLds;
-  auto kplane = small ? k_plane<T, true, true> : tab ? k_plane<T, true> : k_plane<T, false>;
+  const bool fits_small = tab && smp <= kSmallPlaneLds;
+  const int form = s.plane_form >= 0 ? s.plane_form : (fits_small ? 1 : 0);
+  const bool small = fits_small && (form == 1 || form == 3);
+  const bool wlines = tab && (form == 2 || form == 3);
+  auto kplane = !tab ? k_plane<T, false>
+                     : small ? (wlines ? k_plane<T, true, true, true> : k_plane<T, true, true>)
+                             : (wlines ? k_plane<T, true, false, true> : k_plane<T, true>);
   const int pthr = small ? kSmallPlaneThreads : kPlaneThreads<T>;
   DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(pthr), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
                      s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(), Tw<T>(pot, 0),
@@ -700,6 +748,138 @@ extern "C" dks_status dks_apply_H_noalloc(dks_basis *b, int sys, const void *X, 
       apply_h_noalloc<double>(b, sys, (const double2 *)X, (double2 *)HX, nb, st);
     else
       apply_h_noalloc<float>(b, sys, (const float2 *)X, (float2 *)HX, nb, st);
+    return DKS_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape autotuner
+// ---------------------------------------------------------------------------
+// For each listed system, H X on nb bands of that system is timed (HIP events,
+// median of three calls after a warm-up) for each candidate of one launch
+// shape while the others keep their current values, and the fastest is kept:
+// first the z-transform tile (xy-columns per workgroup, within the LDS), then
+// the plane workgroup form (768/512 or 256 threads, where the plane fits the
+// small form's LDS budget), then the split-K target of the projector product.
+namespace dks {
+template <typename T>
+static float time_apply(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1) {
+  apply_h<T>(b, sys, X, HX, nb, 0.0, 1.0, st, b->ws);
+  float t[3];
+  for (int r = 0; r < 3; ++r) {
+    DKS_HIP(hipEventRecord(e0, st));
+    apply_h<T>(b, sys, X, HX, nb, 0.0, 1.0, st, b->ws);
+    DKS_HIP(hipEventRecord(e1, st));
+    DKS_HIP(hipEventSynchronize(e1));
+    DKS_HIP(hipEventElapsedTime(&t[r], e0, e1));
+  }
+  std::sort(t, t + 3);
+  return t[1];
+}
+
+template <typename T>
+static void tune_system(dks_basis *b, int sys, int nb, hipStream_t st, double *ms_out) {
+  System &s = *b->sys[sys];
+  const size_t K = 4 * (size_t)s.N;
+  DevBuf x, hx;
+  x.ensure(sizeof(cplx<T>) * K * nb);
+  hx.ensure(sizeof(cplx<T>) * K * nb);
+  DKS_HIP(hipMemsetAsync(x.p, 0, x.bytes, st));
+  hipEvent_t e0, e1;
+  DKS_HIP(hipEventCreate(&e0));
+  DKS_HIP(hipEventCreate(&e1));
+  try {
+    const cplx<T> *X = x.as<cplx<T>>();
+    cplx<T> *HX = hx.as<cplx<T>>();
+    const int n3 = s.grid[2];
+    auto best_of = [&](int &knob, const std::vector<int> &cand) {
+      int bestv = knob;
+      float bestt = 1e30f;
+      for (int v : cand) {
+        knob = v;
+        const float t = time_apply<T>(b, sys, X, HX, nb, st, e0, e1);
+        if (t < bestt) {
+          bestt = t;
+          bestv = v;
+        }
+      }
+      knob = bestv;
+      return bestt;
+    };
+    std::vector<int> tiles;
+    for (int t : {2, 4, 8, 16, 32, 64})
+      if (sizeof(cplx<T>) * (size_t)t * (n3 + 1) <= 163840 && t <= std::max(1, s.ncol)) tiles.push_back(t);
+    float t = best_of(s.tile_z, tiles);
+    const bool tab = fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]);
+    if (tab) {
+      if (plane_lds_bytes<T>(s.grid[0], s.grid[1]) <= kSmallPlaneLds)
+        t = best_of(s.plane_form, {0, 1, 2, 3});
+      else
+        t = best_of(s.plane_form, {0, 2});
+    }
+    if (s.nproj > 0) t = best_of(s.ip_blocks, {256, 512, 1024, 2048});
+    if (ms_out) *ms_out = t;
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  DKS_HIP(hipEventDestroy(e0));
+  DKS_HIP(hipEventDestroy(e1));
+}
+}  // namespace dks
+
+extern "C" dks_status dks_autotune(dks_basis *b, int nsys, const int *sys, const int *nb,
+                                   dks_prec prec, void *stream) {
+  using namespace dks;
+  return guarded([&]() -> dks_status {
+    DKS_REQUIRE(b && nsys >= 0 && (nsys == 0 || (sys && nb)), DKS_EINVAL, "bad argument");
+    for (int i = 0; i < nsys; ++i)
+      DKS_REQUIRE(sys[i] >= 0 && sys[i] < (int)b->sys.size() && nb[i] >= 1, DKS_EINVAL,
+                  "bad system index or band count");
+    DKS_HIP(hipSetDevice(b->device));
+    hipStream_t st = (hipStream_t)stream;
+    ProfPause no_events;
+    for (int i = 0; i < nsys; ++i) {
+      if (prec == DKS_FP64)
+        tune_system<double>(b, sys[i], nb[i], st, nullptr);
+      else
+        tune_system<float>(b, sys[i], nb[i], st, nullptr);
+    }
+    return DKS_OK;
+  });
+}
+
+extern "C" dks_status dks_get_tuning(const dks_basis *b, int sys, int *tile_z, int *plane_form,
+                                     int *ip_blocks) {
+  using namespace dks;
+  return guarded([&]() -> dks_status {
+    DKS_REQUIRE(b && sys >= 0 && sys < (int)b->sys.size(), DKS_EINVAL, "bad argument");
+    const System &s = *b->sys[sys];
+    if (tile_z) *tile_z = s.tile_z;
+    if (plane_form) {
+      const bool fits = plane_lds_bytes<double>(s.grid[0], s.grid[1]) <= kSmallPlaneLds;
+      *plane_form = s.plane_form >= 0 ? s.plane_form : (fits ? 1 : 0);
+    }
+    if (ip_blocks) *ip_blocks = s.ip_blocks > 0 ? s.ip_blocks : 1024;
+    return DKS_OK;
+  });
+}
+
+extern "C" dks_status dks_set_tuning(dks_basis *b, int sys, int tile_z, int plane_form,
+                                     int ip_blocks) {
+  using namespace dks;
+  return guarded([&]() -> dks_status {
+    DKS_REQUIRE(b && sys >= 0 && sys < (int)b->sys.size(), DKS_EINVAL, "bad argument");
+    System &s = *b->sys[sys];
+    DKS_REQUIRE(tile_z >= 1 && tile_z <= 64 && sizeof(double2) * (size_t)tile_z * (s.grid[2] + 1) <= 163840,
+                DKS_EINVAL, "tile_z out of range for this grid");
+    DKS_REQUIRE(plane_form >= -1 && plane_form <= 3, DKS_EINVAL, "plane_form must be in [-1, 3]");
+    DKS_REQUIRE(ip_blocks >= 0 && ip_blocks <= 65536, DKS_EINVAL, "ip_blocks out of range");
+    s.tile_z = tile_z;
+    s.plane_form = plane_form;
+    s.ip_blocks = ip_blocks;
     return DKS_OK;
   });
 }

@@ -1378,6 +1378,8 @@ static size_t rr_vec_lds_bytes(int nz) {
   return fixed + std::max(slots, refl + ucs);
 }
 
+size_t rr_scratch_bytes(int nz, int nkeep) { return RRScratch::bytes(nz, nkeep); }
+
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info,
                    double *dinfo, DevBuf &scratch, hipStream_t st, long long *tstamp,

@@ -87,17 +87,27 @@ struct Solver {
 
 // Lanes of dks_lobpcgf_solve_batch: a solver workspace and a stream each,
 // kept with the basis so that repeated batches reuse their allocations.
-// Eight lanes on the four hardware queues a process gets by default: each lane
-// waits on the host a few times per iteration, and a second lane on the same
-// queue keeps it fed meanwhile (64-system batch: 4.1 s with 4 lanes, 3.3 s with 8).
-constexpr int kBatchLanes = 8;
+// Two lanes per hardware queue the process has (GPU_MAX_HW_QUEUES, 4 unless
+// set): each lane waits on the host a few times per iteration, and a second
+// lane on the same queue keeps it fed meanwhile (64-system batch on 4 queues:
+// 4.1 s with 4 lanes, 3.3 s with 8).
+constexpr int kMaxBatchLanes = 32;
+static int batch_lanes() {
+  static int v = 0;
+  if (!v) {
+    const char *e = std::getenv("GPU_MAX_HW_QUEUES");
+    const int q = (e && std::atoi(e) > 0) ? std::atoi(e) : 4;
+    v = std::max(1, std::min(kMaxBatchLanes, 2 * q));
+  }
+  return v;
+}
 struct Lane {
   Solver sv;
   hipStream_t st = nullptr;
   hipEvent_t done = nullptr;
 };
 struct BatchLanes {
-  Lane lane[kBatchLanes];
+  Lane lane[kMaxBatchLanes];
   ~BatchLanes() {
     for (auto &l : lane) {
       if (l.done) (void)hipEventDestroy(l.done);
@@ -108,10 +118,12 @@ struct BatchLanes {
 
 // The basis keeps one Solver for the unbatched entry point and, once a batch
 // has run, its lanes.
+struct GraphPool;
 struct SolverSet {
   Solver main;
   BatchLanes *lanes = nullptr;
-  ~SolverSet() { delete lanes; }
+  GraphPool *graph = nullptr;
+  ~SolverSet();
 };
 static SolverSet *solvers_of(dks_basis *b) {
   if (!b->solver) b->solver = new SolverSet();
@@ -686,6 +698,600 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
 }
 
 
+
+// ---------------------------------------------------------------------------
+// batches: lanes, and the graph-captured lockstep form
+// ---------------------------------------------------------------------------
+static BatchLanes &lanes_of(dks_basis *b) {
+  SolverSet *set = solvers_of(b);
+  if (!set->lanes) {
+    auto *bl = new BatchLanes();
+    set->lanes = bl;
+    for (int l = 0; l < batch_lanes(); ++l) {
+      DKS_HIP(hipStreamCreateWithFlags(&bl->lane[l].st, hipStreamNonBlocking));
+      DKS_HIP(hipEventCreateWithFlags(&bl->lane[l].done, hipEventDisableTiming));
+    }
+  }
+  return *set->lanes;
+}
+
+// Solves items[] of a batch on the lanes (a stream and a host thread each; a
+// free lane takes the next item, largest 4N n^2 first), item i with options
+// opt[i]; the lanes start after the work queued on `cst`, and `cst` waits for
+// them.  Statuses and messages go to rc[i], msg[i].
+static void run_on_lanes(dks_basis *b, const std::vector<int> &items, const int *sys, const int *n,
+                         void *const *X, double *const *lambda, double *const *resnorms,
+                         const std::vector<dks_solve_opts> &opt, dks_solve_info *info,
+                         hipStream_t cst, std::vector<dks_status> &rc,
+                         std::vector<std::string> &msg) {
+  const int ni = (int)items.size();
+  if (ni == 0) return;
+  BatchLanes &bl = lanes_of(b);
+  const int L = std::min(batch_lanes(), ni);
+  hipEvent_t start;
+  DKS_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  DKS_HIP(hipEventRecord(start, cst));
+  for (int l = 0; l < L; ++l) DKS_HIP(hipStreamWaitEvent(bl.lane[l].st, start, 0));
+  // items are taken in turn by whichever lane is free, the largest first
+  // (work ~ K n^2 per iteration), so that uneven sizes even out over lanes
+  std::vector<int> order(items);
+  auto work = [&](int i) {
+    const double K = 4.0 * b->sys[sys[i]]->N;
+    return K * (double)n[i] * (double)n[i];
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work(a) > work(c); });
+  std::atomic<int> next{0};
+  auto run_lane = [&](int l) {
+    const bool dev_ok = hipSetDevice(b->device) == hipSuccess;
+    for (int q = next++; q < ni; q = next++) {
+      const int i = order[q];
+      if (!dev_ok) {
+        rc[i] = DKS_EHIP;
+        continue;
+      }
+      try {
+        rc[i] = solve_one(b, sys[i], n[i], (double2 *)X[i], lambda[i],
+                          resnorms ? resnorms[i] : nullptr, opt[i], info ? &info[i] : nullptr,
+                          bl.lane[l].st, &bl.lane[l].sv, msg[i]);
+      } catch (...) {   // nothing may escape a lane thread
+        rc[i] = status_of_current_exception(msg[i]);
+      }
+    }
+  };
+  // a lane thread that cannot start leaves its items to the running lanes
+  std::vector<std::thread> th;
+  for (int l = 1; l < L; ++l) {
+    try {
+      th.emplace_back(run_lane, l);
+    } catch (...) {
+      break;
+    }
+  }
+  run_lane(0);
+  for (auto &t : th) t.join();
+  for (int l = 0; l < L; ++l) {
+    DKS_HIP(hipEventRecord(bl.lane[l].done, bl.lane[l].st));
+    DKS_HIP(hipStreamWaitEvent(cst, bl.lane[l].done, 0));
+  }
+  DKS_HIP(hipEventDestroy(start));
+}
+
+// ---- the graph-captured lockstep form --------------------------------------
+//
+// Every item iterates Algorithm 1 on a fixed shape: all n columns stay active
+// (no soft locking), the subspace is always [X, Y, P] of 3n rows (P = 0 in the
+// first step, whose zero columns the Rayleigh-Ritz drops as dependent), and P
+// is kept orthogonal to X.  Each iteration is then the same sequence of
+// launches with the same sizes, so the iterations of all items can be
+// captured once into one HIP graph (one branch per item on its own stream)
+// and replayed.  Two device kernels per iteration make the decisions the host
+// makes on the lanes: k_graph_check after the Rayleigh-Ritz (failed
+// factorisation, or a Ritz value below its predecessor by more than the block
+// residual allows) and k_graph_step after the residual norms (convergence of
+// the wanted columns, stagnation, iteration cap).  A decision sets the item's
+// skip flag, which every later kernel of the item reads first: a finished item
+// costs empty launches.  The host waits once per graph launch, for the flags.
+
+// per-item device flags (ints) and state (doubles)
+enum { kGfSkip = 0, kGfStatus, kGfIters, kGfStall, kGfXbuf, kGfBestNact, kGfCount = 8 };
+enum { kGsBest = 0, kGsRf, kGsResMax, kGsLam, kGsCount = kGsLam + 172 };
+
+// A broken-down step (the recurrences for H X and H P drifted in an
+// ill-conditioned basis, so the projected pencil no longer compresses H) shows
+// as Ritz values below the spectrum: the lowest positive-band eigenvalue is at
+// least min V_loc - ||V_NL|| (the kinetic part is >= 0 there), `lower`.  (A
+// Ritz value may legitimately fall by more than the block residual when the
+// subspace finds an eigenvalue the block had missed, which the graph form,
+// iterating every column, does often; so the bound is on the spectrum.)
+__global__ void k_graph_check(const int *__restrict__ info, const double *__restrict__ theta,
+                              int *__restrict__ flags, double *__restrict__ state, int n, int cur,
+                              int guard, double lower) {
+  if (threadIdx.x != 0 || flags[kGfSkip]) return;
+  int status = 0;
+  if (info[1] != 0) {
+    status = 2;   // too few independent directions, or too few Ritz values above the floor
+  } else if (guard && n > 0 && theta[0] < lower) {
+    status = 3;
+  }
+  if (status) {
+    flags[kGfStatus] = status;
+    flags[kGfXbuf] = cur;   // the last good block is still the one this step read
+    flags[kGfSkip] = 1;
+  }
+}
+
+__global__ void k_graph_step(const double *__restrict__ norm2, const double *__restrict__ theta,
+                             int *__restrict__ flags, double *__restrict__ state, int n, int nwant,
+                             double tol, int cap, int stall_window, int nxt, int init, int guard) {
+  __shared__ double act[kGsCount - kGsLam];
+  if (threadIdx.x != 0 || flags[kGfSkip]) return;
+  double rf2 = 0, mx = 0;
+  int nact = 0;
+  bool conv = true;
+  for (int j = 0; j < n; ++j) {
+    const double r = sqrt(fmax(norm2[j], 0.0));
+    rf2 += r * r;
+    if (j < nwant) mx = fmax(mx, r);   // buffer columns may rotate between states freely
+    if (j < nwant && !(r < tol)) {
+      conv = false;
+      act[nact++] = r;
+    }
+  }
+  // median of the wanted residuals not yet below tol (insertion sort, n <= 170)
+  for (int a = 1; a < nact; ++a) {
+    const double v = act[a];
+    int c = a - 1;
+    while (c >= 0 && act[c] > v) {
+      act[c + 1] = act[c];
+      --c;
+    }
+    act[c + 1] = v;
+  }
+  const double level = nact ? act[nact / 2] : 0.0;
+  int status = 0, xbuf = nxt;
+  if (!init) {
+    flags[kGfIters] += 1;
+    if (guard && !(mx <= 1e3 * state[kGsResMax])) {
+      status = 6;   // wanted residuals jumped: the step broke down, keep the block it read
+      xbuf = 1 - nxt;
+    }
+  }
+  if (!status) {
+    for (int j = 0; j < n; ++j) state[kGsLam + j] = theta[j];
+    state[kGsRf] = sqrt(rf2);
+    state[kGsResMax] = mx;
+    if (conv) {
+      status = 1;
+    } else if (!init && flags[kGfIters] >= cap) {
+      status = 5;
+    } else if (init || nact < flags[kGfBestNact]) {
+      flags[kGfBestNact] = nact;
+      state[kGsBest] = level;
+      flags[kGfStall] = 0;
+    } else if (level < 0.95 * state[kGsBest]) {
+      state[kGsBest] = level;
+      flags[kGfStall] = 0;
+    } else if (stall_window > 0 && ++flags[kGfStall] >= stall_window) {
+      status = 4;
+    }
+  }
+  if (status) {
+    flags[kGfStatus] = status;
+    flags[kGfXbuf] = xbuf;
+    flags[kGfSkip] = 1;
+  }
+}
+
+template <typename T>
+__global__ void k_zero_rows(cplx<T> *__restrict__ X, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) X[i] = cplx<T>{0, 0};
+}
+
+struct GraphItem {
+  int idx = 0;        // batch item
+  int sys = 0, n = 0, nwant = 0;
+  hipStream_t st = nullptr;
+  Solver *sv = nullptr;
+  Ctx x;              // operator context (filter constants, component count)
+  int *flags = nullptr;
+  double *state = nullptr;
+  double lower = 0;   // lower bound of the positive band (Ha, shifted)
+};
+
+struct GraphPool {
+  std::vector<Solver *> solvers;
+  std::vector<hipStream_t> streams;
+  DevBuf gflags, gstate;
+  HostBuf hflags;
+  hipStream_t origin = nullptr;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  ~GraphPool() {
+    for (auto *sv : solvers) delete sv;
+    for (auto st : streams) (void)hipStreamDestroy(st);
+    for (auto e : join) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (origin) (void)hipStreamDestroy(origin);
+  }
+  void ensure(int count) {
+    while ((int)solvers.size() < count) solvers.push_back(new Solver());
+    while ((int)streams.size() < count) {
+      hipStream_t st;
+      DKS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      streams.push_back(st);
+    }
+    while ((int)join.size() < count) {
+      hipEvent_t e;
+      DKS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      join.push_back(e);
+    }
+    if (!origin) DKS_HIP(hipStreamCreateWithFlags(&origin, hipStreamNonBlocking));
+    if (!fork) DKS_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  }
+};
+
+SolverSet::~SolverSet() {
+  delete lanes;
+  delete graph;
+}
+
+// Buffers of one item in precision T sized for the fixed-shape iteration, so
+// that nothing is allocated while it is captured.
+template <typename T>
+static void graph_reserve(GraphItem &g, Blocks<T> &bk) {
+  Solver &sv = *g.sv;
+  const int n = g.n, nz = 3 * n;
+  const int64_t K = g.x.K;
+  bk.ensure(n, K);
+  sv.gS.ensure(sizeof(double2) * nz * nz);
+  sv.gA.ensure(sizeof(double2) * nz * nz);
+  sv.Vz.ensure(sizeof(double2) * nz * n);
+  sv.Wxp.ensure(sizeof(double2) * n * n);
+  sv.theta.ensure(sizeof(double) * n);
+  sv.norms.ensure(sizeof(double) * n);
+  sv.rinfo.ensure(sizeof(int) * 4);
+  sv.rdinfo.ensure(sizeof(double) * 2);
+  sv.rrs.ensure(rr_scratch_bytes(nz, n));
+  sv.part.ensure(sizeof(double2) * std::max(gemm_ip_part_elems(nz, nz, K, true, true),
+                                            gemm_ip_part_elems(n, n, K, false, false)));
+  sv.part2.ensure(sizeof(double) * (size_t)n * (size_t)((K + 8191) / 8192));
+}
+
+// One iteration of item g reading Z[p], writing Z[1 - p]; every launch is
+// skipped once the item's flag is set.
+template <typename T>
+static void graph_iteration(GraphItem &g, Blocks<T> &bk, int p, double tol, int cap,
+                            int stall_window, double drop_tol) {
+  Solver &sv = *g.sv;
+  Ctx &x = g.x;
+  const int n = g.n, nz = 3 * n, q = 1 - p;
+  const int64_t K = x.K;
+  const int *skip = g.flags + kGfSkip;
+  hipStream_t st = g.st;
+  cplx<T> *Y = bk.z(p, n), *HY = bk.hz(p, n);
+  if (x.filt) {
+    apply_h<T>(x.b, x.sys, Y, bk.W.template as<cplx<T>>(), n, x.C, 1.0, st, sv.ws, x.ncomp, skip);
+    apply_h<T>(x.b, x.sys, bk.W.template as<cplx<T>>(), Y, n, x.C, 1.0 / (x.Om * x.Om), st, sv.ws,
+               x.ncomp, skip);
+  }
+  apply_h<T>(x.b, x.sys, Y, HY, n, 0.0, 1.0, st, sv.ws, x.ncomp, skip);
+  gemm_ip<T>(bk.z(p, 0), nullptr, nz, bk.z(p, 0), nullptr, nz, bk.hz(p, 0), K, sv.gS.as<double2>(),
+             sv.gA.as<double2>(), nz, sv.part, st, /*hermitian=*/true, skip);
+  rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, drop_tol, x.floor, nullptr,
+                sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
+                sv.rdinfo.as<double>(), sv.rrs, st, nullptr, skip);
+  DKS_LAUNCH("k_graph_check", k_graph_check, dim3(1), dim3(64), 0, st, sv.rinfo.as<int>(),
+             sv.theta.as<double>(), g.flags, g.state, n, p, x.guard ? 1 : 0, g.lower);
+  DKS_HIP(hipGetLastError());
+  // X = Z V, H X alike; P = [Y, P] V (the rows of V below the X block); then
+  // P and H P made orthogonal to the new X
+  gemm_up2<T>(bk.z(p, 0), bk.hz(p, 0), nullptr, nz, sv.Vz.as<double2>(), n, n, K, bk.z(q, 0),
+              bk.hz(q, 0), K, 0.0, st, 1.0, nullptr, skip);
+  gemm_up2<T>(bk.z(p, n), bk.hz(p, n), nullptr, nz - n, sv.Vz.as<double2>() + (size_t)n * n, n, n,
+              K, bk.z(q, 2 * n), bk.hz(q, 2 * n), K, 0.0, st, 1.0, nullptr, skip);
+  gemm_ip<T>(bk.z(q, 0), nullptr, n, bk.z(q, 2 * n), nullptr, n, nullptr, K, sv.Wxp.as<double2>(),
+             nullptr, n, sv.part, st, false, skip);
+  gemm_up2<T>(bk.z(q, 0), bk.hz(q, 0), nullptr, n, sv.Wxp.as<double2>(), n, n, K, bk.z(q, 2 * n),
+              bk.hz(q, 2 * n), K, 1.0, st, -1.0,
+              sizeof(T) == 8 ? "k_gemm_up.portho.f64" : "k_gemm_up.portho.f32", skip);
+  // R = H X - X Lambda, written where the next step's Y goes
+  residual<T>(bk.z(q, 0), bk.hz(q, 0), sv.theta.as<double>(), n, K, bk.z(q, n),
+              sv.norms.as<double>(), sv.part2, st, skip);
+  DKS_LAUNCH("k_graph_step", k_graph_step, dim3(1), dim3(64), 0, st, sv.norms.as<double>(),
+             sv.theta.as<double>(), g.flags, g.state, n, g.nwant, tol, cap, stall_window, q, 0,
+             x.guard ? 1 : 0);
+  DKS_HIP(hipGetLastError());
+}
+
+// The start of a graph stage for item g, eager on its stream: the block is in
+// Z[0] rows [0, n); n_init filter passes, H X, the Rayleigh-Ritz on X alone,
+// X = X V into Z[1], P = 0, R into Z[1]'s Y rows, and the first decisions.
+template <typename T>
+static void graph_start(GraphItem &g, Blocks<T> &bk, int n_init, double tol, double drop_tol) {
+  Solver &sv = *g.sv;
+  Ctx &x = g.x;
+  const int n = g.n;
+  const int64_t K = x.K;
+  hipStream_t st = g.st;
+  if (x.filt)
+    for (int k = 0; k < n_init; ++k) filter_inplace<T>(x, bk.z(0, 0), bk.W.template as<cplx<T>>(), n);
+  apply_h<T>(x.b, x.sys, bk.z(0, 0), bk.hz(0, 0), n, 0.0, 1.0, st, sv.ws, x.ncomp);
+  gemm_ip<T>(bk.z(0, 0), nullptr, n, bk.z(0, 0), nullptr, n, bk.hz(0, 0), K, sv.gS.as<double2>(),
+             sv.gA.as<double2>(), n, sv.part, st, true);
+  rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), n, n, drop_tol, x.floor, nullptr,
+                sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
+                sv.rdinfo.as<double>(), sv.rrs, st);
+  // a failed start leaves the item at status 2 with its block in Z[0]
+  DKS_LAUNCH("k_graph_check", k_graph_check, dim3(1), dim3(64), 0, st, sv.rinfo.as<int>(),
+             sv.theta.as<double>(), g.flags, g.state, n, 0, 0, g.lower);
+  const int *skip = g.flags + kGfSkip;
+  gemm_up2<T>(bk.z(0, 0), bk.hz(0, 0), nullptr, n, sv.Vz.as<double2>(), n, n, K, bk.z(1, 0),
+              bk.hz(1, 0), K, 0.0, st, 1.0, nullptr, skip);
+  const int64_t cnt = (int64_t)n * K;
+  DKS_LAUNCH("k_zero_rows", k_zero_rows<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+             bk.z(1, 2 * n), cnt);
+  DKS_LAUNCH("k_zero_rows", k_zero_rows<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+             bk.hz(1, 2 * n), cnt);
+  residual<T>(bk.z(1, 0), bk.hz(1, 0), sv.theta.as<double>(), n, K, bk.z(1, n),
+              sv.norms.as<double>(), sv.part2, st, skip);
+  DKS_LAUNCH("k_graph_step", k_graph_step, dim3(1), dim3(64), 0, st, sv.norms.as<double>(),
+             sv.theta.as<double>(), g.flags, g.state, n, g.nwant, tol, 1 << 30, 0, 1, 1,
+             x.guard ? 1 : 0);
+  DKS_HIP(hipGetLastError());
+}
+
+// Runs one graph stage in precision T for every item: the eager start, one
+// eager iteration (which also sizes every buffer), then a graph of `chunk`
+// iterations per item captured once and launched until every item has left.
+// Returns the iterations each item took (through its flags).
+template <typename T>
+static void graph_stage(GraphPool &pool, std::vector<GraphItem> &items,
+                        std::vector<Blocks<T> *> &blk, int n_init, double tol, int cap,
+                        int stall_window, double drop_tol, int chunk, int *flags_h) {
+  const int ni = (int)items.size();
+  const int nf = kGfCount * ni;
+  const auto t_begin = std::chrono::steady_clock::now();
+  // reset the flags and state of every item
+  {
+    std::vector<int> f0(nf, 0);
+    DKS_HIP(hipMemcpyAsync(pool.gflags.p, f0.data(), sizeof(int) * nf, hipMemcpyHostToDevice,
+                           pool.origin));
+    DKS_HIP(hipStreamSynchronize(pool.origin));
+  }
+  for (int i = 0; i < ni; ++i) {
+    graph_reserve<T>(items[i], *blk[i]);
+    graph_start<T>(items[i], *blk[i], n_init, tol, drop_tol);
+    // one eager iteration: Z[1] -> Z[0]
+    graph_iteration<T>(items[i], *blk[i], 1, tol, cap, stall_window, drop_tol);
+  }
+  for (int i = 0; i < ni; ++i) DKS_HIP(hipStreamSynchronize(items[i].st));
+  // capture `chunk` iterations of every item (Z[0] -> Z[1] -> Z[0] ...), one
+  // branch per item
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  {
+    ProfPause no_events;
+    DKS_HIP(hipStreamBeginCapture(pool.origin, hipStreamCaptureModeThreadLocal));
+    try {
+      DKS_HIP(hipEventRecord(pool.fork, pool.origin));
+      for (int i = 0; i < ni; ++i) {
+        DKS_HIP(hipStreamWaitEvent(items[i].st, pool.fork, 0));
+        for (int k = 0; k < chunk; ++k)
+          graph_iteration<T>(items[i], *blk[i], k & 1, tol, cap, stall_window, drop_tol);
+        DKS_HIP(hipEventRecord(pool.join[i], items[i].st));
+        DKS_HIP(hipStreamWaitEvent(pool.origin, pool.join[i], 0));
+      }
+    } catch (...) {
+      hipGraph_t dead = nullptr;
+      (void)hipStreamEndCapture(pool.origin, &dead);
+      if (dead) (void)hipGraphDestroy(dead);
+      throw;
+    }
+    DKS_HIP(hipStreamEndCapture(pool.origin, &graph));
+  }
+  const auto t_cap = std::chrono::steady_clock::now();
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    DKS_HIP(e);
+  }
+  try {
+    int *hf = flags_h;
+    // each launch runs `chunk` iterations of every item still in the stage
+    const auto t_inst = std::chrono::steady_clock::now();
+    const int max_launch = cap / chunk + 2;
+    int launches = 0;
+    for (int l = 0; l < max_launch; ++l, ++launches) {
+      DKS_HIP(hipMemcpyAsync(hf, pool.gflags.p, sizeof(int) * nf, hipMemcpyDeviceToHost,
+                             pool.origin));
+      DKS_HIP(hipStreamSynchronize(pool.origin));
+      bool all = true;
+      for (int i = 0; i < ni; ++i) all = all && hf[kGfCount * i + kGfSkip];
+      if (all) break;
+      DKS_HIP(hipGraphLaunch(exec, pool.origin));
+    }
+    DKS_HIP(hipStreamSynchronize(pool.origin));
+    DKS_HIP(hipMemcpy(hf, pool.gflags.p, sizeof(int) * nf, hipMemcpyDeviceToHost));
+    if (log_enabled()) {
+      auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+      std::fprintf(stderr,
+                   "{\"graph_stage\": {\"prec\": %d, \"items\": %d, \"chunk\": %d, \"start_ms\": %.1f, "
+                   "\"instantiate_ms\": %.1f, \"launches\": %d, \"run_ms\": %.1f}}\n",
+                   (int)sizeof(T), ni, chunk, ms(t_begin, t_cap), ms(t_cap, t_inst), launches,
+                   ms(t_inst, std::chrono::steady_clock::now()));
+    }
+  } catch (...) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    throw;
+  }
+  DKS_HIP(hipGraphExecDestroy(exec));
+  DKS_HIP(hipGraphDestroy(graph));
+}
+
+// dks_lobpcgf_solve_batch with batch_graph = 1.
+static void solve_batch_graph(dks_basis *b, int nsys, const int *sys, const int *n, void *const *X,
+                              double *const *lambda, double *const *resnorms,
+                              const std::vector<dks_solve_opts> &iopt, dks_solve_info *info,
+                              hipStream_t cst, std::vector<dks_status> &rc,
+                              std::vector<std::string> &msg) {
+  const dks_solve_opts &o = iopt[0];   // shared options (n_buffer differs per item)
+  SolverSet *set = solvers_of(b);
+  if (!set->graph) set->graph = new GraphPool();
+  GraphPool &pool = *set->graph;
+  pool.ensure(nsys);
+  const int chunk = std::max(2, o.graph_chunk + (o.graph_chunk & 1));
+  DKS_REQUIRE(o.mode >= 0 && o.mode <= 2, DKS_EINVAL, "bad mode");
+  DKS_REQUIRE(o.model == DKS_MODEL_DKS || o.model == DKS_MODEL_KSSO, DKS_EINVAL, "bad model");
+  const int ncomp = o.model == DKS_MODEL_KSSO ? 2 : 4;
+  pool.gflags.ensure(sizeof(int) * kGfCount * nsys);
+  pool.gstate.ensure(sizeof(double) * kGsCount * nsys);
+  int *hf = pool.hflags.as<int>((size_t)kGfCount * nsys);
+  // the stage starts after the work queued on the caller's stream
+  DKS_HIP(hipEventRecord(pool.fork, cst));
+  std::vector<GraphItem> items(nsys);
+  std::vector<dks_solve_info> inf(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    const System &s = *b->sys[sys[i]];
+    DKS_REQUIRE(n[i] >= 1 && n[i] <= 170 && n[i] <= ncomp * s.N, DKS_EINVAL,
+                "batch item " + std::to_string(i) + ": n must be in [1, min(170, ncomp N)]");
+    GraphItem &g = items[i];
+    g.idx = i;
+    g.sys = sys[i];
+    g.n = n[i];
+    g.nwant = n[i] - iopt[i].n_buffer;
+    g.st = pool.streams[i];
+    g.sv = pool.solvers[i];
+    g.flags = pool.gflags.as<int>() + kGfCount * i;
+    g.state = pool.gstate.as<double>() + kGsCount * i;
+    Ctx &x = g.x;
+    x.b = b;
+    x.sys = sys[i];
+    x.st = g.st;
+    x.sv = g.sv;
+    x.o = &iopt[i];
+    x.info = nullptr;
+    x.N = s.N;
+    x.ncomp = ncomp;
+    x.K = ncomp * (int64_t)s.N;
+    x.c2 = s.c * s.c;
+    x.filt = o.use_filter != 0 && ncomp == 4;
+    x.guard = x.filt || ncomp == 2;
+    double C0, O0;
+    dks_filter_constants(b, sys[i], &C0, &O0);
+    x.C = std::isnan(o.C) ? C0 : o.C;
+    x.Om = std::isnan(o.Omega) ? O0 : o.Omega;
+    DKS_REQUIRE(std::isfinite(x.C) && std::isfinite(x.Om) && x.Om != 0.0, DKS_EINVAL,
+                "bad C or Omega");
+    x.floor = x.filt ? -x.c2 : -std::numeric_limits<double>::infinity();
+    g.lower = b->pot[s.vsrc]->vmin - s.nl_bound - 1.0;
+    inf[i] = dks_solve_info{};
+    inf[i].min_ritz = std::numeric_limits<double>::infinity();
+    inf[i].C = x.C;
+    inf[i].Omega = x.Om;
+    DKS_HIP(hipStreamWaitEvent(g.st, pool.fork, 0));
+    if (o.kinetic_balance && ncomp == 4) kinetic_balance(b, sys[i], (double2 *)X[i], n[i], g.st);
+  }
+  std::vector<int> xbuf(nsys, 0), status(nsys, 0);
+  const bool mixed = o.mode != DKS_MODE_FP64;
+  int n_init64 = o.n_init;
+  if (mixed) {
+    // reduced-precision stage: FP32 to mixed_tol (or a stall), then FP64
+    std::vector<Blocks<float> *> b32(nsys);
+    for (int i = 0; i < nsys; ++i) {
+      b32[i] = &items[i].sv->b32;
+      b32[i]->ensure(n[i], items[i].x.K);
+      convert<double, float>((const double2 *)X[i], b32[i]->z(0, 0), items[i].x.K * n[i], items[i].st);
+    }
+    const double t32 = o.mixed_tol > 0 ? o.mixed_tol : 0.0;
+    graph_stage<float>(pool, items, b32, o.n_init, t32, std::max(2, o.mixed_iter), kStallFp32, 1e-5,
+                       chunk, hf);
+    for (int i = 0; i < nsys; ++i) {
+      const int xb = hf[kGfCount * i + kGfXbuf];
+      inf[i].iters_reduced = hf[kGfCount * i + kGfIters];
+      items[i].sv->b64.ensure(n[i], items[i].x.K);
+      convert<float, double>(b32[i]->z(xb, 0), items[i].sv->b64.z(0, 0), items[i].x.K * n[i],
+                             items[i].st);
+    }
+    n_init64 = kPolishFilters;
+  } else {
+    for (int i = 0; i < nsys; ++i) {
+      items[i].sv->b64.ensure(n[i], items[i].x.K);
+      DKS_HIP(hipMemcpyAsync(items[i].sv->b64.z(0, 0), X[i], sizeof(double2) * items[i].x.K * n[i],
+                             hipMemcpyDeviceToDevice, items[i].st));
+    }
+  }
+  std::vector<Blocks<double> *> b64(nsys);
+  for (int i = 0; i < nsys; ++i) b64[i] = &items[i].sv->b64;
+  graph_stage<double>(pool, items, b64, n_init64, o.tol, std::max(2, o.n_iter), kStallFp64, 1e-10,
+                      chunk, hf);
+  // results: converged items straight from the device; the others go back to
+  // the lanes from their last good block (a filtered restart)
+  std::vector<int> left;
+  std::vector<dks_solve_opts> opt(iopt);
+  for (int i = 0; i < nsys; ++i) {
+    GraphItem &g = items[i];
+    const int *f = hf + kGfCount * i;
+    status[i] = f[kGfStatus];
+    xbuf[i] = f[kGfXbuf];
+    inf[i].graph_exit = status[i];
+    inf[i].graph_iterations = f[kGfIters] + inf[i].iters_reduced;
+    inf[i].iterations = inf[i].graph_iterations;
+    const int64_t K = g.x.K;
+    DKS_HIP(hipMemcpyAsync(X[i], g.sv->b64.z(xbuf[i], 0), sizeof(double2) * K * n[i],
+                           hipMemcpyDeviceToDevice, g.st));
+    if (status[i] == 1) {
+      std::vector<double> th(n[i]), r2(n[i]);
+      DKS_HIP(hipMemcpyAsync(th.data(), g.sv->theta.p, sizeof(double) * n[i], hipMemcpyDeviceToHost, g.st));
+      DKS_HIP(hipMemcpyAsync(r2.data(), g.sv->norms.p, sizeof(double) * n[i], hipMemcpyDeviceToHost, g.st));
+      DKS_HIP(hipStreamSynchronize(g.st));
+      double mx = 0, mn = std::numeric_limits<double>::infinity();
+      int nconv = 0;
+      for (int j = 0; j < n[i]; ++j) {
+        lambda[i][j] = th[j];
+        const double r = std::sqrt(std::max(r2[j], 0.0));
+        if (resnorms) resnorms[i][j] = r;
+        mn = std::min(mn, th[j]);
+        if (j < g.nwant) {
+          mx = std::max(mx, r);
+          if (r < o.tol) ++nconv;
+        }
+      }
+      inf[i].converged = 1;
+      inf[i].n_converged = nconv;
+      inf[i].max_resnorm = mx;
+      inf[i].min_ritz = mn;
+      inf[i].h_applies = inf[i].iterations * n[i] * (g.x.filt ? 3 : 1);
+      rc[i] = DKS_OK;
+    } else {
+      DKS_HIP(hipStreamSynchronize(g.st));
+      left.push_back(i);
+      dks_solve_opts &oi = opt[i];
+      oi.mode = DKS_MODE_FP64;
+      oi.n_init = kPolishFilters;
+      oi.kinetic_balance = 0;
+      oi.n_iter = std::max(20, o.n_iter - f[kGfIters]);
+    }
+  }
+  for (int i = 0; i < nsys; ++i) {
+    DKS_HIP(hipEventRecord(pool.join[i], items[i].st));
+    DKS_HIP(hipStreamWaitEvent(cst, pool.join[i], 0));
+  }
+  std::vector<dks_solve_info> lane_inf(nsys);
+  run_on_lanes(b, left, sys, n, X, lambda, resnorms, opt, lane_inf.data(), cst, rc, msg);
+  for (int i : left) {
+    const int gi = inf[i].graph_iterations, ge = inf[i].graph_exit, ir = inf[i].iters_reduced;
+    inf[i] = lane_inf[i];
+    inf[i].graph_iterations = gi;
+    inf[i].graph_exit = ge;
+    inf[i].iterations += gi;
+    inf[i].iters_reduced += ir;
+  }
+  if (info)
+    for (int i = 0; i < nsys; ++i) info[i] = inf[i];
+}
+
 }  // namespace dks
 
 using namespace dks;
@@ -712,6 +1318,9 @@ void dks_default_opts(dks_solve_opts *o) {
   o->kinetic_balance = 0;
   o->use_filter = 1;
   o->model = DKS_MODEL_DKS;
+  o->batch_graph = 0;
+  o->graph_chunk = 8;
+  o->item_buffer = nullptr;
   o->n_buffer = 0;
 }
 
@@ -805,69 +1414,23 @@ dks_status dks_lobpcgf_solve_batch(dks_basis *b, int nsys, const int *sys, const
     if (opts) o = *opts; else dks_default_opts(&o);
     o.iter_ms = nullptr;   // per-iteration times are a single-solve feature
     DKS_HIP(hipSetDevice(b->device));
-    SolverSet *set = solvers_of(b);
-    if (!set->lanes) {
-      auto *bl = new BatchLanes();
-      set->lanes = bl;
-      for (auto &l : bl->lane) {
-        DKS_HIP(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
-        DKS_HIP(hipEventCreateWithFlags(&l.done, hipEventDisableTiming));
-      }
-    }
-    BatchLanes &bl = *set->lanes;
-    const int L = std::min(kBatchLanes, nsys);
-    // lanes start after the work already queued on the caller's stream
     hipStream_t cst = (hipStream_t)stream;
-    hipEvent_t start;
-    DKS_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-    DKS_HIP(hipEventRecord(start, cst));
-    for (int l = 0; l < L; ++l) DKS_HIP(hipStreamWaitEvent(bl.lane[l].st, start, 0));
     std::vector<dks_status> rc(nsys, DKS_OK);
     std::vector<std::string> msg(nsys);
-    // items are taken in turn by whichever lane is free, the largest first
-    // (work ~ K n^2 per iteration), so that uneven sizes even out over lanes
-    std::vector<int> order(nsys);
-    for (int i = 0; i < nsys; ++i) order[i] = i;
-    auto work = [&](int i) {
-      const double K = 4.0 * b->sys[sys[i]]->N;
-      return K * (double)n[i] * (double)n[i];
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work(a) > work(c); });
-    std::atomic<int> next{0};
-    auto run_lane = [&](int l) {
-      const bool dev_ok = hipSetDevice(b->device) == hipSuccess;
-      for (int q = next++; q < nsys; q = next++) {
-        const int i = order[q];
-        if (!dev_ok) {
-          rc[i] = DKS_EHIP;
-          continue;
-        }
-        try {
-          rc[i] = solve_one(b, sys[i], n[i], (double2 *)X[i], lambda[i],
-                            resnorms ? resnorms[i] : nullptr, o, info ? &info[i] : nullptr,
-                            bl.lane[l].st, &bl.lane[l].sv, msg[i]);
-        } catch (...) {   // nothing may escape a lane thread
-          rc[i] = status_of_current_exception(msg[i]);
-        }
-      }
-    };
-    // a lane thread that cannot start leaves its items to the running lanes
-    std::vector<std::thread> th;
-    for (int l = 1; l < L; ++l) {
-      try {
-        th.emplace_back(run_lane, l);
-      } catch (...) {
-        break;
-      }
+    std::vector<dks_solve_opts> opt(nsys, o);
+    for (int i = 0; i < nsys; ++i) {
+      if (o.item_buffer) opt[i].n_buffer = o.item_buffer[i];
+      opt[i].item_buffer = nullptr;
+      DKS_REQUIRE(opt[i].n_buffer >= 0 && opt[i].n_buffer < n[i], DKS_EINVAL,
+                  "batch item " + std::to_string(i) + ": n_buffer must be in [0, n)");
     }
-    run_lane(0);
-    for (auto &t : th) t.join();
-    // the caller's stream waits for every lane
-    for (int l = 0; l < L; ++l) {
-      DKS_HIP(hipEventRecord(bl.lane[l].done, bl.lane[l].st));
-      DKS_HIP(hipStreamWaitEvent(cst, bl.lane[l].done, 0));
+    if (o.batch_graph) {
+      solve_batch_graph(b, nsys, sys, n, X, lambda, resnorms, opt, info, cst, rc, msg);
+    } else {
+      std::vector<int> all(nsys);
+      for (int i = 0; i < nsys; ++i) all[i] = i;
+      run_on_lanes(b, all, sys, n, X, lambda, resnorms, opt, info, cst, rc, msg);
     }
-    DKS_HIP(hipEventDestroy(start));
     // errors first (most negative), then warnings
     dks_status worst = DKS_OK;
     for (int i = 0; i < nsys; ++i) {

@@ -1,16 +1,17 @@
-"""Write tests/golden/layered_crystal_seed0_k0.json: the 120 lowest positive-band
+"""Write tests/golden/layered_crystal_seed0_k0.json: the 40 lowest positive-band
 eigenvalues of k-point 0 of the layered crystal (hexagonal a = 7.8, c = 54 bohr,
 five atoms in quintuple-layer stacking, Ecut 25 Ha, 48 x 48 x 320 grid, seed 0;
 k-point 0 of the shifted 4 x 4 x 1 Monkhorst-Pack grid, N ~ 17.0k planewaves).
 
 Computed only with the FP64 oracle: the matrix-free Algorithm 1 of
-oracle/lobpcgf.py with 8 buffer columns (a 128-column block of which the first
-120 must converge), from two independent start blocks that must agree.  4N is
-about 68 000, out of reach of a dense diagonalisation, so that the 120 values
-are the lowest ones is backed by the two starts, not by a dense solve.
+oracle/lobpcgf.py with 16 buffer columns (a 56-column block of which the first
+40 must converge), from two independent start blocks that must agree.  4N is
+about 68 000, out of reach of a dense diagonalisation, so that the 40 values
+are the lowest ones is backed by the two starts, not by a dense solve.  (The
+full 120-band block of the library is compared on these 40; the oracle's
+numpy FFTs make 120 bands a matter of many hours.)
 
 Run from the repository root:  python tests/golden/make_layered_golden.py
-(about an hour on eight cores).
 """
 import json
 import os
@@ -25,8 +26,8 @@ sys.path.insert(0, ROOT)
 import sysgen  # noqa: E402
 from oracle import dks, lobpcgf  # noqa: E402
 
-N_WANT = 120
-N_BUFFER = 8
+N_WANT = 40
+N_BUFFER = 16
 
 
 def main():
