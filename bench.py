@@ -115,7 +115,7 @@ def main():
 
     # sixteen hardware queues (HIP's default is four): the batched solves run
     # two lanes per queue; must be set before the HIP runtime starts
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
     import numpy as np
     import torch
 

@@ -51,9 +51,13 @@ typedef enum {
   DKS_MODE_MIXED_FP32 = 1,    /* FP32 operator, filter, Gram and updates; FP64 Rayleigh-Ritz;
                                  then FP64 polish iterations to the requested tolerance */
   DKS_MODE_MIXED_BF16GRAM = 2 /* as MIXED_FP32 but, while the median residual of the FP32
-                                 stage exceeds 10 * mixed_tol, the Gram products take BF16
-                                 inputs (rounded to nearest even) with FP32 accumulation on
-                                 the matrix cores */
+                                 stage exceeds 10 * mixed_tol, the Gram products split each
+                                 FP32 input into two BF16 numbers (x ~ hi + lo, each rounded
+                                 to nearest even) and accumulate hi*hi + hi*lo + lo*hi in FP32
+                                 on the BF16 matrix cores (plain BF16 inputs are too coarse
+                                 for the Dirac Rayleigh-Ritz).  Three BF16 products per FP32
+                                 product: measured no faster than MIXED_FP32 (the Gram
+                                 launch takes about as long), kept as the studied option */
 } dks_mode;
 
 /* Which operator a solve works on (the modules of the paper's Table 1). */
