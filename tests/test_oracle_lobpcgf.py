@@ -148,3 +148,39 @@ def test_kinetic_balance_gives_free_eigenvectors():
         q2 = float(op.q[g] @ op.q[g])
         E = math.sqrt(s.c ** 2 * q2 + s.c ** 4) - s.c ** 2
         assert np.max(np.abs(HX[b] - E * X[b])) < 1e-9
+
+
+@pytest.mark.parametrize("max_dim", [16, 32])
+def test_davidson_f_matches_dense_definition(tiny, max_dim):
+    """The filter inside a block Davidson iteration (Sec. 3 opening, Sec. 5)
+    reaches the same answer as Algorithm 1: the 8 lowest positive-band
+    eigenvalues of the dense matrix to 1e-8 Ha, within each residual norm, and
+    no Ritz value in or below the gap.  max_dim = 16 restarts the space every
+    step or two, 32 lets it grow to four blocks."""
+    s, op, H, w, v = tiny
+    lam_ref, _ = lobpcgf.lowest_positive(H, 8, s.c)
+    phi = sysgen.start_block(op.miller, s.lattice, s.kpts[0], 8, 0)
+    r = lobpcgf.solve(op, 8, phi0=phi, tol=1e-9, n_iter=200, method="davidson", max_dim=max_dim)
+    assert r.converged
+    assert np.max(np.abs(r.eigvals - lam_ref)) < 1e-8
+    # |lambda - exact| <= ||r||, up to the dense solver's backward error eps ||H||
+    slack = 16 * np.finfo(float).eps * np.linalg.norm(H, 2)
+    assert np.all(np.abs(r.eigvals - lam_ref) <= r.resnorms + slack)
+    assert min(r.min_ritz_history) > -s.c ** 2
+
+
+def test_davidson_collapses_without_the_filter(tiny):
+    """Without F the Davidson space, like LOBPCG's, takes in the negative band
+    from a start block contaminated at 1e-15 (Sec. 3.1's argument holds for any
+    solver whose new directions are the residuals); with F it never does."""
+    s, op, H, w, v = tiny
+    phi = sysgen.start_block(op.miller, s.lattice, s.kpts[0], 8, 0)
+    X0 = lobpcgf.kinetic_balance(op, phi).reshape(8, -1).T
+    X0 = X0 / np.linalg.norm(X0, axis=0) + 1e-15 * v[:, [0]]
+    C_, Om = lobpcgf.filter_constants(op.spectrum_bounds(), s.c)
+    plain = lobpcgf.davidson_f(lobpcgf.block_apply(op), X0, 8, C_, Om, n_iter=12, tol=1e-9,
+                               use_filter=False)
+    assert min(plain.min_ritz_history) < -s.c ** 2
+    filt = lobpcgf.davidson_f(lobpcgf.block_apply(op), X0, 8, C_, Om, n_iter=12, tol=1e-9,
+                              use_filter=True)
+    assert min(filt.min_ritz_history) > -s.c ** 2
