@@ -69,6 +69,16 @@ typedef enum {
                           kinetic_balance are ignored */
 } dks_model;
 
+/* The iterative method a solve uses. */
+typedef enum {
+  DKS_METHOD_LOBPCG = 0,    /* Algorithm 1: LOBPCG-F (or standard LOBPCG, use_filter = 0) */
+  DKS_METHOD_DAVIDSON = 1   /* the filter inside a block Davidson iteration (the paper's remark
+                               that F can precondition other iterative solvers): the subspace
+                               keeps every filtered residual block f(H) R of the unconverged
+                               columns up to davidson_dim * n vectors, then restarts from the
+                               Ritz vectors; FP64 only */
+} dks_method;
+
 /* One (atom, l) block of separable projectors of Eq. (HGH): couplings of the
  * j = l + 1/2 channel (d_plus) and of the j = l - 1/2 channel (d_minus), each a
  * real symmetric n_rad x n_rad matrix (row-major, Ha).  Radial functions are
@@ -206,11 +216,15 @@ typedef struct {
                            iterates every column (no soft locking) and keeps P orthogonal
                            to X; items that leave it unconverged (stall, a failed
                            Rayleigh-Ritz, a broken-down step) are finished on the lanes
-                           from their last good block.  Default 0 */
+                           from their last good block.  Algorithm 1 only (method =
+                           DKS_METHOD_LOBPCG; else DKS_EINVAL).  Default 0 */
   int graph_chunk;      /* iterations per graph launch (even, >= 2).  Default 8 */
   const int *item_buffer; /* dks_lobpcgf_solve_batch only: optional caller-owned host array
                            of nsys buffer-column counts, item i taking item_buffer[i] in
                            place of n_buffer (each in [0, n[i])).  Default NULL */
+  int method;           /* dks_method.  Default DKS_METHOD_LOBPCG */
+  int davidson_dim;     /* DKS_METHOD_DAVIDSON: largest subspace, in multiples of n (>= 2;
+                           capped at 510 vectors).  Default 4 */
 } dks_solve_opts;
 
 typedef struct {

@@ -18,6 +18,7 @@ _LIBPATH = os.path.join(_HERE, "libdks.so")
 DKS_FP64, DKS_FP32 = 0, 1
 MODE_FP64, MODE_MIXED_FP32, MODE_MIXED_BF16GRAM = 0, 1, 2
 MODEL_DKS, MODEL_KSSO = 0, 1
+METHOD_LOBPCG, METHOD_DAVIDSON = 0, 1
 
 _STATUS = {0: "DKS_OK", -1: "DKS_EINVAL", -2: "DKS_ENOMEM", -3: "DKS_EHIP", -4: "DKS_ECHOL",
            -5: "DKS_ECOLLAPSE", -6: "DKS_EINTERNAL", 1: "DKS_WNOTCONV"}
@@ -49,7 +50,8 @@ class SolveOpts(ct.Structure):
                 ("kinetic_balance", ct.c_int), ("use_filter", ct.c_int),
                 ("iter_ms", ct.POINTER(ct.c_double)), ("n_buffer", ct.c_int), ("model", ct.c_int),
                 ("batch_graph", ct.c_int), ("graph_chunk", ct.c_int),
-                ("item_buffer", ct.POINTER(ct.c_int))]
+                ("item_buffer", ct.POINTER(ct.c_int)), ("method", ct.c_int),
+                ("davidson_dim", ct.c_int)]
 
 
 class SolveInfo(ct.Structure):

@@ -80,6 +80,7 @@ struct HostBuf {
 struct Solver {
   Blocks<double> b64;
   Blocks<float> b32;
+  DevBuf dv, dhv;   // Davidson subspace V and H V (up to davidson_dim x n rows)
   DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2, tst;
   HostBuf h_rr, h_lam, h_res, h_act, h_vp;
   Workspace ws;   // H.X scratch of this solver's applies
@@ -599,6 +600,121 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   return s.converged ? DKS_OK : DKS_WNOTCONV;
 }
 
+// The filter inside a Davidson-type solver (the paper's closing remark that F
+// can precondition other iterative methods): a block Davidson iteration in
+// FP64 whose subspace V keeps every filtered residual block f(H) R of the
+// unconverged columns until it would exceed max_dim rows, then restarts
+// from the current Ritz vectors.  Each step is a Rayleigh-Ritz on span V (the
+// same Gram products and FP64 reduction as Algorithm 1, n lowest Ritz pairs
+// above the floor), X = V Vz and H X = (H V) Vz, the residuals, and one
+// filter + H application to the new block.  The result goes to Z[0] rows
+// [0, n) of `bk` with s.lam and s.res.
+static dks_status run_davidson(Ctx &x, Blocks<double> &bk, LoopState<double> &s, int n, int n_init,
+                               double tol, int max_iter, int max_dim) {
+  Solver &sv = *x.sv;
+  const int64_t K = x.K;
+  const size_t rowb = sizeof(double2) * (size_t)K;
+  sv.dv.ensure(rowb * max_dim);
+  sv.dhv.ensure(rowb * max_dim);
+  double2 *V = sv.dv.as<double2>(), *HV = sv.dhv.as<double2>();
+  auto row = [&](double2 *base, int r) { return base + (size_t)r * K; };
+  // start block: already in Z[0] rows [0, n)
+  DKS_HIP(hipMemcpyAsync(V, bk.z(0, 0), rowb * n, hipMemcpyDeviceToDevice, x.st));
+  if (x.filt)
+    for (int k = 0; k < n_init; ++k) filter_inplace<double>(x, V, bk.W.as<double2>(), n);
+  apply_h<double>(x.b, x.sys, V, HV, n, 0.0, 1.0, x.st, sv.ws, x.ncomp);
+  if (x.info) x.info->h_applies += n;
+  int dim = n;
+  s.cur = 0;
+  s.converged = false;
+  s.iters = 0;
+  const int nwant = n - x.o->n_buffer;
+  std::vector<double2> hV;
+  double2 *Xb = bk.z(0, 0), *HXb = bk.hz(0, 0);
+  for (;;) {
+    // Rayleigh-Ritz on span V (retried from the Ritz vectors alone if the
+    // subspace turned numerically dependent)
+    bool ok = false;
+    for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
+      sv.gS.ensure(sizeof(double2) * dim * dim);
+      sv.gA.ensure(sizeof(double2) * dim * dim);
+      gemm_ip<double>(V, nullptr, dim, V, nullptr, dim, HV, K, sv.gS.as<double2>(),
+                      sv.gA.as<double2>(), dim, sv.part, x.st, true);
+      sv.Vz.ensure(sizeof(double2) * dim * n);
+      sv.theta.ensure(sizeof(double) * n);
+      sv.rinfo.ensure(sizeof(int) * 4);
+      sv.rdinfo.ensure(sizeof(double) * 2);
+      rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), dim, n, 1e-10, x.floor, nullptr,
+                    sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
+                    sv.rdinfo.as<double>(), sv.rrs, x.st);
+      double2 *hr = sv.h_rr.as<double2>(2 + (size_t)n);
+      int *inf4 = reinterpret_cast<int *>(hr);
+      double *dinfo = reinterpret_cast<double *>(hr + 1);
+      double *hth = reinterpret_cast<double *>(hr + 2);
+      DKS_HIP(hipMemcpyAsync(inf4, sv.rinfo.p, sizeof(int) * 4, hipMemcpyDeviceToHost, x.st));
+      DKS_HIP(hipMemcpyAsync(dinfo, sv.rdinfo.p, sizeof(double) * 2, hipMemcpyDeviceToHost, x.st));
+      DKS_HIP(hipMemcpyAsync(hth, sv.theta.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
+      DKS_HIP(hipStreamSynchronize(x.st));
+      if (inf4[1] == 0) {
+        ok = true;
+        s.lam.assign(hth, hth + n);
+        if (x.info) {
+          x.info->basis_drops += inf4[2];
+          x.info->neg_ritz_discarded += inf4[3];
+          x.info->min_ritz = std::min(x.info->min_ritz, dinfo[0]);
+        }
+      } else if (dim > n && s.iters > 0) {
+        // restart from the last Ritz vectors (still in Xb, HXb)
+        DKS_HIP(hipMemcpyAsync(V, Xb, rowb * n, hipMemcpyDeviceToDevice, x.st));
+        DKS_HIP(hipMemcpyAsync(HV, HXb, rowb * n, hipMemcpyDeviceToDevice, x.st));
+        dim = n;
+        if (x.info) x.info->p_restarts += 1;
+      } else {
+        break;
+      }
+    }
+    if (!ok) throw Error{DKS_ECHOL, "the Davidson subspace is numerically rank deficient"};
+    // Ritz vectors, residuals
+    gemm_up2<double>(V, HV, nullptr, dim, sv.Vz.as<double2>(), n, n, K, Xb, HXb, K, 0.0, x.st);
+    sv.lam.ensure(sizeof(double) * n);
+    sv.norms.ensure(sizeof(double) * n);
+    residual<double>(Xb, HXb, sv.theta.as<double>(), n, K, bk.R.as<double2>(), sv.norms.as<double>(),
+                     sv.part2, x.st);
+    double *hres = sv.h_res.as<double>(n);
+    DKS_HIP(hipMemcpyAsync(hres, sv.norms.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
+    DKS_HIP(hipStreamSynchronize(x.st));
+    s.res.assign(hres, hres + n);
+    for (auto &r : s.res) r = std::sqrt(std::max(r, 0.0));
+    s.converged = true;
+    for (int j = 0; j < nwant; ++j)
+      if (!(s.res[j] < tol)) s.converged = false;
+    if (s.converged || s.iters >= max_iter) break;
+    s.iters++;
+    if (x.info) x.info->iterations++;
+    // new block: the filtered residuals of the columns not yet below tol
+    std::vector<int> act;
+    for (int j = 0; j < n; ++j)
+      if (!(s.res[j] < tol)) act.push_back(j);
+    const int m = (int)act.size();
+    if (dim + m > max_dim) {
+      DKS_HIP(hipMemcpyAsync(V, Xb, rowb * n, hipMemcpyDeviceToDevice, x.st));
+      DKS_HIP(hipMemcpyAsync(HV, HXb, rowb * n, hipMemcpyDeviceToDevice, x.st));
+      dim = n;
+    }
+    sv.idx.ensure(sizeof(int) * n);
+    int *ha = sv.h_act.as<int>(n);
+    std::copy(act.begin(), act.end(), ha);
+    DKS_HIP(hipMemcpyAsync(sv.idx.p, ha, sizeof(int) * m, hipMemcpyHostToDevice, x.st));
+    gather_rows<double>(bk.R.as<double2>(), sv.idx.as<int>(), m, K, row(V, dim), x.st);
+    if (x.filt) filter_inplace<double>(x, row(V, dim), bk.W.as<double2>(), m);
+    apply_h<double>(x.b, x.sys, row(V, dim), row(HV, dim), m, 0.0, 1.0, x.st, sv.ws, x.ncomp);
+    if (x.info) x.info->h_applies += m;
+    dim += m;
+  }
+  s.cur = 0;
+  return s.converged ? DKS_OK : DKS_WNOTCONV;
+}
+
 // One solve of Algorithm 1 on `st` with solver workspace `sv`; returns the
 // status and, for a nonzero one, its message.  Throws dks::Error on failures.
 static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *lambda,
@@ -642,7 +758,16 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
     if (o.kinetic_balance && ncomp == 4) kinetic_balance(b, sys, Xu, n, st);
     dks_status rc = DKS_OK;
     LoopState<double> s64;
-    if (o.mode == DKS_MODE_FP64) {
+    DKS_REQUIRE(o.method == DKS_METHOD_LOBPCG || o.method == DKS_METHOD_DAVIDSON, DKS_EINVAL,
+                "bad method");
+    if (o.method == DKS_METHOD_DAVIDSON) {
+      DKS_REQUIRE(o.mode == DKS_MODE_FP64, DKS_EINVAL, "the Davidson form runs in FP64 only");
+      const int max_dim = std::min(510, std::max(2, o.davidson_dim) * n);
+      DKS_REQUIRE(max_dim >= 2 * n, DKS_EINVAL, "Davidson subspace too small (davidson_dim n > 510)");
+      x.sv->b64.ensure(n, x.K);
+      DKS_HIP(hipMemcpyAsync(x.sv->b64.z(0, 0), Xu, sizeof(double2) * x.K * n, hipMemcpyDeviceToDevice, st));
+      rc = run_davidson(x, x.sv->b64, s64, n, o.n_init, o.tol, o.n_iter, max_dim);
+    } else if (o.mode == DKS_MODE_FP64) {
       x.sv->b64.ensure(n, x.K);
       DKS_HIP(hipMemcpyAsync(x.sv->b64.z(0, 0), Xu, sizeof(double2) * x.K * n, hipMemcpyDeviceToDevice, st));
       rc = run_stage<double>(x, x.sv->b64, s64, n, o.n_init, o.tol, o.n_iter, 1e-10, kStallFp64,
@@ -1321,6 +1446,8 @@ void dks_default_opts(dks_solve_opts *o) {
   o->batch_graph = 0;
   o->graph_chunk = 8;
   o->item_buffer = nullptr;
+  o->method = DKS_METHOD_LOBPCG;
+  o->davidson_dim = 4;
   o->n_buffer = 0;
 }
 
@@ -1424,6 +1551,8 @@ dks_status dks_lobpcgf_solve_batch(dks_basis *b, int nsys, const int *sys, const
       DKS_REQUIRE(opt[i].n_buffer >= 0 && opt[i].n_buffer < n[i], DKS_EINVAL,
                   "batch item " + std::to_string(i) + ": n_buffer must be in [0, n)");
     }
+    DKS_REQUIRE(!(o.batch_graph && o.method != DKS_METHOD_LOBPCG), DKS_EINVAL,
+                "the graph-captured batch runs Algorithm 1 only (method = DKS_METHOD_LOBPCG)");
     if (o.batch_graph) {
       solve_batch_graph(b, nsys, sys, n, X, lambda, resnorms, opt, info, cst, rc, msg);
     } else {
