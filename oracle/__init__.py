@@ -13,12 +13,16 @@ against the paper:
                   with the local and separable spin-orbit parts of Eq. (HGH),
                   built densely and applied matrix-free through FFTs;
 * ``lobpcgf``  -- the filter of Eq. (filter), Algorithm 1 (LOBPCG-F, and
-                  plain LOBPCG when the filter is switched off), and the
-                  dense definition of the answer: the lowest n eigenpairs of
-                  the positive energy band.
+                  plain LOBPCG when the filter is switched off), the filter
+                  inside a block Davidson iteration, and the dense definition
+                  of the answer: the lowest n eigenpairs of the positive
+                  energy band;
+* ``scf``      -- the self-consistent field loop around it: Eq. (density),
+                  the Hartree and LDA parts of V_hxc, Fermi occupations and
+                  Anderson mixing with the Kerker preconditioner (Sec. 4).
 
 Every function names the passage it follows.  No function here is
 "parity unpinned": each is checked in ``tests/test_oracle_*.py`` against
 closed forms, invariants or brute force.
 """
-from . import dks, lobpcgf  # noqa: F401
+from . import dks, lobpcgf, scf  # noqa: F401
