@@ -127,6 +127,33 @@ struct Lines {
   __device__ __forceinline__ int base(int l) const { return (rows ? rows[l] : l) * ld; }
 };
 
+// A thread's walk over the tasks t = tid, tid + nthr, ... of a step on nl
+// lines, task t standing for (outer index t / nl, line t % nl).  The quotient
+// and remainder are carried from task to task (one division per walk, none
+// per task; an integer division costs some twenty instructions).
+struct Walk {
+  int nl, q0, r0, dq, dr, tid, nthr;
+};
+__device__ __forceinline__ Walk walk(int nl, int tid = threadIdx.x, int nthr = blockDim.x) {
+  if (nl <= 0) return Walk{nl, 0, 0, 0, 0, tid, nthr};   // no tasks
+  const int q0 = tid / nl, dq = nthr / nl;
+  return Walk{nl, q0, tid - q0 * nl, dq, nthr - dq * nl, tid, nthr};
+}
+// runs body(outer, line) over the walk's tasks below `tasks`
+template <typename F>
+__device__ __forceinline__ void for_tasks(const Walk &w, int tasks, F &&body) {
+  int q = w.q0, l = w.r0;
+  for (int t = w.tid; t < tasks; t += w.nthr) {
+    body(q, l);
+    q += w.dq;
+    l += w.dr;
+    if (l >= w.nl) {
+      l -= w.nl;
+      ++q;
+    }
+  }
+}
+
 // twiddle w_n^{S e} from the table tw[t] = exp(-2 pi i t / n)
 template <int S, typename C>
 __device__ __forceinline__ C twt(const C *tw, int e) {
@@ -135,15 +162,13 @@ __device__ __forceinline__ C twt(const C *tw, int e) {
   return w;
 }
 
-// inverse step 1 on nl lines (in place)
+// inverse step 1 on nl lines (in place); `w` walks nl lines
 template <int A, int B, typename T>
-__device__ __forceinline__ void inv_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
-                                          int tid = threadIdx.x, int nthr = blockDim.x) {
+__device__ __forceinline__ void inv_step1(typename CT<T>::c *buf, const Walk &w, Lines L,
+                                          const typename CT<T>::c *tw) {
   using C = typename CT<T>::c;
   if constexpr (A > 1) {
-    const int tasks = nl * B;
-    for (int t = tid; t < tasks; t += nthr) {
-      const int b = t / nl, l = t - (t / nl) * nl;
+    for_tasks(w, w.nl * B, [&](int b, int l) {
       const int base = L.base(l) + b * L.stride;
       C v[A];
 #pragma unroll
@@ -153,19 +178,16 @@ __device__ __forceinline__ void inv_step1(typename CT<T>::c *buf, int nl, Lines 
       for (int ka = 1; ka < A; ++ka) v[ka] = cmul(v[ka], twt<+1>(tw, b * ka));
 #pragma unroll
       for (int a = 0; a < A; ++a) buf[base + B * a * L.stride] = v[a];
-    }
+    });
   }
 }
 
 // forward step 1' on nl lines (in place): DFT_A over k_a, natural output
 template <int A, int B, typename T>
-__device__ __forceinline__ void fwd_step1(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
-                                          int tid = threadIdx.x, int nthr = blockDim.x) {
+__device__ __forceinline__ void fwd_step1(typename CT<T>::c *buf, const Walk &w, Lines L) {
   using C = typename CT<T>::c;
   if constexpr (A > 1) {
-    const int tasks = nl * B;
-    for (int t = tid; t < tasks; t += nthr) {
-      const int b = t / nl, l = t - (t / nl) * nl;
+    for_tasks(w, w.nl * B, [&](int b, int l) {
       const int base = L.base(l) + b * L.stride;
       C v[A];
 #pragma unroll
@@ -173,18 +195,15 @@ __device__ __forceinline__ void fwd_step1(typename CT<T>::c *buf, int nl, Lines 
       Codelet<A, -1, T>::run(v);
 #pragma unroll
       for (int a = 0; a < A; ++a) buf[base + B * a * L.stride] = v[a];
-    }
+    });
   }
 }
 
 // inverse step 2 on the blocks (in place)
 template <int A, int B, typename T>
-__device__ __forceinline__ void inv_step2(typename CT<T>::c *buf, int nl, Lines L, int tid = threadIdx.x,
-                                          int nthr = blockDim.x) {
+__device__ __forceinline__ void inv_step2(typename CT<T>::c *buf, const Walk &w, Lines L) {
   using C = typename CT<T>::c;
-  const int tasks = nl * A;
-  for (int t = tid; t < tasks; t += nthr) {
-    const int ka = t / nl, l = t - (t / nl) * nl;
+  for_tasks(w, w.nl * A, [&](int ka, int l) {
     const int base = L.base(l) + B * ka * L.stride;
     C v[B];
 #pragma unroll
@@ -192,17 +211,15 @@ __device__ __forceinline__ void inv_step2(typename CT<T>::c *buf, int nl, Lines 
     Codelet<B, +1, T>::run(v);
 #pragma unroll
     for (int b = 0; b < B; ++b) buf[base + b * L.stride] = v[b];
-  }
+  });
 }
 
 // forward step 2' on the blocks (in place), including the w_n^{-b k_a} twiddle
 template <int A, int B, typename T>
-__device__ __forceinline__ void fwd_step2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
-                                          int tid = threadIdx.x, int nthr = blockDim.x) {
+__device__ __forceinline__ void fwd_step2(typename CT<T>::c *buf, const Walk &w, Lines L,
+                                          const typename CT<T>::c *tw) {
   using C = typename CT<T>::c;
-  const int tasks = nl * A;
-  for (int t = tid; t < tasks; t += nthr) {
-    const int ka = t / nl, l = t - (t / nl) * nl;
+  for_tasks(w, w.nl * A, [&](int ka, int l) {
     const int base = L.base(l) + B * ka * L.stride;
     C v[B];
 #pragma unroll
@@ -214,19 +231,17 @@ __device__ __forceinline__ void fwd_step2(typename CT<T>::c *buf, int nl, Lines 
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) buf[base + b * L.stride] = v[b];
-  }
+  });
 }
 
 // inverse step 2, x V (scrambled layout, element-wise), forward step 2' fused.
 // V for line l, position p is Vp[l * vls + p * vps].
 template <int A, int B, typename T>
-__device__ __forceinline__ void inv2_mul_fwd2(typename CT<T>::c *buf, int nl, Lines L, const typename CT<T>::c *tw,
-                              const T *__restrict__ Vp, int vls, int vps, int tid = threadIdx.x,
-                              int nthr = blockDim.x) {
+__device__ __forceinline__ void inv2_mul_fwd2(typename CT<T>::c *buf, const Walk &w, Lines L,
+                                              const typename CT<T>::c *tw, const T *__restrict__ Vp,
+                                              int vls, int vps) {
   using C = typename CT<T>::c;
-  const int tasks = nl * A;
-  for (int t = tid; t < tasks; t += nthr) {
-    const int ka = t / nl, l = t - (t / nl) * nl;
+  for_tasks(w, w.nl * A, [&](int ka, int l) {
     const int base = L.base(l) + B * ka * L.stride;
     const T *vl = Vp + (size_t)l * vls + (size_t)(B * ka) * vps;
     C v[B];
@@ -245,7 +260,7 @@ __device__ __forceinline__ void inv2_mul_fwd2(typename CT<T>::c *buf, int nl, Li
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) buf[base + b * L.stride] = v[b];
-  }
+  });
 }
 
 // ---- supported lengths and their (A, B) split --------------------------------

@@ -75,10 +75,11 @@ __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__res
   __syncthreads();
   const fft2::Lines Lz{nullptr, ld, 1};
   if constexpr (kTab) {
+    const fft2::Walk Wz = fft2::walk(w);
     fft2::dispatch_z(n3, [&]<int A, int B>() {
-      fft2::inv_step1<A, B, T>(lines, w, Lz, twz);
+      fft2::inv_step1<A, B, T>(lines, Wz, Lz, twz);
       __syncthreads();
-      fft2::inv_step2<A, B, T>(lines, w, Lz);
+      fft2::inv_step2<A, B, T>(lines, Wz, Lz);
     });
   } else {
     fft_lines<+1, T>(lines, w, nullptr, ld, 1, pz, twz);
@@ -135,10 +136,11 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
   __syncthreads();
   const fft2::Lines Lz{nullptr, ld, 1};
   if constexpr (kTab) {
+    const fft2::Walk Wz = fft2::walk(w);
     fft2::dispatch_z(n3, [&]<int A, int B>() {
-      fft2::fwd_step2<A, B, T>(lines, w, Lz, twz);
+      fft2::fwd_step2<A, B, T>(lines, Wz, Lz, twz);
       __syncthreads();
-      fft2::fwd_step1<A, B, T>(lines, w, Lz, twz);
+      fft2::fwd_step1<A, B, T>(lines, Wz, Lz);
     });
   } else {
     fft_lines<-1, T>(lines, w, nullptr, ld, 1, pz, twz);
@@ -275,33 +277,35 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       __builtin_amdgcn_wave_barrier();
     };
+    const fft2::Walk Wr = fft2::walk(r1 - r0, lane, 64), Wc = fft2::walk(c1 - c0, lane, 64);
     fft2::dispatch_plane(n2, [&]<int A, int B>() {
-      fft2::inv_step1<A, B, T>(pl, r1 - r0, Lyw, ty, lane, 64);
+      fft2::inv_step1<A, B, T>(pl, Wr, Lyw, ty);
       wave_sync();
-      fft2::inv_step2<A, B, T>(pl, r1 - r0, Lyw, lane, 64);
+      fft2::inv_step2<A, B, T>(pl, Wr, Lyw);
     });
     __syncthreads();
     fft2::dispatch_plane(n1, [&]<int A, int B>() {
-      fft2::inv_step1<A, B, T>(pl + c0, c1 - c0, Lx, tx, lane, 64);
+      fft2::inv_step1<A, B, T>(pl + c0, Wc, Lx, tx);
       wave_sync();
-      fft2::inv2_mul_fwd2<A, B, T>(pl + c0, c1 - c0, Lx, tx, v + c0, 1, n2, lane, 64);
+      fft2::inv2_mul_fwd2<A, B, T>(pl + c0, Wc, Lx, tx, v + c0, 1, n2);
       wave_sync();
-      fft2::fwd_step1<A, B, T>(pl + c0, c1 - c0, Lx, tx, lane, 64);
+      fft2::fwd_step1<A, B, T>(pl + c0, Wc, Lx);
     });
     __syncthreads();
     fft2::dispatch_plane(n2, [&]<int A, int B>() {
-      fft2::fwd_step2<A, B, T>(pl, r1 - r0, Lyw, ty, lane, 64);
+      fft2::fwd_step2<A, B, T>(pl, Wr, Lyw, ty);
       wave_sync();
-      fft2::fwd_step1<A, B, T>(pl, r1 - r0, Lyw, ty, lane, 64);
+      fft2::fwd_step1<A, B, T>(pl, Wr, Lyw);
     });
     __syncthreads();
   } else {
   // inverse along a2
+  const fft2::Walk Wr = fft2::walk(nrows), Wc = fft2::walk(n2);
   if constexpr (kTab) {
     fft2::dispatch_plane(n2, [&]<int A, int B>() {
-      fft2::inv_step1<A, B, T>(pl, nrows, Ly, ty);
+      fft2::inv_step1<A, B, T>(pl, Wr, Ly, ty);
       __syncthreads();
-      fft2::inv_step2<A, B, T>(pl, nrows, Ly);
+      fft2::inv_step2<A, B, T>(pl, Wr, Ly);
     });
   } else {
     fft_lines<+1, T>(pl, nrows, rows, ld, 1, py, twy);
@@ -310,11 +314,11 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   // inverse along a1, x V, forward along a1
   if constexpr (kTab) {
     fft2::dispatch_plane(n1, [&]<int A, int B>() {
-      fft2::inv_step1<A, B, T>(pl, n2, Lx, tx);
+      fft2::inv_step1<A, B, T>(pl, Wc, Lx, tx);
       __syncthreads();
-      fft2::inv2_mul_fwd2<A, B, T>(pl, n2, Lx, tx, v, 1, n2);
+      fft2::inv2_mul_fwd2<A, B, T>(pl, Wc, Lx, tx, v, 1, n2);
       __syncthreads();
-      fft2::fwd_step1<A, B, T>(pl, n2, Lx, tx);
+      fft2::fwd_step1<A, B, T>(pl, Wc, Lx);
     });
   } else {
     fft_lines<+1, T>(pl, n2, nullptr, 1, ld, px, twx);
@@ -331,9 +335,9 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   // forward along a2
   if constexpr (kTab) {
     fft2::dispatch_plane(n2, [&]<int A, int B>() {
-      fft2::fwd_step2<A, B, T>(pl, nrows, Ly, ty);
+      fft2::fwd_step2<A, B, T>(pl, Wr, Ly, ty);
       __syncthreads();
-      fft2::fwd_step1<A, B, T>(pl, nrows, Ly, ty);
+      fft2::fwd_step1<A, B, T>(pl, Wr, Ly);
     });
   } else {
     fft_lines<-1, T>(pl, nrows, rows, ld, 1, py, twy);
@@ -639,9 +643,9 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
                      : small ? (wlines ? k_plane<T, true, true, true> : k_plane<T, true, true>)
                              : (wlines ? k_plane<T, true, false, true> : k_plane<T, true>);
   const int pthr = small ? kSmallPlaneThreads : kPlaneThreads<T>;
-  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(pthr), smp, st, t1, s.ncol, s.d_col_info.as<int4>(),
-                     s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(), Tw<T>(pot, 0),
-                     Tw<T>(pot, 1), Vtab<T>(pot), skip);
+  DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(pthr), smp, st, t1, s.ncol,
+             s.d_col_info.as<int4>(), s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(),
+             Tw<T>(pot, 0), Tw<T>(pot, 1), Vtab<T>(pot), skip);
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_fwd.f64" : "k_zfft_fwd.f32"), kzfwd, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
                      s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2),
