@@ -317,11 +317,29 @@ def free_energy(eps, f, v_in, v_ext, rho, vh, exc_density, omega, kT) -> float:
     return e_band - dc + e_h + e_xc - kT * entropy(f)
 
 
+def lowest_states(system, v, n: int, model: str = "dks"):
+    """The n lowest eigenpairs of the operator with local potential v: the
+    positive band of the DKS operator (model "dks"), or the two-component
+    Kohn-Sham operator with spin-orbit coupling (model "ksso", Table 1),
+    whose spinors are returned with zero small components."""
+    op = _operator_with(system, v)
+    if model == "dks":
+        eps, vec = lobpcgf.lowest_positive(op.dense(), n, system.c)
+        return op, eps, vec.T.reshape(n, 4, op.N)
+    w, vec = np.linalg.eigh(op.pauli_dense())
+    X = np.zeros((n, 4, op.N), dtype=np.complex128)
+    X[:, :2] = vec[:, :n].T.reshape(n, 2, op.N)
+    return op, w[:n], X
+
+
 def scf(system, n: int, n_el: float, temperature: float = 5000.0, tol: float = 1e-8,
-        max_iter: int = 60, depth: int = 6, alpha: float = 0.5, q0: float = 0.8) -> ScfResult:
+        max_iter: int = 60, depth: int = 6, alpha: float = 0.5, q0: float = 0.8,
+        model: str = "dks") -> ScfResult:
     """The SCF loop with exact eigenpairs of each H[V_in] (the dense definition
-    of Algorithm 1's answer), the n lowest positive-band states occupied by
-    n_el electrons at `temperature` (K)."""
+    of Algorithm 1's answer), the n lowest states (of the positive band for
+    DKS) occupied by n_el electrons at `temperature` (K).  The sigma.B_xc term
+    of Eq. (DKS) is left out of H: the densities here are Kramers-paired and
+    carry no spin density (B_xc = 0), which the tests check."""
     v_ext = np.asarray(system.v_loc, dtype=np.float64)
     omega = cell_volume(system.lattice)
     kT = K_BOLTZMANN * temperature
@@ -329,9 +347,7 @@ def scf(system, n: int, n_el: float, temperature: float = 5000.0, tol: float = 1
     v_in = v_ext.copy()
     res: List[float] = []
     for it in range(max_iter):
-        op = _operator_with(system, v_in)
-        eps, vec = lobpcgf.lowest_positive(op.dense(), n, system.c)
-        X = vec.T.reshape(n, 4, op.N)
+        op, eps, X = lowest_states(system, v_in, n, model)
         f, mu = fermi(eps, n_el, kT)
         rho, m = density(op, X, f)
         vh = hartree(rho, system.lattice)

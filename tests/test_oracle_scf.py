@@ -203,6 +203,23 @@ def test_scf_of_the_uniform_gas_is_known_exactly():
     assert np.allclose(out.eigvals, lev + v0 + vxc0, atol=1e-9)
 
 
+def test_scf_of_the_uniform_gas_ksso():
+    """The same gas with the two-component operator (model "ksso"): the
+    self-consistent eigenvalues are |q|^2 / 2 + V0 + v_xc(rho0), each twice."""
+    s = sysgen.tiny_dimer(0, ecut=2.0, grid=(12, 12, 12), n_bands=14, with_nonlocal=False)
+    v0 = 0.2
+    s = dataclasses.replace(s, v_loc=np.full(s.grid, v0))
+    n, n_el = 14, 9.0
+    out = scf.scf(s, n, n_el, tol=1e-11, max_iter=10, model="ksso")
+    assert out.converged, out.residuals
+    rho0 = n_el / scf.cell_volume(s.lattice)
+    vxc0 = scf.lda_xc(np.full((1, 1, 1), rho0))[0][0, 0, 0]
+    q = dks.planewave_basis(s.lattice, s.kpts[0], s.ecut)[1]
+    lev = np.sort(np.repeat(0.5 * np.einsum("ij,ij->i", q, q), 2))[:n]
+    assert np.allclose(out.eigvals, lev + v0 + vxc0, atol=1e-10)
+    assert np.abs(out.m).max() < 1e-9 * rho0
+
+
 def test_scf_dimer_fixed_point_is_independent_of_the_mixing():
     """The tiny dimer's SCF reaches the same self-consistent potential and
     eigenvalues with two different mixing settings, and that potential
