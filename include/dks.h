@@ -313,6 +313,103 @@ dks_status dks_set_tuning(dks_basis *b, int sys, int tile_z, int plane_form, int
 void dks_profile_enable(int on);
 dks_status dks_profile_report(char *buf, size_t len);
 
+/* ---- the self-consistent field loop (Sec. 2.1: Eq. density, V_hxc; Sec. 4) ----
+ * Real-space fields are FP64 device arrays on the FFT grid of the description
+ * of `sys`, natural order (index j3 fastest), ng = N1 N2 N3 values each. */
+
+/* Eq. (density): rho(r) = sum_i occ[i] psi_i^+ psi_i and the spin density
+ * m(r) = sum_i occ[i] psi_i^+ diag(sigma, -sigma) psi_i of the nb FP64 bands X
+ * of system `sys` ([nb][4][N] complex128 for DKS_MODEL_DKS; [nb][2][N] for
+ * DKS_MODEL_KSSO, where m = sum occ phi^+ sigma phi), with
+ * psi(r) = Omega^-1/2 sum_G c_G exp(i (k+G).r): rho in electrons / bohr^3
+ * integrates to sum occ over the cell.  rho: ng values; mag: 3 ng values
+ * (m_x | m_y | m_z) or NULL.  occ: host, nb values >= 0 (bands with 0 are
+ * skipped).  Allocates real-space scratch of up to 512 MB on first use (kept
+ * by the basis); calls on one basis must not overlap.  Asynchronous on
+ * `stream`. */
+dks_status dks_density(dks_basis *b, int sys, int model, const void *X, int nb, const double *occ,
+                       double *rho, double *mag, void *stream);
+
+/* The Hartree part of V_hxc (Sec. 2.1) of a periodic density:
+ * V_H(G) = 4 pi rho(G) / |G|^2 for G != 0, 0 at G = 0 (neutralising
+ * background), rho(G) = N_g^-1 sum_j rho_j exp(-2 pi i G.r_j); the frequency of
+ * FFT index m along an axis of N points is m for m < N/2, else m - N; vh is the
+ * real part of the inverse transform.  rho and vh: ng values (may alias). */
+dks_status dks_hartree(dks_basis *b, int sys, const double *rho, double *vh, void *stream);
+
+/* The Kerker preconditioner of Sec. 4 applied to a potential residual:
+ * out(G) = G^2 / (G^2 + q0^2) in(G), the G = 0 part passed unchanged.  q0 > 0
+ * (bohr^-1).  in and out: ng values (may alias). */
+dks_status dks_kerker(dks_basis *b, int sys, const double *in, double *out, double q0, void *stream);
+
+/* The exchange-correlation part of V_hxc in the local spin density
+ * approximation of Sec. 2.1: Slater exchange and the Perdew-Zunger
+ * parametrisation of the Ceperley-Alder correlation, spin-interpolated in the
+ * local polarisation zeta = |m| / rho.  vxc = dE_xc/drho (ng), bxc = dE_xc/dm
+ * (3 ng, along m, or NULL), exc = rho eps_xc (ng, or NULL).  mag NULL means
+ * m = 0.  Densities below 1e-14 bohr^-3 give zeros. */
+dks_status dks_lda_xc(dks_basis *b, int sys, const double *rho, const double *mag, double *vxc,
+                      double *bxc, double *exc, void *stream);
+
+/* Read or replace the local potential V_loc(r) of the description of `sys`
+ * (ng values, natural order).  Replacing it changes the operator of every
+ * k-point of that description (H, the filter constants' bounds) for all later
+ * calls; it synchronises `stream` (the bounds are read on the host) and fails
+ * with DKS_EINVAL on a non-finite value. */
+dks_status dks_get_local_potential(const dks_basis *b, int sys, double *v, void *stream);
+dks_status dks_set_local_potential(dks_basis *b, int sys, const double *v, void *stream);
+
+typedef struct {
+  double n_electrons;   /* electrons (one per spinor band), 0 < n_electrons < wanted bands */
+  double temperature;   /* electronic temperature (K) of the Fermi-Dirac occupations.  Default 5000 */
+  int max_scf;          /* SCF steps.  Default 60 */
+  double tol;           /* stop when ||V_out - V_in|| / ||V_in|| < tol and the last solve
+                           converged (Sec. 4.4's measure).  Default 1e-8 */
+  int eig_iters;        /* eigensolver iterations per SCF step (Table 6: 3).  Default 3 */
+  int n_init_first;     /* filter applications on the start block, first step.  Default 3 */
+  int n_init_next;      /* the same on later steps (Sec. 3.2).  Default 1 */
+  int anderson_depth;   /* stored input/residual pairs beyond the current one (<= 7).  Default 6 */
+  double alpha;         /* step on the preconditioned residual.  Default 0.5 */
+  double kerker_q0;     /* Kerker wavevector (bohr^-1).  Default 0.8 */
+  double max_bxc;       /* largest |B_xc| (Ha) accepted at the fixed point: the operator applies
+                           V_xc but not the sigma.B_xc term, so a spin-polarised
+                           self-consistent density fails with DKS_EINVAL (iterates on the way
+                           may carry one).  Default 1e-6 */
+} dks_scf_opts;
+
+typedef struct {
+  int iterations;       /* SCF steps taken */
+  int eig_iterations;   /* eigensolver iterations over all steps */
+  int converged;        /* 1 if tol was met */
+  int eig_converged;    /* the last solve's convergence flag */
+  double residual;      /* last ||V_out - V_in|| / ||V_in|| */
+  double fermi;         /* Fermi level (Ha, shifted by -c^2 like the eigenvalues) */
+  double free_energy;   /* sum f eps - int (V_in - V_ext) rho + E_H + E_xc - T S (Ha) */
+  double e_hartree, e_xc;
+  double max_mag;       /* largest |m_x|, |m_y| or |m_z| (bohr^-3) */
+  double max_bxc;       /* largest component of B_xc (Ha) */
+} dks_scf_info;
+
+void dks_scf_default_opts(dks_scf_opts *o);
+
+/* The SCF loop of Sec. 4 on system `sys` (a description with one k-point):
+ * each step takes eig_iters iterations of the solver configured by `eopts`
+ * (LOBPCG-F by default; n_iter and n_init are set per step, kinetic balance is
+ * applied on the first step only) from the block X ([n][4][N] or [n][2][N],
+ * in: start block, out: last eigenvectors), occupies the n - n_buffer wanted
+ * bands with Fermi-Dirac occupations holding n_electrons, builds rho and m
+ * (dks_density), V_out = V_ext + V_H + V_xc (V_ext: the potential the basis
+ * held when the call began), and stops when the measure falls below tol, else
+ * mixes: Anderson's combination of the stored (V_in, residual) pairs followed
+ * by a Kerker-preconditioned step of size alpha.  On return the basis holds the
+ * last V_in, lambda (host, n) the eigenvalues of the last solve, occ (host, n,
+ * or NULL) the occupations (0 for buffer columns).  DKS_WNOTCONV (> 0) when
+ * max_scf steps pass without convergence; eigensolver errors are returned as
+ * they are.  Synchronous. */
+dks_status dks_scf(dks_basis *b, int sys, int n, void *X, double *lambda, double *occ,
+                   const dks_scf_opts *sopts, const dks_solve_opts *eopts, dks_scf_info *info,
+                   void *stream);
+
 /* Release everything owned by the basis (after synchronising its device). */
 void dks_free_basis(dks_basis *b);
 

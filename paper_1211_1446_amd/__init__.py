@@ -12,4 +12,6 @@ from ._lib import (  # noqa: F401
     apply_filter, apply_H, apply_H_ksso, apply_H_noalloc, autotune, basis_info, get_tuning, set_tuning, default_opts, filter_constants, free_basis, init_basis,
     library_path, lobpcgf_solve, lobpcgf_solve_batch, num_systems, profile_enable,
     profile_report,
+    ScfInfo, ScfOpts, density, get_local_potential, hartree, kerker, lda_xc, scf,
+    scf_default_opts, set_local_potential,
 )

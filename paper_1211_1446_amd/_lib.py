@@ -66,6 +66,23 @@ class SolveInfo(ct.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ScfOpts(ct.Structure):
+    _fields_ = [("n_electrons", ct.c_double), ("temperature", ct.c_double), ("max_scf", ct.c_int),
+                ("tol", ct.c_double), ("eig_iters", ct.c_int), ("n_init_first", ct.c_int),
+                ("n_init_next", ct.c_int), ("anderson_depth", ct.c_int), ("alpha", ct.c_double),
+                ("kerker_q0", ct.c_double), ("max_bxc", ct.c_double)]
+
+
+class ScfInfo(ct.Structure):
+    _fields_ = [("iterations", ct.c_int), ("eig_iterations", ct.c_int), ("converged", ct.c_int),
+                ("eig_converged", ct.c_int), ("residual", ct.c_double), ("fermi", ct.c_double),
+                ("free_energy", ct.c_double), ("e_hartree", ct.c_double), ("e_xc", ct.c_double),
+                ("max_mag", ct.c_double), ("max_bxc", ct.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 def library_path() -> str:
     return _LIBPATH
 
@@ -93,6 +110,16 @@ def _load():
     lib.dks_lobpcgf_solve_batch.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(vp),
                                             ct.POINTER(ct.POINTER(d)), ct.POINTER(ct.POINTER(d)),
                                             ct.POINTER(SolveOpts), ct.POINTER(SolveInfo), vp]
+    lib.dks_density.argtypes = [vp, i, i, vp, i, ct.POINTER(d), vp, vp, vp]
+    lib.dks_hartree.argtypes = [vp, i, vp, vp, vp]
+    lib.dks_kerker.argtypes = [vp, i, vp, vp, d, vp]
+    lib.dks_lda_xc.argtypes = [vp, i, vp, vp, vp, vp, vp, vp]
+    lib.dks_get_local_potential.argtypes = [vp, i, vp, vp]
+    lib.dks_set_local_potential.argtypes = [vp, i, vp, vp]
+    lib.dks_scf_default_opts.argtypes = [ct.POINTER(ScfOpts)]
+    lib.dks_scf_default_opts.restype = None
+    lib.dks_scf.argtypes = [vp, i, i, vp, ct.POINTER(d), ct.POINTER(d), ct.POINTER(ScfOpts),
+                            ct.POINTER(SolveOpts), ct.POINTER(ScfInfo), vp]
     lib.dks_free_basis.argtypes = [vp]
     lib.dks_free_basis.restype = None
     lib.dks_last_error.restype = ct.c_char_p
@@ -386,3 +413,114 @@ def lobpcgf_solve_batch(b: Basis, systems: Sequence[int], ns: Sequence[int], Xs:
     o.item_buffer = ct.POINTER(ct.c_int)()
     _check(rc, allow_warning=allow_notconv)
     return lams, ress, [infos[i].as_dict() for i in range(nsys)], rc
+
+
+# ---- the self-consistent field loop ---------------------------------------
+
+def _grid_shape(b: Basis, sys: int):
+    _, grid, _ = basis_info(b, sys, miller=False)
+    return tuple(int(g) for g in grid)
+
+
+def _field(t, count, name):
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() < count:
+        raise ValueError(f"{name} must be a contiguous float64 device tensor of >= {count} values")
+    return ct.c_void_p(t.data_ptr())
+
+
+def density(b: Basis, sys: int, X, occ, model: int = MODEL_DKS, stream=None, with_mag: bool = True):
+    """rho (N1, N2, N3) and m (3, N1, N2, N3) device tensors of the bands X with
+    occupations occ (dks_density)."""
+    import torch
+    if X.dtype != torch.complex128:
+        raise TypeError("X must be complex128")
+    N, _, _ = basis_info(b, sys, miller=False)
+    occ = np.ascontiguousarray(occ, dtype=np.float64)
+    nb = occ.size
+    _check_block(X, nb, N, 2 if model == MODEL_KSSO else 4)
+    g = _grid_shape(b, sys)
+    rho = torch.empty(g, dtype=torch.float64, device=X.device)
+    mag = torch.empty((3,) + g, dtype=torch.float64, device=X.device) if with_mag else None
+    _check(_lib.dks_density(b.handle, sys, model, ct.c_void_p(X.data_ptr()), nb, _dptr(occ),
+                            ct.c_void_p(rho.data_ptr()),
+                            ct.c_void_p(mag.data_ptr()) if mag is not None else None, _stream(stream)))
+    return rho, mag
+
+
+def hartree(b: Basis, sys: int, rho, out=None, stream=None):
+    """V_H of the density rho (dks_hartree)."""
+    import torch
+    g = _grid_shape(b, sys)
+    ng = int(np.prod(g))
+    out = torch.empty(g, dtype=torch.float64, device=rho.device) if out is None else out
+    _check(_lib.dks_hartree(b.handle, sys, _field(rho, ng, "rho"), _field(out, ng, "out"), _stream(stream)))
+    return out
+
+
+def kerker(b: Basis, sys: int, x, q0: float, out=None, stream=None):
+    """The Kerker preconditioner G^2 / (G^2 + q0^2) of a grid field (dks_kerker)."""
+    import torch
+    g = _grid_shape(b, sys)
+    ng = int(np.prod(g))
+    out = torch.empty(g, dtype=torch.float64, device=x.device) if out is None else out
+    _check(_lib.dks_kerker(b.handle, sys, _field(x, ng, "x"), _field(out, ng, "out"), float(q0),
+                           _stream(stream)))
+    return out
+
+
+def lda_xc(b: Basis, sys: int, rho, mag=None, stream=None):
+    """(v_xc, B_xc, rho eps_xc) of the local spin density approximation (dks_lda_xc)."""
+    import torch
+    g = _grid_shape(b, sys)
+    ng = int(np.prod(g))
+    vxc = torch.empty(g, dtype=torch.float64, device=rho.device)
+    bxc = torch.empty((3,) + g, dtype=torch.float64, device=rho.device)
+    exc = torch.empty(g, dtype=torch.float64, device=rho.device)
+    _check(_lib.dks_lda_xc(b.handle, sys, _field(rho, ng, "rho"),
+                           _field(mag, 3 * ng, "mag") if mag is not None else None,
+                           ct.c_void_p(vxc.data_ptr()), ct.c_void_p(bxc.data_ptr()),
+                           ct.c_void_p(exc.data_ptr()), _stream(stream)))
+    return vxc, bxc, exc
+
+
+def get_local_potential(b: Basis, sys: int, stream=None):
+    import torch
+    g = _grid_shape(b, sys)
+    v = torch.empty(g, dtype=torch.float64, device="cuda")
+    _check(_lib.dks_get_local_potential(b.handle, sys, ct.c_void_p(v.data_ptr()), _stream(stream)))
+    return v
+
+
+def set_local_potential(b: Basis, sys: int, v, stream=None) -> None:
+    g = _grid_shape(b, sys)
+    _check(_lib.dks_set_local_potential(b.handle, sys, _field(v, int(np.prod(g)), "v"), _stream(stream)))
+
+
+def scf_default_opts(**kw) -> ScfOpts:
+    o = ScfOpts()
+    _lib.dks_scf_default_opts(ct.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def scf(b: Basis, sys: int, n: int, X, sopts: ScfOpts, eopts: Optional[SolveOpts] = None,
+        stream=None, allow_notconv: bool = True):
+    """The SCF loop (dks_scf) on the complex128 block X (in: start block, out:
+    last eigenvectors).  Returns (eigenvalues, occupations, info dict, status)."""
+    import torch
+    if X.dtype != torch.complex128:
+        raise TypeError("X must be complex128")
+    N, _, _ = basis_info(b, sys, miller=False)
+    eo = eopts if eopts is not None else default_opts()
+    _check_block(X, n, N, 2 if eo.model == MODEL_KSSO else 4)
+    lam = np.zeros(n)
+    occ = np.zeros(n)
+    info = ScfInfo()
+    rc = _lib.dks_scf(b.handle, sys, n, ct.c_void_p(X.data_ptr()), _dptr(lam), _dptr(occ),
+                      ct.byref(sopts), ct.byref(eo), ct.byref(info), _stream(stream))
+    _check(rc, allow_warning=allow_notconv)
+    return lam, occ, info.as_dict(), rc

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["basis.cpp", "profile.cpp", "operator.hip", "blas.hip", "rr.hip", "solver.hip"]
+SRC = ["basis.cpp", "profile.cpp", "operator.hip", "blas.hip", "rr.hip", "solver.hip", "scf.hip"]
 LIB = os.path.join(HERE, "libdks.so")
 
 

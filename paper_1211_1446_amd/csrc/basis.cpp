@@ -142,7 +142,10 @@ void init_kernel_attributes();
 
 using namespace dks;
 
+void free_scf_work(dks_basis *b);
+
 dks_basis::~dks_basis() {
+  free_scf_work(this);
   for (auto *s : sys) delete s;
   for (auto *p : pot) delete p;
 }
@@ -209,12 +212,16 @@ dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, d
       {
         // plane layout [p3][p1][p2] in the real-space order the transforms
         // leave behind: position p of axis d holds natural index nat[d][p]
+        // (the plane kernels take the two-step transforms only when both plane
+        // axes have a compiled split, else the natural-order radix transforms)
         std::vector<int> nat[3];
+        int A0 = 1, B0 = 1;
+        const bool plane_fast = fft2::split_plane(D.grid[0], &A0, &B0) && fft2::split_plane(D.grid[1], &A0, &B0);
         for (int d = 0; d < 3; ++d) {
           const int n = D.grid[d];
           nat[d].resize(n);
           int A = 1, Bq = n;
-          bool fast = (d == 2) ? fft2::split_z(n, &A, &Bq) : fft2::split_plane(n, &A, &Bq);
+          bool fast = (d == 2) ? fft2::split_z(n, &A, &Bq) : (plane_fast && fft2::split_plane(n, &A, &Bq));
           for (int p = 0; p < n; ++p) nat[d][p] = fast ? fft2::scrambled_to_natural(p, A, Bq) : p;
         }
         std::vector<double> v64(ng);
@@ -240,6 +247,7 @@ dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, d
         P->vmean = vs / (double)ng;
         upload(P->d_v64, v64.data(), sizeof(double) * ng);
         upload(P->d_v32, v32.data(), sizeof(float) * ng);
+        for (int d = 0; d < 3; ++d) upload(P->d_nat[d], nat[d].data(), sizeof(int) * nat[d].size());
         for (int d = 0; d < 3; ++d) {
           const int n = D.grid[d];
           std::vector<double2> t64(n);

@@ -193,6 +193,7 @@ struct Potential {
   double vmin, vmax, vmean;
   DevBuf d_v64, d_v32;            // plane layout [N3][N1][N2]
   DevBuf d_tw64[3], d_tw32[3];    // exp(-2 pi i t / n_d), t < n_d
+  DevBuf d_nat[3];                // natural index of real-space position p along axis d
 };
 
 }  // namespace dks
@@ -214,6 +215,8 @@ struct dks_basis {
   dks::DevBuf ftmp64, ftmp32;
   // solver workspace (created on first solve)
   void *solver = nullptr;
+  // self-consistent field workspace (created on first use)
+  void *scf = nullptr;
   ~dks_basis();
 };
 
@@ -313,6 +316,15 @@ void convert(const cplx<Ts> *src, cplx<Td> *dst, int64_t count, hipStream_t st);
 
 template <typename T>
 void scale_rows(cplx<T> *X, const double *s, int n, int64_t K, hipStream_t st);
+
+// Every band-component of the ncols FP64 rows X ([ncols][N]) on the real-space
+// grid: R[cc][p3][p1][p2] (the real-space order of the potential table), no
+// 1/sqrt(volume) factor.  t1: real_space_t1_bytes of scratch.
+size_t real_space_t1_bytes(const dks_basis *b, int sys, int ncols);
+void real_space_planes(dks_basis *b, int sys, const double2 *X, int ncols, void *t1, double2 *R,
+                       hipStream_t st);
+// LDS limits of the self-consistent field kernels (once, with the others)
+void init_scf_kernel_attributes();
 
 // small component from the large one by kinetic balance, in place on [n][4][N]
 void kinetic_balance(dks_basis *b, int sys, double2 *X, int n, hipStream_t st);

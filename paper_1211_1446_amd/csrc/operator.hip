@@ -525,6 +525,93 @@ template <typename T> static const typename CT<T>::c *Tw(const Potential &p, int
 template <> const double2 *Tw<double>(const Potential &p, int d) { return p.d_tw64[d].as<double2>(); }
 template <> const float2 *Tw<float>(const Potential &p, int d) { return p.d_tw32[d].as<float2>(); }
 
+// ---------------------------------------------------------------------------
+// spinor components on the real-space grid (the densities of Eq. density)
+// ---------------------------------------------------------------------------
+// One z plane of one band-component: the column values the z transform left
+// in T1 are placed in the plane, transformed along a2 (sphere rows) and a1
+// (every column) to real space, and the whole plane is written to
+// R[cc][z][p1][p2] in the transforms' real-space order (that of the potential
+// table).  FP64, the thread count of the plane kernel's form 0.
+template <bool kTab>
+__global__ void __launch_bounds__(kPlaneThreads<double>, kPlaneWaves<double>) k_plane_real(
+    const double2 *__restrict__ T1, int ncol, const int4 *__restrict__ col_info,
+    const int *__restrict__ rows, int nrows, const FftPlan *__restrict__ pxy,
+    const double2 *__restrict__ twx, const double2 *__restrict__ twy, double2 *__restrict__ R) {
+  using C = double2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *pl = reinterpret_cast<C *>(smem_raw);
+  const FftPlan &px = pxy[0], &py = pxy[1];
+  const int n1 = px.n, n2 = py.n;
+  const int ld = n2 + 1;
+  const int z = blockIdx.x, cc = blockIdx.y, n3 = gridDim.x;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  int *rows_s = reinterpret_cast<int *>(pl + n1 * ld);
+  for (int e = tid; e < n1 * ld; e += nthr) pl[e] = C{0, 0};
+  for (int e = tid; e < nrows; e += nthr) rows_s[e] = rows[e];
+  __syncthreads();
+  const C *t = T1 + ((size_t)cc * n3 + z) * ncol;
+  for (int c = tid; c < ncol; c += nthr) {
+    const int4 ci = col_info[c];
+    pl[ci.x * ld + ci.y] = t[c];
+  }
+  __syncthreads();
+  const fft2::Lines Ly{rows_s, ld, 1};
+  const fft2::Lines Lx{nullptr, 1, ld};
+  if constexpr (kTab) {
+    const fft2::Walk Wr = fft2::walk(nrows), Wc = fft2::walk(n2);
+    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+      fft2::inv_step1<A, B, double>(pl, Wr, Ly, twy);
+      __syncthreads();
+      fft2::inv_step2<A, B, double>(pl, Wr, Ly);
+    });
+    __syncthreads();
+    fft2::dispatch_plane(n1, [&]<int A, int B>() {
+      fft2::inv_step1<A, B, double>(pl, Wc, Lx, twx);
+      __syncthreads();
+      fft2::inv_step2<A, B, double>(pl, Wc, Lx);
+    });
+  } else {
+    fft_lines<+1, double>(pl, nrows, rows_s, ld, 1, py, twy);
+    __syncthreads();
+    fft_lines<+1, double>(pl, n2, nullptr, 1, ld, px, twx);
+  }
+  __syncthreads();
+  C *r = R + ((size_t)cc * n3 + z) * n1 * n2;
+  for (int e = tid; e < n1 * n2; e += nthr) {
+    const int p1 = e / n2, p2 = e - (e / n2) * n2;
+    r[e] = pl[p1 * ld + p2];
+  }
+}
+
+size_t real_space_t1_bytes(const dks_basis *b, int sysi, int ncols) {
+  const System &s = *b->sys[sysi];
+  return sizeof(double2) * (size_t)ncols * s.grid[2] * s.ncol;
+}
+
+void real_space_planes(dks_basis *b, int sysi, const double2 *X, int ncols, void *t1v,
+                       double2 *R, hipStream_t st) {
+  const System &s = *b->sys[sysi];
+  const Potential &pot = *b->pot[s.vsrc];
+  const int N = s.N, n3 = s.grid[2];
+  double2 *t1 = static_cast<double2 *>(t1v);
+  const int tile = s.tile_z;
+  dim3 gz((s.ncol + tile - 1) / tile, ncols);
+  const size_t smz = sizeof(double2) * (size_t)tile * (n3 + 1);
+  auto kzinv = fft2::z_has(n3) ? k_zfft_inv<double, true> : k_zfft_inv<double, false>;
+  DKS_LAUNCH("k_zfft_inv.f64", kzinv, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
+             s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<double>(pot, 2), t1,
+             (const int *)nullptr);
+  DKS_HIP(hipGetLastError());
+  const bool tab = fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]);
+  auto kp = tab ? k_plane_real<true> : k_plane_real<false>;
+  DKS_LAUNCH("k_plane_real", kp, dim3(n3, ncols), dim3(kPlaneThreads<double>),
+             plane_lds_bytes<double>(s.grid[0], s.grid[1]), st, t1, s.ncol,
+             s.d_col_info.as<int4>(), s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(),
+             Tw<double>(pot, 0), Tw<double>(pot, 1), R);
+  DKS_HIP(hipGetLastError());
+}
+
 void init_kernel_attributes() {
   static bool done = false;
   if (done) return;
@@ -549,6 +636,9 @@ void init_kernel_attributes() {
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_real<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_real<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  init_scf_kernel_attributes();
   done = true;
 }
 

@@ -190,6 +190,28 @@ def test_apply_h_edge_sizes(dev):
     b.close()
 
 
+@pytest.mark.parametrize("grid", [(16, 81, 16), (81, 16, 18)])
+def test_apply_h_plane_axis_without_two_step_split(dev, grid):
+    """A plane axis of 81 points has no compiled two-step split: both plane
+    axes then take the radix transforms in natural order, and the potential
+    table must follow that order (tiny dimer on the stretched grid)."""
+    dk = _dk()
+    s = sysgen.tiny_dimer(0, grid=grid)
+    op = dks.DKSOperator(s)
+    b = dk.init_basis([s])
+    N, _, mil = dk.basis_info(b, 0)
+    p = perm_to_oracle(mil, op.miller)
+    X = random_block(np.random.default_rng(9), 3, N)
+    Xd = torch.from_numpy(X).to(dev)
+    HXd = torch.empty_like(Xd)
+    print(f"[apply_H grid {grid}]", flush=True)
+    dk.apply_H(b, 0, Xd, HXd)
+    got = to_orc(HXd.cpu().numpy(), p)
+    ref = op.apply(to_orc(X, p))
+    b.close()
+    assert np.abs(got - ref).max() < 2e-13 * np.abs(ref).max()
+
+
 def test_apply_filter_matches_oracle(dev):
     dk = _dk()
     s = sysgen.tiny_dimer(3)
