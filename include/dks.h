@@ -368,13 +368,18 @@ typedef struct {
   int eig_iters;        /* eigensolver iterations per SCF step (Table 6: 3).  Default 3 */
   int n_init_first;     /* filter applications on the start block, first step.  Default 3 */
   int n_init_next;      /* the same on later steps (Sec. 3.2).  Default 1 */
-  int anderson_depth;   /* stored input/residual pairs beyond the current one (<= 7).  Default 6 */
+  int anderson_depth;   /* stored differences of successive inputs and residuals (<= 15).
+                           Default 6 */
   double alpha;         /* step on the preconditioned residual.  Default 0.5 */
   double kerker_q0;     /* Kerker wavevector (bohr^-1).  Default 0.8 */
   double max_bxc;       /* largest |B_xc| (Ha) accepted at the fixed point: the operator applies
                            V_xc but not the sigma.B_xc term, so a spin-polarised
                            self-consistent density fails with DKS_EINVAL (iterates on the way
                            may carry one).  Default 1e-6 */
+  double *history;      /* optional caller-owned host array of max_scf entries: the measure
+                           ||V_out - V_in|| / ||V_in|| of each step.  Default NULL */
+  double *eig_history;  /* optional caller-owned host array of max_scf entries: the largest
+                           wanted residual norm of each step's solve.  Default NULL */
 } dks_scf_opts;
 
 typedef struct {
@@ -399,9 +404,12 @@ void dks_scf_default_opts(dks_scf_opts *o);
  * in: start block, out: last eigenvectors), occupies the n - n_buffer wanted
  * bands with Fermi-Dirac occupations holding n_electrons, builds rho and m
  * (dks_density), V_out = V_ext + V_H + V_xc (V_ext: the potential the basis
- * held when the call began), and stops when the measure falls below tol, else
- * mixes: Anderson's combination of the stored (V_in, residual) pairs followed
- * by a Kerker-preconditioned step of size alpha.  On return the basis holds the
+ * held when the call began), and stops when the measure falls below tol with
+ * the solve converged, else mixes: Anderson's combination over the stored
+ * differences of successive (V_in, residual) pairs followed by a
+ * Kerker-preconditioned step of size alpha.  When the measure falls below tol
+ * before the solve has converged, the next step keeps V_in and runs the solver
+ * for up to eopts->n_iter iterations to its tolerance.  On return the basis holds the
  * last V_in, lambda (host, n) the eigenvalues of the last solve, occ (host, n,
  * or NULL) the occupations (0 for buffer columns).  DKS_WNOTCONV (> 0) when
  * max_scf steps pass without convergence; eigensolver errors are returned as

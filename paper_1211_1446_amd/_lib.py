@@ -70,7 +70,8 @@ class ScfOpts(ct.Structure):
     _fields_ = [("n_electrons", ct.c_double), ("temperature", ct.c_double), ("max_scf", ct.c_int),
                 ("tol", ct.c_double), ("eig_iters", ct.c_int), ("n_init_first", ct.c_int),
                 ("n_init_next", ct.c_int), ("anderson_depth", ct.c_int), ("alpha", ct.c_double),
-                ("kerker_q0", ct.c_double), ("max_bxc", ct.c_double)]
+                ("kerker_q0", ct.c_double), ("max_bxc", ct.c_double),
+                ("history", ct.POINTER(ct.c_double)), ("eig_history", ct.POINTER(ct.c_double))]
 
 
 class ScfInfo(ct.Structure):
@@ -508,9 +509,12 @@ def scf_default_opts(**kw) -> ScfOpts:
 
 
 def scf(b: Basis, sys: int, n: int, X, sopts: ScfOpts, eopts: Optional[SolveOpts] = None,
-        stream=None, allow_notconv: bool = True):
+        stream=None, allow_notconv: bool = True, history: Optional[np.ndarray] = None,
+        eig_history: Optional[np.ndarray] = None):
     """The SCF loop (dks_scf) on the complex128 block X (in: start block, out:
-    last eigenvectors).  Returns (eigenvalues, occupations, info dict, status)."""
+    last eigenvectors).  ``history``: optional float64 array of >= max_scf
+    entries receiving each step's ||V_out - V_in|| / ||V_in||.  Returns
+    (eigenvalues, occupations, info dict, status)."""
     import torch
     if X.dtype != torch.complex128:
         raise TypeError("X must be complex128")
@@ -520,6 +524,15 @@ def scf(b: Basis, sys: int, n: int, X, sopts: ScfOpts, eopts: Optional[SolveOpts
     lam = np.zeros(n)
     occ = np.zeros(n)
     info = ScfInfo()
+    if history is not None:
+        if history.dtype != np.float64 or history.size < sopts.max_scf or not history.flags.c_contiguous:
+            raise ValueError(f"history must be a contiguous float64 array of >= {sopts.max_scf} entries")
+        sopts.history = _dptr(history)
+    if eig_history is not None:
+        if (eig_history.dtype != np.float64 or eig_history.size < sopts.max_scf
+                or not eig_history.flags.c_contiguous):
+            raise ValueError(f"eig_history must be a contiguous float64 array of >= {sopts.max_scf} entries")
+        sopts.eig_history = _dptr(eig_history)
     rc = _lib.dks_scf(b.handle, sys, n, ct.c_void_p(X.data_ptr()), _dptr(lam), _dptr(occ),
                       ct.byref(sopts), ct.byref(eo), ct.byref(info), _stream(stream))
     _check(rc, allow_warning=allow_notconv)

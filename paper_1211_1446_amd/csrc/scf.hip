@@ -370,6 +370,30 @@ __global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ x, co
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
+// part[j * gridDim.x + block] = the block's share of x_j . y_j for k pairs
+constexpr int kMaxDots = 16;
+struct DotPairs {
+  const double *x[kMaxDots];
+  const double *y[kMaxDots];
+  int k;
+};
+__global__ void __launch_bounds__(256) k_multidot(DotPairs d, size_t n, double *__restrict__ part) {
+  __shared__ double s[256];
+  for (int j = 0; j < d.k; ++j) {
+    double a = 0;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+      a += d.x[j][e] * d.y[j][e];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)j * gridDim.x + blockIdx.x] = s[0];
+    __syncthreads();
+  }
+}
+
 // min, max and sum of x in one pass: part[3 b + {0, 1, 2}]
 __global__ void __launch_bounds__(256) k_minmaxsum(const double *__restrict__ x, size_t n,
                                                    double *__restrict__ part) {
@@ -420,8 +444,8 @@ __global__ void __launch_bounds__(256) k_lincomb(double *__restrict__ out, Terms
 // ---------------------------------------------------------------------------
 struct ScfWork {
   DevBuf t1, R, acc, gridw, part, occ_d;
-  DevBuf v_ext, v_in, v_out, vh, vxc, bxc, exc, rho, mag, tmp, xbar, rbar;
-  std::vector<DevBuf *> hx, hr;   // Anderson history (inputs, residuals)
+  DevBuf v_ext, v_in, v_out, vh, vxc, bxc, exc, rho, mag, tmp, xbar, rbar, x_prev, r_prev;
+  std::vector<DevBuf *> hx, hr;   // Anderson history: differences of successive inputs, residuals
   std::vector<double> part_h;
   ~ScfWork() {
     for (auto *p : hx) delete p;
@@ -478,6 +502,33 @@ static double reduce(ScfWork &w, const double *x, const double *y, size_t n, boo
   double a = 0;
   for (double v : w.part_h) a = mx ? std::max(a, v) : a + v;
   return a;
+}
+
+// x_j . y_j for the given pairs (any number; kMaxDots per launch), synchronising `st`
+static std::vector<double> dots(ScfWork &w, const std::vector<std::pair<const double *, const double *>> &pr,
+                                size_t n, hipStream_t st) {
+  std::vector<double> out(pr.size(), 0.0);
+  w.part.ensure(sizeof(double) * kRedBlocks * kMaxDots);
+  w.part_h.resize((size_t)kRedBlocks * kMaxDots);
+  for (size_t j0 = 0; j0 < pr.size(); j0 += kMaxDots) {
+    DotPairs d{};
+    d.k = (int)std::min<size_t>(kMaxDots, pr.size() - j0);
+    for (int j = 0; j < d.k; ++j) {
+      d.x[j] = pr[j0 + j].first;
+      d.y[j] = pr[j0 + j].second;
+    }
+    DKS_LAUNCH("k_multidot", k_multidot, dim3(kRedBlocks), dim3(256), 0, st, d, n, w.part.as<double>());
+    DKS_HIP(hipGetLastError());
+    DKS_HIP(hipMemcpyAsync(w.part_h.data(), w.part.p, sizeof(double) * kRedBlocks * d.k, hipMemcpyDeviceToHost,
+                           st));
+    DKS_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < d.k; ++j) {
+      double a = 0;
+      for (int q = 0; q < kRedBlocks; ++q) a += w.part_h[(size_t)j * kRedBlocks + q];
+      out[j0 + j] = a;
+    }
+  }
+  return out;
 }
 
 static void lincomb(double *out, const std::vector<const double *> &xs, const std::vector<double> &cs,
@@ -772,6 +823,8 @@ void dks_scf_default_opts(dks_scf_opts *o) {
   o->alpha = 0.5;
   o->kerker_q0 = 0.8;
   o->max_bxc = 1e-6;
+  o->history = nullptr;
+  o->eig_history = nullptr;
 }
 
 dks_status dks_scf(dks_basis *b, int sys, int n, void *X, double *lambda, double *occ,
@@ -791,7 +844,7 @@ dks_status dks_scf(dks_basis *b, int sys, int n, void *X, double *lambda, double
                 "n_electrons must lie strictly between 0 and the number of wanted bands");
     DKS_REQUIRE(so.temperature > 0 && so.max_scf >= 1 && so.tol > 0 && so.eig_iters >= 1 &&
                     so.n_init_first >= 0 && so.n_init_next >= 0 && so.anderson_depth >= 0 &&
-                    so.anderson_depth + 1 <= kMaxTerms / 2 && so.alpha > 0 && so.kerker_q0 > 0 &&
+                    so.anderson_depth + 1 <= kMaxTerms && so.alpha > 0 && so.kerker_q0 > 0 &&
                     so.max_bxc > 0,
                 DKS_EINVAL, "bad SCF options");
     DKS_REQUIRE(systems_sharing(b, sys) == 1, DKS_EINVAL,
@@ -803,16 +856,17 @@ dks_status dks_scf(dks_basis *b, int sys, int n, void *X, double *lambda, double
     const size_t ng = (size_t)s.grid[0] * s.grid[1] * s.grid[2];
     const size_t gb = sizeof(double) * ng;
     ScfWork &w = work_of(b);
-    for (DevBuf *d : {&w.v_ext, &w.v_in, &w.v_out, &w.vh, &w.vxc, &w.exc, &w.rho, &w.tmp, &w.xbar, &w.rbar})
+    for (DevBuf *d : {&w.v_ext, &w.v_in, &w.v_out, &w.vh, &w.vxc, &w.exc, &w.rho, &w.tmp, &w.xbar, &w.rbar,
+                      &w.x_prev, &w.r_prev})
       d->ensure(gb);
     w.mag.ensure(3 * gb);
     w.bxc.ensure(3 * gb);
     const int depth = so.anderson_depth;
-    while ((int)w.hx.size() < depth + 1) {
+    while ((int)w.hx.size() < depth) {
       w.hx.push_back(new DevBuf());
       w.hr.push_back(new DevBuf());
     }
-    for (int j = 0; j <= depth; ++j) {
+    for (int j = 0; j < depth; ++j) {
       w.hx[j]->ensure(gb);
       w.hr[j]->ensure(gb);
     }
@@ -822,16 +876,21 @@ dks_status dks_scf(dks_basis *b, int sys, int n, void *X, double *lambda, double
     const double kT = 3.166811563e-6 * so.temperature;
     const double dv = cell_volume(s) / (double)ng;
     std::vector<double> f(n, 0.0), res(n);
-    // Anderson history: slots in order of age, Gram matrix of the residuals
+    // Anderson history: the slots of the stored differences in order of age,
+    // their Gram matrix G[slot][slot'] = dR_slot . dR_slot'
     std::vector<int> order;
-    std::vector<double> G((size_t)(depth + 1) * (depth + 1), 0.0);
+    std::vector<double> G((size_t)std::max(depth, 1) * std::max(depth, 1), 0.0);
+    bool have_prev = false;
     dks_scf_info inf{};
     inf.residual = INFINITY;
     dks_status out = DKS_WNOTCONV;
+    // once the measure is below tol while the last solve has not converged,
+    // the next step keeps V_in and solves to the eigensolver's own tolerance
+    bool polish = false;
     for (int it = 0; it < so.max_scf; ++it) {
       // eigenpairs of H[V_in]: a few LOBPCG-F iterations from the last block
       dks_solve_opts o = eo;
-      o.n_iter = so.eig_iters;
+      o.n_iter = polish ? eo.n_iter : so.eig_iters;
       o.n_init = it == 0 ? so.n_init_first : so.n_init_next;
       o.kinetic_balance = it == 0 ? eo.kinetic_balance : 0;
       dks_solve_info si{};
@@ -855,6 +914,8 @@ dks_status dks_scf(dks_basis *b, int sys, int n, void *X, double *lambda, double
       const double rn = std::sqrt(reduce(w, r, r, ng, false, st));
       const double vn = std::sqrt(reduce(w, v_in, v_in, ng, false, st));
       inf.residual = rn / std::max(vn, 1e-300);
+      if (so.history) so.history[it] = inf.residual;
+      if (so.eig_history) so.eig_history[it] = si.max_resnorm;
       // energies: band energy - double counting + E_H + E_xc - T S
       double eband = 0, ent = 0;
       for (int i = 0; i < nwant; ++i) {
@@ -879,46 +940,52 @@ dks_status dks_scf(dks_basis *b, int sys, int n, void *X, double *lambda, double
         break;
       }
       if (it + 1 == so.max_scf) break;
-      // Anderson: store (V_in, r) in the oldest slot
-      int slot;
-      if ((int)order.size() < depth + 1) {
-        slot = (int)order.size();
-      } else {
-        slot = order.front();
-        order.erase(order.begin());
+      if (inf.residual < so.tol && !polish) {
+        polish = true;
+        continue;
       }
-      DKS_HIP(hipMemcpyAsync(w.hx[slot]->p, v_in, gb, hipMemcpyDeviceToDevice, st));
-      DKS_HIP(hipMemcpyAsync(w.hr[slot]->p, r, gb, hipMemcpyDeviceToDevice, st));
-      order.push_back(slot);
-      for (int j : order) {
-        const double g = reduce(w, w.hr[slot]->as<double>(), w.hr[j]->as<double>(), ng, false, st);
-        G[(size_t)slot * (depth + 1) + j] = g;
-        G[(size_t)j * (depth + 1) + slot] = g;
-      }
-      const int k = (int)order.size() - 1;
-      // coefficients a_j of xbar = sum a_j x_j and rbar = sum a_j r_j over the
-      // stored pairs (oldest first): xbar = x_k - sum_i gamma_i (x_{i+1} - x_i)
-      std::vector<double> a(k + 1, 0.0);
-      a[k] = 1.0;
-      if (k > 0) {
-        auto gr = [&](int i, int j) { return G[(size_t)order[i] * (depth + 1) + order[j]]; };
-        // (dR^T dR)_{ij} and (dR^T r_k)_i with dR_i = r_{i+1} - r_i
-        std::vector<double> A((size_t)k * k), rhs(k);
-        for (int i = 0; i < k; ++i) {
-          for (int j = 0; j < k; ++j)
-            A[(size_t)i * k + j] = gr(i + 1, j + 1) - gr(i + 1, j) - gr(i, j + 1) + gr(i, j);
-          rhs[i] = gr(i + 1, k) - gr(i, k);
+      polish = false;
+      // Anderson: the differences to the last pair go into the oldest slot
+      // (dX = x_k - x_{k-1}, dR = r_k - r_{k-1}), then
+      // gamma = argmin |r_k - dR gamma|, xbar = x_k - dX gamma, rbar = r_k - dR gamma
+      if (have_prev && depth > 0) {
+        int slot;
+        if ((int)order.size() < depth) {
+          slot = (int)order.size();
+        } else {
+          slot = order.front();
+          order.erase(order.begin());
         }
+        lincomb(w.hx[slot]->as<double>(), {v_in, w.x_prev.as<double>()}, {1.0, -1.0}, ng, st);
+        lincomb(w.hr[slot]->as<double>(), {r, w.r_prev.as<double>()}, {1.0, -1.0}, ng, st);
+        order.push_back(slot);
+        std::vector<std::pair<const double *, const double *>> pr;
+        for (int j : order) pr.push_back({w.hr[slot]->as<double>(), w.hr[j]->as<double>()});
+        const std::vector<double> g = dots(w, pr, ng, st);
+        for (size_t q = 0; q < order.size(); ++q) {
+          G[(size_t)slot * depth + order[q]] = g[q];
+          G[(size_t)order[q] * depth + slot] = g[q];
+        }
+      }
+      DKS_HIP(hipMemcpyAsync(w.x_prev.p, v_in, gb, hipMemcpyDeviceToDevice, st));
+      DKS_HIP(hipMemcpyAsync(w.r_prev.p, r, gb, hipMemcpyDeviceToDevice, st));
+      have_prev = true;
+      const int k = (int)order.size();
+      std::vector<const double *> xs{v_in}, rs{r};
+      std::vector<double> a{1.0};
+      if (k > 0) {
+        std::vector<std::pair<const double *, const double *>> pr;
+        for (int j : order) pr.push_back({w.hr[j]->as<double>(), r});
+        const std::vector<double> rhs = dots(w, pr, ng, st);
+        std::vector<double> A((size_t)k * k);
+        for (int i = 0; i < k; ++i)
+          for (int j = 0; j < k; ++j) A[(size_t)i * k + j] = G[(size_t)order[i] * depth + order[j]];
         const std::vector<double> gam = small_lsq(A, rhs, k);
         for (int i = 0; i < k; ++i) {
-          a[i + 1] -= gam[i];
-          a[i] += gam[i];
+          xs.push_back(w.hx[order[i]]->as<double>());
+          rs.push_back(w.hr[order[i]]->as<double>());
+          a.push_back(-gam[i]);
         }
-      }
-      std::vector<const double *> xs, rs;
-      for (int i = 0; i <= k; ++i) {
-        xs.push_back(w.hx[order[i]]->as<double>());
-        rs.push_back(w.hr[order[i]]->as<double>());
       }
       lincomb(w.xbar.as<double>(), xs, a, ng, st);
       lincomb(w.tmp.as<double>(), rs, a, ng, st);
