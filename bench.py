@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve runs")
+    ap.add_argument("--only-scf", action="store_true",
+                    help="profiling aid: only the heavy-dimer SCF loops (DKS and KSSO)")
     ap.add_argument("--only-apply", action="store_true",
                     help="profiling aid: only K FP64 H.X applications of the 40-band block, then "
                          "one device copy of 1 GiB (the calibration kernel for HBM counters)")
@@ -137,6 +139,52 @@ def main():
     X0[:, :2] = phi
     X0d = torch.from_numpy(X0).to(dev)
     stream = torch.cuda.current_stream()
+
+    # ---- the SCF loop around the eigensolver (Sec. 4; Table 6 reports the wall
+    # time per SCF step): 24 electrons in the 40 lowest bands (+ 8 buffer
+    # columns) at 5000 K, 10 eigensolver iterations per step, Anderson + Kerker
+    # mixing, to ||dV|| / ||V|| < 1e-8 with every wanted residual below 1e-8;
+    # DKS (LOBPCG-F) and KSSO (standard LOBPCG)
+    def run_scf():
+        v_ext = dk.get_local_potential(b, 0).clone()
+        nscf = n + 8
+        phis = sysgen.start_block(mil, s.lattice, s.kpts[0], nscf, 0)
+        X4s = np.zeros((nscf, 4, N), dtype=np.complex128)
+        X4s[:, :2] = phis
+        scf_rec = {"workload": "heavy dimer, 24 electrons in the 40 lowest bands + 8 buffer at "
+                               "5000 K, 10 eigensolver iterations per SCF step, Anderson + Kerker, "
+                               "tol 1e-8", "models": {}}
+        for tag, model, start in (("dks", dk.MODEL_DKS, X4s), ("ksso", dk.MODEL_KSSO, phis)):
+            dk.set_local_potential(b, 0, v_ext)
+            Xs = torch.from_numpy(np.ascontiguousarray(start)).to(dev)
+            eo = dk.default_opts(model=model, kinetic_balance=1 if model == dk.MODEL_DKS else 0,
+                                 use_filter=1 if model == dk.MODEL_DKS else 0, tol=1e-8, n_buffer=8,
+                                 n_iter=400)
+            so = dk.scf_default_opts(n_electrons=24.0, tol=1e-8, max_scf=120, eig_iters=10)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, occ_, info_, rc_ = dk.scf(b, 0, nscf, Xs, so, eo)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t
+            scf_rec["models"][tag] = {
+                "seconds": sec, "steps": info_["iterations"],
+                "step_ms": 1000.0 * sec / max(info_["iterations"], 1),
+                "ms_per_eig_iteration": 1000.0 * sec / max(info_["eig_iterations"], 1),
+                "eig_iterations": info_["eig_iterations"], "converged": info_["converged"],
+                "status": rc_, "residual": info_["residual"], "free_energy_Ha": info_["free_energy"],
+                "fermi_Ha": info_["fermi"], "max_bxc_Ha": info_["max_bxc"]}
+            log(f"[bench] SCF {tag}: {info_['iterations']} steps in {sec:.3f}s "
+                f"({1000.0 * sec / max(info_['iterations'], 1):.2f} ms/step), converged {info_['converged']}, "
+                f"residual {info_['residual']:.1e}")
+        m_ = scf_rec["models"]
+        scf_rec["dks_over_ksso_step_cost"] = m_["dks"]["step_ms"] / m_["ksso"]["step_ms"]
+        dk.set_local_potential(b, 0, v_ext)
+        return scf_rec
+
+    if args.only_scf:
+        run_scf()
+        b.close()
+        return
 
     if args.only_apply:
         Xd = X0d
@@ -265,9 +313,10 @@ def main():
         path = os.path.join(ROOT, "tests", "golden", name)
         return json.load(open(path)) if os.path.exists(path) else None
 
-    def solve_record(bs, nb, X0_, mode, ref=None, n_buffer=0):
+    def solve_record(bs, nb, X0_, mode, ref=None, n_buffer=0, method=None):
         Xd_ = X0_.clone()
-        o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=n_buffer)
+        o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=n_buffer,
+                            method=dk.METHOD_LOBPCG if method is None else method)
         torch.cuda.synchronize()
         t = time.perf_counter()
         lam, res, info, rc = dk.lobpcgf_solve(bs, 0, nb, Xd_, o)
@@ -296,6 +345,12 @@ def main():
             tts["seeds"]["0"][tag] = rec
             log(f"[bench] seed 0 solve {tag}: {rec['seconds']:.3f}s, {rec['iterations']} it, "
                 f"max|r| {rec['max_resnorm']:.2e}")
+        # the filter inside a block Davidson solver (FP64, space of 4n vectors)
+        rec = solve_record(b, n, X0d, dk.MODE_FP64, gh["eigenvalues"] if gh else None,
+                           method=dk.METHOD_DAVIDSON)
+        tts["seeds"]["0"]["davidson_fp64"] = rec
+        log(f"[bench] seed 0 solve davidson_fp64: {rec['seconds']:.3f}s, {rec['iterations']} it, "
+            f"max|r| {rec['max_resnorm']:.2e}")
 
     # ---- the paper's comparison module (Table 1): the two-component KSSO
     # operator |k+G|^2/2 + V_loc + V_2 on the same system, standard LOBPCG (one
@@ -325,46 +380,7 @@ def main():
         log(f"[bench] KSSO LOBPCG iteration {ksso_ms:.3f} ms, to 1e-8 {ksso_tts:.3f}s "
             f"({infok['iterations']} it); DKS/KSSO per iteration {ksso['dks_over_ksso_iteration_cost']:.2f}")
 
-    # ---- the SCF loop around the eigensolver (Sec. 4; Table 6 reports the wall
-    # time per SCF step): 24 electrons in the 40 lowest bands (+ 8 buffer
-    # columns) at 5000 K, 10 eigensolver iterations per step, Anderson + Kerker
-    # mixing, to ||dV|| / ||V|| < 1e-8 with every wanted residual below 1e-8;
-    # DKS (LOBPCG-F) and KSSO (standard LOBPCG)
-    scf_rec = None
-    if not args.no_solve:
-        v_ext = dk.get_local_potential(b, 0).clone()
-        nscf = n + 8
-        phis = sysgen.start_block(mil, s.lattice, s.kpts[0], nscf, 0)
-        X4s = np.zeros((nscf, 4, N), dtype=np.complex128)
-        X4s[:, :2] = phis
-        scf_rec = {"workload": "heavy dimer, 24 electrons in the 40 lowest bands + 8 buffer at "
-                               "5000 K, 10 eigensolver iterations per SCF step, Anderson + Kerker, "
-                               "tol 1e-8", "models": {}}
-        for tag, model, start in (("dks", dk.MODEL_DKS, X4s), ("ksso", dk.MODEL_KSSO, phis)):
-            dk.set_local_potential(b, 0, v_ext)
-            Xs = torch.from_numpy(np.ascontiguousarray(start)).to(dev)
-            eo = dk.default_opts(model=model, kinetic_balance=1 if model == dk.MODEL_DKS else 0,
-                                 use_filter=1 if model == dk.MODEL_DKS else 0, tol=1e-8, n_buffer=8,
-                                 n_iter=400)
-            so = dk.scf_default_opts(n_electrons=24.0, tol=1e-8, max_scf=120, eig_iters=10)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            _, occ_, info_, rc_ = dk.scf(b, 0, nscf, Xs, so, eo)
-            torch.cuda.synchronize()
-            sec = time.perf_counter() - t
-            scf_rec["models"][tag] = {
-                "seconds": sec, "steps": info_["iterations"],
-                "step_ms": 1000.0 * sec / max(info_["iterations"], 1),
-                "ms_per_eig_iteration": 1000.0 * sec / max(info_["eig_iterations"], 1),
-                "eig_iterations": info_["eig_iterations"], "converged": info_["converged"],
-                "status": rc_, "residual": info_["residual"], "free_energy_Ha": info_["free_energy"],
-                "fermi_Ha": info_["fermi"], "max_bxc_Ha": info_["max_bxc"]}
-            log(f"[bench] SCF {tag}: {info_['iterations']} steps in {sec:.3f}s "
-                f"({1000.0 * sec / max(info_['iterations'], 1):.2f} ms/step), converged {info_['converged']}, "
-                f"residual {info_['residual']:.1e}")
-        m_ = scf_rec["models"]
-        scf_rec["dks_over_ksso_step_cost"] = m_["dks"]["step_ms"] / m_["ksso"]["step_ms"]
-        dk.set_local_potential(b, 0, v_ext)
+    scf_rec = run_scf() if not args.no_solve else None
     b.close()
 
     # ---- seeds 1 and 2 of the same workload: the timed iterations (the
