@@ -1167,13 +1167,17 @@ static void graph_start(GraphItem &g, Blocks<T> &bk, int n_init, double tol, dou
 }
 
 // Runs one graph stage in precision T for every item: the eager start, one
-// eager iteration (which also sizes every buffer), then a graph of `chunk`
-// iterations per item captured once and launched until every item has left.
-// Returns the iterations each item took (through its flags).
+// eager iteration (which also sizes every buffer), then one graph per group of
+// items (the items of a group one after another on the group's stream, which
+// every item of the group uses), each holding `chunk` iterations of its items,
+// captured once and launched on its stream until every item has left.  The
+// groups run concurrently, one stream each.  Returns the iterations each item
+// took (through its flags).
 template <typename T>
 static void graph_stage(GraphPool &pool, std::vector<GraphItem> &items,
                         std::vector<Blocks<T> *> &blk, int n_init, double tol, int cap,
-                        int stall_window, double drop_tol, int chunk, int *flags_h) {
+                        int stall_window, double drop_tol, int chunk, int *flags_h,
+                        const std::vector<std::vector<int>> &groups) {
   const int ni = (int)items.size();
   const int nf = kGfCount * ni;
   const auto t_begin = std::chrono::steady_clock::now();
@@ -1191,39 +1195,43 @@ static void graph_stage(GraphPool &pool, std::vector<GraphItem> &items,
     graph_iteration<T>(items[i], *blk[i], 1, tol, cap, stall_window, drop_tol);
   }
   for (int i = 0; i < ni; ++i) DKS_HIP(hipStreamSynchronize(items[i].st));
-  // capture `chunk` iterations of every item (Z[0] -> Z[1] -> Z[0] ...), one
-  // branch per item
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  {
+  // capture `chunk` iterations of the items of each group (Z[0] -> Z[1] ->
+  // Z[0] ...) on the group's stream
+  const int ng = (int)groups.size();
+  std::vector<hipGraph_t> graphs(ng, nullptr);
+  std::vector<hipGraphExec_t> execs(ng, nullptr);
+  auto destroy = [&]() {
+    for (auto &e : execs)
+      if (e) (void)hipGraphExecDestroy(e), e = nullptr;
+    for (auto &g : graphs)
+      if (g) (void)hipGraphDestroy(g), g = nullptr;
+  };
+  try {
     ProfPause no_events;
-    DKS_HIP(hipStreamBeginCapture(pool.origin, hipStreamCaptureModeThreadLocal));
-    try {
-      DKS_HIP(hipEventRecord(pool.fork, pool.origin));
-      for (int i = 0; i < ni; ++i) {
-        DKS_HIP(hipStreamWaitEvent(items[i].st, pool.fork, 0));
-        for (int k = 0; k < chunk; ++k)
-          graph_iteration<T>(items[i], *blk[i], k & 1, tol, cap, stall_window, drop_tol);
-        DKS_HIP(hipEventRecord(pool.join[i], items[i].st));
-        DKS_HIP(hipStreamWaitEvent(pool.origin, pool.join[i], 0));
+    for (int gi = 0; gi < ng; ++gi) {
+      hipStream_t gs = items[groups[gi][0]].st;
+      DKS_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int i : groups[gi])
+          for (int k = 0; k < chunk; ++k)
+            graph_iteration<T>(items[i], *blk[i], k & 1, tol, cap, stall_window, drop_tol);
+      } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(gs, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        throw;
       }
-    } catch (...) {
-      hipGraph_t dead = nullptr;
-      (void)hipStreamEndCapture(pool.origin, &dead);
-      if (dead) (void)hipGraphDestroy(dead);
-      throw;
+      DKS_HIP(hipStreamEndCapture(gs, &graphs[gi]));
     }
-    DKS_HIP(hipStreamEndCapture(pool.origin, &graph));
+  } catch (...) {
+    destroy();
+    throw;
   }
   const auto t_cap = std::chrono::steady_clock::now();
-  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    DKS_HIP(e);
-  }
   try {
+    for (int gi = 0; gi < ng; ++gi) DKS_HIP(hipGraphInstantiate(&execs[gi], graphs[gi], nullptr, nullptr, 0));
     int *hf = flags_h;
-    // each launch runs `chunk` iterations of every item still in the stage
+    // each round runs `chunk` iterations of every item still in the stage
     const auto t_inst = std::chrono::steady_clock::now();
     const int max_launch = cap / chunk + 2;
     int launches = 0;
@@ -1231,28 +1239,31 @@ static void graph_stage(GraphPool &pool, std::vector<GraphItem> &items,
       DKS_HIP(hipMemcpyAsync(hf, pool.gflags.p, sizeof(int) * nf, hipMemcpyDeviceToHost,
                              pool.origin));
       DKS_HIP(hipStreamSynchronize(pool.origin));
-      bool all = true;
-      for (int i = 0; i < ni; ++i) all = all && hf[kGfCount * i + kGfSkip];
-      if (all) break;
-      DKS_HIP(hipGraphLaunch(exec, pool.origin));
+      std::vector<int> live;
+      for (int gi = 0; gi < ng; ++gi) {
+        bool all = true;
+        for (int i : groups[gi]) all = all && hf[kGfCount * i + kGfSkip];
+        if (!all) live.push_back(gi);
+      }
+      if (live.empty()) break;
+      for (int gi : live) DKS_HIP(hipGraphLaunch(execs[gi], items[groups[gi][0]].st));
+      for (int gi : live) DKS_HIP(hipStreamSynchronize(items[groups[gi][0]].st));
     }
     DKS_HIP(hipStreamSynchronize(pool.origin));
     DKS_HIP(hipMemcpy(hf, pool.gflags.p, sizeof(int) * nf, hipMemcpyDeviceToHost));
     if (log_enabled()) {
       auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
       std::fprintf(stderr,
-                   "{\"graph_stage\": {\"prec\": %d, \"items\": %d, \"chunk\": %d, \"start_ms\": %.1f, "
-                   "\"instantiate_ms\": %.1f, \"launches\": %d, \"run_ms\": %.1f}}\n",
-                   (int)sizeof(T), ni, chunk, ms(t_begin, t_cap), ms(t_cap, t_inst), launches,
+                   "{\"graph_stage\": {\"prec\": %d, \"items\": %d, \"groups\": %d, \"chunk\": %d, "
+                   "\"start_ms\": %.1f, \"instantiate_ms\": %.1f, \"rounds\": %d, \"run_ms\": %.1f}}\n",
+                   (int)sizeof(T), ni, ng, chunk, ms(t_begin, t_cap), ms(t_cap, t_inst), launches,
                    ms(t_inst, std::chrono::steady_clock::now()));
     }
   } catch (...) {
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    destroy();
     throw;
   }
-  DKS_HIP(hipGraphExecDestroy(exec));
-  DKS_HIP(hipGraphDestroy(graph));
+  destroy();
 }
 
 // dks_lobpcgf_solve_batch with batch_graph = 1.
@@ -1275,6 +1286,20 @@ static void solve_batch_graph(dks_basis *b, int nsys, const int *sys, const int 
   int *hf = pool.hflags.as<int>((size_t)kGfCount * nsys);
   // the stage starts after the work queued on the caller's stream
   DKS_HIP(hipEventRecord(pool.fork, cst));
+  // groups of items, one stream each: largest items first, dealt round-robin
+  const int ngroups = std::max(1, std::min(nsys, batch_lanes()));
+  std::vector<std::vector<int>> groups(ngroups);
+  {
+    std::vector<int> order(nsys);
+    for (int i = 0; i < nsys; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+      return (int64_t)b->sys[sys[a]]->N * n[a] > (int64_t)b->sys[sys[c]]->N * n[c];
+    });
+    for (int q = 0; q < nsys; ++q) groups[q % ngroups].push_back(order[q]);
+  }
+  std::vector<int> group_of(nsys);
+  for (int gi = 0; gi < ngroups; ++gi)
+    for (int i : groups[gi]) group_of[i] = gi;
   std::vector<GraphItem> items(nsys);
   std::vector<dks_solve_info> inf(nsys);
   for (int i = 0; i < nsys; ++i) {
@@ -1286,7 +1311,7 @@ static void solve_batch_graph(dks_basis *b, int nsys, const int *sys, const int 
     g.sys = sys[i];
     g.n = n[i];
     g.nwant = n[i] - iopt[i].n_buffer;
-    g.st = pool.streams[i];
+    g.st = pool.streams[group_of[i]];
     g.sv = pool.solvers[i];
     g.flags = pool.gflags.as<int>() + kGfCount * i;
     g.state = pool.gstate.as<double>() + kGsCount * i;
@@ -1331,7 +1356,7 @@ static void solve_batch_graph(dks_basis *b, int nsys, const int *sys, const int 
     }
     const double t32 = o.mixed_tol > 0 ? o.mixed_tol : 0.0;
     graph_stage<float>(pool, items, b32, o.n_init, t32, std::max(2, o.mixed_iter), kStallFp32, 1e-5,
-                       chunk, hf);
+                       chunk, hf, groups);
     for (int i = 0; i < nsys; ++i) {
       const int xb = hf[kGfCount * i + kGfXbuf];
       inf[i].iters_reduced = hf[kGfCount * i + kGfIters];
@@ -1350,7 +1375,7 @@ static void solve_batch_graph(dks_basis *b, int nsys, const int *sys, const int 
   std::vector<Blocks<double> *> b64(nsys);
   for (int i = 0; i < nsys; ++i) b64[i] = &items[i].sv->b64;
   graph_stage<double>(pool, items, b64, n_init64, o.tol, std::max(2, o.n_iter), kStallFp64, 1e-10,
-                      chunk, hf);
+                      chunk, hf, groups);
   // results: converged items straight from the device; the others go back to
   // the lanes from their last good block (a filtered restart)
   std::vector<int> left;
