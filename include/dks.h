@@ -293,15 +293,18 @@ dks_status dks_autotune(dks_basis *b, int nsys, const int *sys, const int *nb, d
 /* The launch shapes in use for system `sys` (NULL pointers are skipped): z tile,
  * plane kernel form (0: FP64 768 / FP32 512 threads, 1: 256 threads for planes
  * within its LDS budget, 2 and 3: the same with each wave owning whole lines of
- * every line pass), projector split-K target.  Host only. */
+ * every line pass, 4 and 5: forms 0 and 1 with the column loads and stores
+ * folded into the first and last transform steps), projector split-K target.
+ * An unset plane form is reported as the one FP64 applies use (FP32 applies
+ * take form 0 or 1 then).  Host only. */
 dks_status dks_get_tuning(const dks_basis *b, int sys, int *tile_z, int *plane_form,
                           int *ip_blocks);
 
 /* Set the launch shapes of system `sys` (a stored autotuner table):
  * 1 <= tile_z <= 64 within the LDS for the grid's third axis, plane_form in
- * [-1, 3] (-1: by size; a small form on a plane above its budget falls back to
- * the large one), ip_blocks in [0, 65536] (0: default).  Host only; calls on the
- * basis must not overlap it. */
+ * [-1, 5] (-1: by size and precision; a small form on a plane above its budget
+ * falls back to the large one), ip_blocks in [0, 65536] (0: default).  Host
+ * only; calls on the basis must not overlap it. */
 dks_status dks_set_tuning(dks_basis *b, int sys, int tile_z, int plane_form, int ip_blocks);
 
 /* Kernel timing (a diagnostic for roofline accounting).  When enabled, every

@@ -333,6 +333,21 @@ dks_status dks_init_basis(const dks_system_desc *descs, int ndesc, int device, d
           S->rows = r;
           S->nrows = (int)r.size();
         }
+        // per sphere row r and n2 slot p: the column there, or -1; and which n1
+        // slots are sphere rows (the plane kernel's direct form reads these)
+        {
+          std::vector<int> slot(n1, -1), ctab((size_t)S->nrows * n2, -1), flag(n1, 0);
+          for (int r = 0; r < S->nrows; ++r) {
+            slot[S->rows[r]] = r;
+            flag[S->rows[r]] = 1;
+          }
+          for (int c = 0; c < S->ncol; ++c) {
+            const int4 ci = S->col_info[c];
+            ctab[(size_t)slot[ci.x] * n2 + ci.y] = c;
+          }
+          upload(S->d_ctab, ctab.data(), sizeof(int) * ctab.size());
+          upload(S->d_rowflag, flag.data(), sizeof(int) * flag.size());
+        }
         upload(S->d_col_off, S->col_off.data(), sizeof(int) * S->col_off.size());
         upload(S->d_col_info, S->col_info.data(), sizeof(int4) * S->col_info.size());
         upload(S->d_rows, S->rows.data(), sizeof(int) * S->rows.size());

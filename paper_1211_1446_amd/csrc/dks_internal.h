@@ -171,6 +171,8 @@ struct System {
   double nl_bound = 0;
   // device tables
   DevBuf d_col_off, d_col_info, d_rows, d_gmap;   // gmap: per G {local column, z slot}
+  DevBuf d_ctab;                                  // [nrows][n2]: column at (row, n2 slot) or -1
+  DevBuf d_rowflag;                               // [n1]: 1 where the n1 slot is a sphere row
   DevBuf d_q64, d_q32;                            // SoA qx | qy | qz
   DevBuf d_B64, d_B32;                            // [nproj][N] complex
   DevBuf d_W64;                                   // all W blocks, complex double

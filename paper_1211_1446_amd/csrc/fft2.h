@@ -263,6 +263,114 @@ __device__ __forceinline__ void inv2_mul_fwd2(typename CT<T>::c *buf, const Walk
   });
 }
 
+// Steps that touch only part of a line.  `keep[e]` (LDS) is nonzero for the
+// natural-order elements e that carry data: the inverse step 1 reads those and
+// takes the others as zero (they are never written before it), and writes the
+// whole line; the forward step 1' writes only those (the others are not read
+// again).  With A = 1 the inverse form still clears the rest of the line.
+template <int A, int B, typename T>
+__device__ __forceinline__ void inv_step1_keep(typename CT<T>::c *buf, const Walk &w, Lines L,
+                                               const typename CT<T>::c *tw, const int *keep) {
+  using C = typename CT<T>::c;
+  for_tasks(w, w.nl * B, [&](int b, int l) {
+    const int base = L.base(l) + b * L.stride;
+    int kb[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) kb[a] = keep[b + B * a];   // all flags first: no wait between reads
+    C v[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      v[a] = C{0, 0};
+      if (kb[a]) v[a] = buf[base + B * a * L.stride];
+    }
+    if constexpr (A > 1) {
+      Codelet<A, +1, T>::run(v);
+#pragma unroll
+      for (int ka = 1; ka < A; ++ka) v[ka] = cmul(v[ka], twt<+1>(tw, b * ka));
+    }
+#pragma unroll
+    for (int a = 0; a < A; ++a) buf[base + B * a * L.stride] = v[a];
+  });
+}
+template <int A, int B, typename T>
+__device__ __forceinline__ void fwd_step1_keep(typename CT<T>::c *buf, const Walk &w, Lines L,
+                                               const int *keep) {
+  using C = typename CT<T>::c;
+  if constexpr (A > 1) {
+    for_tasks(w, w.nl * B, [&](int b, int l) {
+      const int base = L.base(l) + b * L.stride;
+      int kb[A];
+      C v[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) kb[a] = keep[b + B * a];
+#pragma unroll
+      for (int a = 0; a < A; ++a) v[a] = buf[base + B * a * L.stride];
+      Codelet<A, -1, T>::run(v);
+#pragma unroll
+      for (int a = 0; a < A; ++a)
+        if (kb[a]) buf[base + B * a * L.stride] = v[a];
+    });
+  }
+}
+
+// Steps 1 and 1' of the sphere rows against global memory.  Row r of the
+// plane holds, at n2 slot p, column ctab[r n2 + p] of the plane's column
+// values `t` (-1: no column, zero).  Tasks run b fastest, so that the lanes of
+// a wave read and write neighbouring slots of one row.  The inverse step
+// writes whole rows to the LDS plane at row_of(r) * ld; the forward step reads
+// them there and stores the column slots only.  Loads are unconditional (a
+// missing column reads column 0 and is replaced by zero), so that all of a
+// task's loads are in flight together.
+template <int A, int B, typename T>
+__device__ __forceinline__ void inv_step1_rows_in(typename CT<T>::c *pl, int ld, const int *rows,
+                                                  int nrows, int n2, const int *__restrict__ ctab,
+                                                  const typename CT<T>::c *t,
+                                                  const typename CT<T>::c *tw) {
+  using C = typename CT<T>::c;
+  for_tasks(walk(B), nrows * B, [&](int r, int b) {
+    const int *cr = ctab + (size_t)r * n2 + b;
+    const int row = rows[r];
+    int c[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) c[a] = cr[B * a];
+    C v[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) v[a] = t[c[a] > 0 ? c[a] : 0];
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+      if (c[a] < 0) v[a] = C{0, 0};
+    if constexpr (A > 1) {
+      Codelet<A, +1, T>::run(v);
+#pragma unroll
+      for (int ka = 1; ka < A; ++ka) v[ka] = cmul(v[ka], twt<+1>(tw, b * ka));
+    }
+    C *dst = pl + row * ld + b;
+#pragma unroll
+    for (int a = 0; a < A; ++a) dst[B * a] = v[a];
+  });
+}
+template <int A, int B, typename T>
+__device__ __forceinline__ void fwd_step1_rows_out(const typename CT<T>::c *pl, int ld,
+                                                   const int *rows, int nrows, int n2,
+                                                   const int *__restrict__ ctab,
+                                                   typename CT<T>::c *t) {
+  using C = typename CT<T>::c;
+  for_tasks(walk(B), nrows * B, [&](int r, int b) {
+    const int *cr = ctab + (size_t)r * n2 + b;
+    int c[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) c[a] = cr[B * a];   // in flight during the LDS reads
+    const C *src = pl + rows[r] * ld + b;
+    C v[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) v[a] = src[B * a];
+    if constexpr (A > 1) Codelet<A, -1, T>::run(v);
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+      if (c[a] >= 0) t[c[a]] = v[a];
+  });
+}
+
 // ---- supported lengths and their (A, B) split --------------------------------
 // Plane axes (n <= 128) and z lines (n <= 400) have separate tables so that the
 // register budget of each kernel is set by its own largest codelet.  Returns

@@ -362,6 +362,83 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   }
 }
 
+// The same plane transform with the column loads and stores folded into the
+// first and last steps along a2 (plane form 4): the sphere rows are built in
+// registers from the column values (through the column table, zeros where a
+// row has no column) and their inverse step 1 runs before anything reaches
+// the LDS; the forward step 1' stores the column slots straight from
+// registers.  Along a1 only the sphere rows are read (inverse step 1) and
+// written back (forward step 1').  No clearing, scattering or gathering pass
+// over the LDS plane and three workgroup barriers fewer.
+template <typename T>
+size_t plane_direct_lds_bytes(int n1, int n2) {
+  return plane_lds_bytes<T>(n1, n2) + sizeof(int) * (size_t)((n1 + 3) & ~3);
+}
+// kSmall: 256-thread workgroups for planes within the small LDS budget, as
+// for k_plane (plane form 5).
+template <typename T, bool kSmall>
+__global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plane_direct(
+    typename CT<T>::c *__restrict__ T1, int ncol, const int *__restrict__ ctab,
+    const int *__restrict__ rowflag, const int *__restrict__ rows, int nrows,
+    const FftPlan *__restrict__ pxy, const typename CT<T>::c *__restrict__ twx,
+    const typename CT<T>::c *__restrict__ twy, const T *__restrict__ V,
+    const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a finished system of a graph-captured batch
+  using C = typename CT<T>::c;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *pl = reinterpret_cast<C *>(smem_raw);
+  const int n1 = pxy[0].n, n2 = pxy[1].n;
+  const int ld = n2 + 1;
+  const int z = blockIdx.x;
+  const int cc = blockIdx.y;
+  const int n3 = gridDim.x;
+  const int n1p = (n1 + 3) & ~3;
+  int *rows_s = reinterpret_cast<int *>(pl + n1 * ld);
+  C *twx_s = reinterpret_cast<C *>(rows_s + n1p), *twy_s = twx_s + n1;
+  int *keep_s = reinterpret_cast<int *>(twx_s + (kPlaneTwLds<T> ? n1 + n2 : 0));
+  // the tables' LDS copies are written after the first step, whose loads go
+  // out first
+  auto stage = [&]() {
+    for (int e = threadIdx.x; e < nrows; e += blockDim.x) rows_s[e] = rows[e];
+    for (int e = threadIdx.x; e < n1; e += blockDim.x) keep_s[e] = rowflag[e];
+    if constexpr (kPlaneTwLds<T>) {
+      for (int e = threadIdx.x; e < n1; e += blockDim.x) twx_s[e] = twx[e];
+      for (int e = threadIdx.x; e < n2; e += blockDim.x) twy_s[e] = twy[e];
+    }
+  };
+  const C *tx = kPlaneTwLds<T> ? twx_s : twx;
+  const C *ty = kPlaneTwLds<T> ? twy_s : twy;
+  C *t = T1 + ((size_t)cc * n3 + z) * ncol;
+  const T *v = V + (size_t)z * n1 * n2;   // potential of this plane, [p1][p2] scrambled
+  const fft2::Lines Ly{rows_s, ld, 1};      // rows holding sphere columns, along a2
+  const fft2::Lines Lx{nullptr, 1, ld};     // every a2 position, along a1
+  const fft2::Walk Wr = fft2::walk(nrows), Wc = fft2::walk(n2);
+  // inverse along a2 (step 1 from the columns, global twiddles: the LDS copy
+  // is not complete before the first barrier)
+  fft2::dispatch_plane(n2, [&]<int A, int B>() {
+    fft2::inv_step1_rows_in<A, B, T>(pl, ld, rows, nrows, n2, ctab, t, twy);
+    stage();
+    __syncthreads();
+    fft2::inv_step2<A, B, T>(pl, Wr, Ly);
+  });
+  __syncthreads();
+  // inverse along a1 (sphere rows in), x V, forward along a1 (sphere rows out)
+  fft2::dispatch_plane(n1, [&]<int A, int B>() {
+    fft2::inv_step1_keep<A, B, T>(pl, Wc, Lx, tx, keep_s);
+    __syncthreads();
+    fft2::inv2_mul_fwd2<A, B, T>(pl, Wc, Lx, tx, v, 1, n2);
+    __syncthreads();
+    fft2::fwd_step1_keep<A, B, T>(pl, Wc, Lx, keep_s);
+  });
+  __syncthreads();
+  // forward along a2 (step 1' to the columns)
+  fft2::dispatch_plane(n2, [&]<int A, int B>() {
+    fft2::fwd_step2<A, B, T>(pl, Wr, Ly, ty);
+    __syncthreads();
+    fft2::fwd_step1_rows_out<A, B, T>(pl, ld, rows_s, nrows, n2, ctab, t);
+  });
+}
+
 // ---------------------------------------------------------------------------
 // projectors: C' = W C, per band, two-spinor and (atom, l) group
 // C is [nproj][4 nb] (FP64); W blocks are (2 dim)^2, index (i m, s).
@@ -636,10 +713,28 @@ void init_kernel_attributes() {
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_nl_kin<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane_real<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane_real<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   init_scf_kernel_attributes();
   done = true;
+}
+
+// Plane form when none is set: the direct forms in FP64 (fewer LDS passes pay
+// where the LDS traffic is 16 bytes a point), the LDS-staged ones in FP32;
+// the 256-thread forms for planes within the small budget.
+template <typename T>
+int default_plane_form(const System &s) {
+  if (!(fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]))) return 0;
+  if (sizeof(T) == 8) {
+    const size_t smd = plane_direct_lds_bytes<T>(s.grid[0], s.grid[1]);
+    if (smd > 163840) return 0;
+    return smd <= kSmallPlaneLds ? 5 : 4;
+  }
+  return plane_lds_bytes<T>(s.grid[0], s.grid[1]) <= kSmallPlaneLds ? 1 : 0;
 }
 
 template <typename T>
@@ -726,7 +821,17 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
   size_t smp = plane_lds_bytes<T>(s.grid[0], s.grid[1]);
   const bool tab = fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]);
   const bool fits_small = tab && smp <= kSmallPlaneLds;
-  const int form = s.plane_form >= 0 ? s.plane_form : (fits_small ? 1 : 0);
+  const int form = s.plane_form >= 0 ? s.plane_form : default_plane_form<T>(s);
+  if (tab && (form == 4 || form == 5) &&
+      plane_direct_lds_bytes<T>(s.grid[0], s.grid[1]) <= 163840) {
+    const size_t smd = plane_direct_lds_bytes<T>(s.grid[0], s.grid[1]);
+    const bool dsmall = form == 5 && smd <= kSmallPlaneLds;
+    DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"),
+               (dsmall ? k_plane_direct<T, true> : k_plane_direct<T, false>), gp,
+               dim3(dsmall ? kSmallPlaneThreads : kPlaneThreads<T>), smd, st, t1,
+               s.ncol, s.d_ctab.as<int>(), s.d_rowflag.as<int>(), s.d_rows.as<int>(), s.nrows,
+               s.d_plan.as<FftPlan>(), Tw<T>(pot, 0), Tw<T>(pot, 1), Vtab<T>(pot), skip);
+  } else {
   const bool small = fits_small && (form == 1 || form == 3);
   const bool wlines = tab && (form == 2 || form == 3);
   auto kplane = !tab ? k_plane<T, false>
@@ -736,6 +841,7 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
   DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(pthr), smp, st, t1, s.ncol,
              s.d_col_info.as<int4>(), s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(),
              Tw<T>(pot, 0), Tw<T>(pot, 1), Vtab<T>(pot), skip);
+  }
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_fwd.f64" : "k_zfft_fwd.f32"), kzfwd, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
                      s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2),
@@ -908,9 +1014,9 @@ static void tune_system(dks_basis *b, int sys, int nb, hipStream_t st, double *m
     const bool tab = fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]);
     if (tab) {
       if (plane_lds_bytes<T>(s.grid[0], s.grid[1]) <= kSmallPlaneLds)
-        t = best_of(s.plane_form, {0, 1, 2, 3});
+        t = best_of(s.plane_form, {0, 1, 2, 3, 4, 5});
       else
-        t = best_of(s.plane_form, {0, 2});
+        t = best_of(s.plane_form, {0, 2, 4});
     }
     if (s.nproj > 0) t = best_of(s.ip_blocks, {256, 512, 1024, 2048});
     if (ms_out) *ms_out = t;
@@ -952,10 +1058,7 @@ extern "C" dks_status dks_get_tuning(const dks_basis *b, int sys, int *tile_z, i
     DKS_REQUIRE(b && sys >= 0 && sys < (int)b->sys.size(), DKS_EINVAL, "bad argument");
     const System &s = *b->sys[sys];
     if (tile_z) *tile_z = s.tile_z;
-    if (plane_form) {
-      const bool fits = plane_lds_bytes<double>(s.grid[0], s.grid[1]) <= kSmallPlaneLds;
-      *plane_form = s.plane_form >= 0 ? s.plane_form : (fits ? 1 : 0);
-    }
+    if (plane_form) *plane_form = s.plane_form >= 0 ? s.plane_form : default_plane_form<double>(s);
     if (ip_blocks) *ip_blocks = s.ip_blocks > 0 ? s.ip_blocks : 1024;
     return DKS_OK;
   });
@@ -969,7 +1072,7 @@ extern "C" dks_status dks_set_tuning(dks_basis *b, int sys, int tile_z, int plan
     System &s = *b->sys[sys];
     DKS_REQUIRE(tile_z >= 1 && tile_z <= 64 && sizeof(double2) * (size_t)tile_z * (s.grid[2] + 1) <= 163840,
                 DKS_EINVAL, "tile_z out of range for this grid");
-    DKS_REQUIRE(plane_form >= -1 && plane_form <= 3, DKS_EINVAL, "plane_form must be in [-1, 3]");
+    DKS_REQUIRE(plane_form >= -1 && plane_form <= 5, DKS_EINVAL, "plane_form must be in [-1, 5]");
     DKS_REQUIRE(ip_blocks >= 0 && ip_blocks <= 65536, DKS_EINVAL, "ip_blocks out of range");
     s.tile_z = tile_z;
     s.plane_form = plane_form;

@@ -447,28 +447,33 @@ def test_standard_lobpcg_collapses_and_lobpcgf_does_not(dev):
     assert np.max(np.abs(lam - lam_ref)) < 1e-8
 
 
-@pytest.mark.parametrize("form", [0, 1, 2, 3])
+@pytest.mark.parametrize("form", [0, 1, 2, 3, 4, 5])
 def test_apply_h_every_plane_form(dev, form):
     """Every plane kernel form the autotuner may pick (task split or whole lines
-    per wave, large or 256-thread workgroups) and odd z tiles give the same
-    H X: tiny dimer (24^3, all four forms) and the 96^3 heavy dimer (sampled
-    bands; its plane exceeds the small forms' budget, which then fall back)."""
+    per wave, large or 256-thread workgroups, column loads and stores folded
+    into the a2 steps) and odd z tiles give the same H X, in FP64 and FP32:
+    tiny dimer (24^3, all forms), the 96^3 heavy dimer (sampled bands; its
+    plane exceeds the small forms' budget, which then fall back) and the
+    hexagonal cell at k != 0 (rows of uneven length)."""
     dk = _dk()
-    for s, nb, bands in ((sysgen.tiny_dimer(0), 6, None), (sysgen.heavy_dimer(0), 6, (0, 5))):
+    cases = ((sysgen.tiny_dimer(0), 6, None), (sysgen.heavy_dimer(0), 6, (0, 5)),
+             (_hexagonal_system(), 4, None))
+    for s, nb, bands in cases:
         op = dks.DKSOperator(s)
         b = dk.init_basis([s])
         N, _, mil = dk.basis_info(b, 0)
         p = perm_to_oracle(mil, op.miller)
         dk.set_tuning(b, 0, 3 if s.grid[0] < 50 else 5, form, 512)
         X = random_block(np.random.default_rng(form + 30), nb, N)
-        Xd = torch.from_numpy(X).to(dev)
-        HXd = torch.empty_like(Xd)
-        print(f"[plane form {form}] {s.name} nb={nb}", flush=True)
-        dk.apply_H(b, 0, Xd, HXd)
-        torch.cuda.synchronize()
-        got = HXd.cpu().numpy()
+        for prec, ctype in (("fp64", torch.complex128), ("fp32", torch.complex64)):
+            Xd = torch.from_numpy(X).to(dev).to(ctype)
+            HXd = torch.empty_like(Xd)
+            print(f"[plane form {form}] {s.name} nb={nb} {prec}", flush=True)
+            dk.apply_H(b, 0, Xd, HXd)
+            torch.cuda.synchronize()
+            got = HXd.to(torch.complex128).cpu().numpy()
+            for band in (bands or range(nb)):
+                ref = op.apply(to_orc(X[band:band + 1], p))
+                err = row_errors(to_orc(got[band:band + 1], p), ref)
+                assert err < TOL[prec], (s.name, prec, band, err)
         b.close()
-        for band in (bands or range(nb)):
-            ref = op.apply(to_orc(X[band:band + 1], p))
-            err = row_errors(to_orc(got[band:band + 1], p), ref)
-            assert err < TOL["fp64"], (s.name, band, err)
