@@ -903,10 +903,10 @@ static void run_on_lanes(dks_basis *b, const std::vector<int> &items, const int 
 
 // ---- the graph-captured lockstep form --------------------------------------
 //
-// Every item iterates Algorithm 1 on a fixed shape: all n columns stay active
-// (no soft locking), the subspace is always [X, Y, P] of 3n rows (P = 0 in the
-// first step, whose zero columns the Rayleigh-Ritz drops as dependent), and P
-// is kept orthogonal to X.  Each iteration is then the same sequence of
+// Every item iterates Algorithm 1 on a fixed shape: the subspace is always
+// [X, Y, P] of 3n rows (P = 0 in the first step, whose zero columns the
+// Rayleigh-Ritz drops as dependent; the Y and P columns of converged columns
+// are zero likewise, k_graph_lock), and P is kept orthogonal to X.  Each iteration is then the same sequence of
 // launches with the same sizes, so the iterations of all items can be
 // captured once into one HIP graph (one branch per item on its own stream)
 // and replayed.  Two device kernels per iteration make the decisions the host
@@ -1083,6 +1083,42 @@ static void graph_reserve(GraphItem &g, Blocks<T> &bk) {
   sv.part2.ensure(sizeof(double) * (size_t)n * (size_t)((K + 8191) / 8192));
 }
 
+// Soft locking on the fixed shape: columns j whose residual is below tol get
+// no search direction, as on the lanes (the active set of Algorithm 1).  Their
+// rows of the next Y (the residual, filtered in place next step) and of P and
+// H P are cleared; the Rayleigh-Ritz drops zero columns as dependent, as it
+// does for P = 0 in the first step.  Without this, converged columns keep
+// residual directions made of rounding noise in the basis, whose Gram and
+// projected matrix then lose the H-consistency of the H X recurrence and the
+// iteration breaks down (Ritz values inside the gap below the positive band).
+template <typename T>
+__global__ void k_graph_lock(cplx<T> *__restrict__ Y, cplx<T> *__restrict__ P,
+                             cplx<T> *__restrict__ HP, const double *__restrict__ norm2, int64_t K,
+                             double tol2, const int *__restrict__ skip) {
+  if (skip && *skip) return;
+  const int j = blockIdx.y;
+  if (!(norm2[j] < tol2)) return;   // active: keeps its directions
+  const size_t o = (size_t)j * K;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    Y[o + e] = cplx<T>{0, 0};
+    if (P) {
+      P[o + e] = cplx<T>{0, 0};
+      HP[o + e] = cplx<T>{0, 0};
+    }
+  }
+}
+template <typename T>
+static void graph_lock(GraphItem &g, Blocks<T> &bk, int q, double tol, bool with_p) {
+  const int n = g.n;
+  const int64_t K = g.x.K;
+  const unsigned gx = (unsigned)std::min<int64_t>(64, (K + 255) / 256);
+  DKS_LAUNCH("k_graph_lock", k_graph_lock<T>, dim3(gx, n), dim3(256), 0, g.st, bk.z(q, n),
+             with_p ? bk.z(q, 2 * n) : nullptr, with_p ? bk.hz(q, 2 * n) : nullptr,
+             g.sv->norms.as<double>(), K, tol * tol, g.flags + kGfSkip);
+  DKS_HIP(hipGetLastError());
+}
+
 // One iteration of item g reading Z[p], writing Z[1 - p]; every launch is
 // skipped once the item's flag is set.
 template <typename T>
@@ -1123,6 +1159,7 @@ static void graph_iteration(GraphItem &g, Blocks<T> &bk, int p, double tol, int 
   // R = H X - X Lambda, written where the next step's Y goes
   residual<T>(bk.z(q, 0), bk.hz(q, 0), sv.theta.as<double>(), n, K, bk.z(q, n),
               sv.norms.as<double>(), sv.part2, st, skip);
+  graph_lock<T>(g, bk, q, tol, true);
   DKS_LAUNCH("k_graph_step", k_graph_step, dim3(1), dim3(64), 0, st, sv.norms.as<double>(),
              sv.theta.as<double>(), g.flags, g.state, n, g.nwant, tol, cap, stall_window, q, 0,
              x.guard ? 1 : 0);
@@ -1160,6 +1197,7 @@ static void graph_start(GraphItem &g, Blocks<T> &bk, int n_init, double tol, dou
              bk.hz(1, 2 * n), cnt);
   residual<T>(bk.z(1, 0), bk.hz(1, 0), sv.theta.as<double>(), n, K, bk.z(1, n),
               sv.norms.as<double>(), sv.part2, st, skip);
+  graph_lock<T>(g, bk, 1, tol, false);
   DKS_LAUNCH("k_graph_step", k_graph_step, dim3(1), dim3(64), 0, st, sv.norms.as<double>(),
              sv.theta.as<double>(), g.flags, g.state, n, g.nwant, tol, 1 << 30, 0, 1, 1,
              x.guard ? 1 : 0);
