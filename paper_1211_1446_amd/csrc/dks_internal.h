@@ -244,11 +244,14 @@ __device__ __forceinline__ int xcd_order(int L, int total) {
 // two-component Kohn-Sham operator with spin-orbit coupling (|q|^2/2 + V_loc +
 // V_2) on blocks [nb][2][N].
 // `skip` (optional, device): every kernel of the call returns at once when
-// *skip != 0 (a finished system inside a graph-captured batch).
+// *skip != 0 (a finished system inside a graph-captured batch).  `band_skip`
+// (optional, device, one int per band): the grid transforms skip the flagged
+// bands, whose rows of X must be zero (their H X rows are then the zero that
+// the kinetic and nonlocal kernel writes).
 template <typename T>
 void apply_h(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
              double scale, hipStream_t st, Workspace &ws, int ncomp = 4,
-             const int *skip = nullptr);
+             const int *skip = nullptr, const int *band_skip = nullptr);
 // The same on caller-provided scratch (nothing is allocated): the column-pruned
 // FFT intermediate, the projector coefficients before and after the couplings W,
 // and the split-K partial sums of the projector product, of the sizes
@@ -262,7 +265,7 @@ void apply_scratch_bytes(const dks_basis *b, int sys, int nb, size_t bytes[4], i
 template <typename T>
 void apply_h_on(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
                 double scale, hipStream_t st, const ApplyScratch &scr, int ncomp = 4,
-                const int *skip = nullptr);
+                const int *skip = nullptr, const int *band_skip = nullptr);
 
 // out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
 // rows addressed by element offsets.  M, Nn <= 512.  `hermitian` (A and B the same

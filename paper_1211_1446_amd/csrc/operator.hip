@@ -21,6 +21,20 @@
 
 namespace dks {
 
+// Early exit of the grid transforms, by item and by band: `item` (optional) is
+// a finished system of a graph-captured batch; `band` (optional) flags bands
+// whose input block rows are zero and whose output the kinetic and nonlocal
+// kernel has already written (zero), the locked columns of the fixed-shape
+// batch iteration.  The block index y of these kernels is the band-component.
+struct BandSkip {
+  const int *item;
+  const int *band;
+  int cshift;   // band = band-component >> cshift
+  __device__ __forceinline__ bool done(int cc) const {
+    return (item && *item) || (band && band[cc >> cshift]);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // z transforms of the sphere columns
 // ---------------------------------------------------------------------------
@@ -35,8 +49,8 @@ __global__ void __launch_bounds__(256) k_zfft_inv(const typename CT<T>::c *__res
                                                   int tile, const FftPlan *__restrict__ pzp,
                                                   const typename CT<T>::c *__restrict__ twz,
                                                   typename CT<T>::c *__restrict__ T1,
-                                                  const int *__restrict__ skip) {
-  if (skip && *skip) return;   // a finished system of a graph-captured batch
+                                                  BandSkip skip) {
+  if (skip.done(blockIdx.y)) return;   // a finished system, or a locked band
   using C = typename CT<T>::c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *lines = reinterpret_cast<C *>(smem_raw);
@@ -100,8 +114,8 @@ __global__ void __launch_bounds__(256) k_zfft_fwd(const typename CT<T>::c *__res
                                                   int tile, const FftPlan *__restrict__ pzp,
                                                   const typename CT<T>::c *__restrict__ twz,
                                                   T inv_ng, T scale,
-                                                  const int *__restrict__ skip) {
-  if (skip && *skip) return;   // a finished system of a graph-captured batch
+                                                  BandSkip skip) {
+  if (skip.done(blockIdx.y)) return;   // a finished system, or a locked band
   using C = typename CT<T>::c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *lines = reinterpret_cast<C *>(smem_raw);
@@ -210,8 +224,8 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
                                                 const typename CT<T>::c *__restrict__ twx,
                                                 const typename CT<T>::c *__restrict__ twy,
                                                 const T *__restrict__ V,
-                                                const int *__restrict__ skip) {
-  if (skip && *skip) return;   // a finished system of a graph-captured batch
+                                                BandSkip skip) {
+  if (skip.done(blockIdx.y)) return;   // a finished system, or a locked band
   using C = typename CT<T>::c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *pl = reinterpret_cast<C *>(smem_raw);
@@ -382,8 +396,8 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
     const int *__restrict__ rowflag, const int *__restrict__ rows, int nrows,
     const FftPlan *__restrict__ pxy, const typename CT<T>::c *__restrict__ twx,
     const typename CT<T>::c *__restrict__ twy, const T *__restrict__ V,
-    const int *__restrict__ skip) {
-  if (skip && *skip) return;   // a finished system of a graph-captured batch
+    BandSkip skip) {
+  if (skip.done(blockIdx.y)) return;   // a finished system, or a locked band
   using C = typename CT<T>::c;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *pl = reinterpret_cast<C *>(smem_raw);
@@ -678,7 +692,7 @@ void real_space_planes(dks_basis *b, int sysi, const double2 *X, int ncols, void
   auto kzinv = fft2::z_has(n3) ? k_zfft_inv<double, true> : k_zfft_inv<double, false>;
   DKS_LAUNCH("k_zfft_inv.f64", kzinv, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
              s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<double>(pot, 2), t1,
-             (const int *)nullptr);
+             BandSkip{nullptr, nullptr, 0});
   DKS_HIP(hipGetLastError());
   const bool tab = fft2::plane_has(s.grid[0]) && fft2::plane_has(s.grid[1]);
   auto kp = tab ? k_plane_real<true> : k_plane_real<false>;
@@ -752,7 +766,8 @@ void apply_scratch_bytes(const dks_basis *b, int sysi, int nb, size_t bytes[4], 
 
 template <typename T>
 void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
-             double scale, hipStream_t st, Workspace &ws, int ncomp, const int *skip) {
+             double scale, hipStream_t st, Workspace &ws, int ncomp, const int *skip,
+             const int *band_skip) {
   if (nb <= 0) return;
   size_t bytes[4];
   apply_scratch_bytes<T>(b, sysi, nb, bytes, ncomp);
@@ -765,13 +780,13 @@ void apply_h(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, doub
   scr.nlc = ws.nlc.as<double2>();
   scr.nlc2 = ws.nlc2.as<double2>();
   scr.part = ws.part.as<double2>();
-  apply_h_on<T>(b, sysi, X, HX, nb, shift, scale, st, scr, ncomp, skip);
+  apply_h_on<T>(b, sysi, X, HX, nb, shift, scale, st, scr, ncomp, skip, band_skip);
 }
 
 template <typename T>
 void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
                 double scale, hipStream_t st, const ApplyScratch &scr, int ncomp,
-                const int *skip) {
+                const int *skip, const int *band_skip) {
   using C = cplx<T>;
   System &s = *b->sys[sysi];
   Potential &pot = *b->pot[s.vsrc];
@@ -805,6 +820,7 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
     DKS_HIP(hipGetLastError());
   }
   // --- local potential through the grid
+  const BandSkip gskip{skip, band_skip, ncomp == 4 ? 2 : 1};
   const int n3 = s.grid[2];
   C *t1 = static_cast<C *>(scr.t1);
   const int tile = s.tile_z;
@@ -815,7 +831,7 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
   auto kzfwd = ztab ? k_zfft_fwd<T, true> : k_zfft_fwd<T, false>;
   DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_inv.f64" : "k_zfft_inv.f32"), kzinv, gz, dim3(256), smz, st, X, N, s.d_col_off.as<int>(),
                      s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2), t1,
-                     skip);
+                     gskip);
   DKS_HIP(hipGetLastError());
   dim3 gp(n3, ncols);
   size_t smp = plane_lds_bytes<T>(s.grid[0], s.grid[1]);
@@ -830,7 +846,7 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
                (dsmall ? k_plane_direct<T, true> : k_plane_direct<T, false>), gp,
                dim3(dsmall ? kSmallPlaneThreads : kPlaneThreads<T>), smd, st, t1,
                s.ncol, s.d_ctab.as<int>(), s.d_rowflag.as<int>(), s.d_rows.as<int>(), s.nrows,
-               s.d_plan.as<FftPlan>(), Tw<T>(pot, 0), Tw<T>(pot, 1), Vtab<T>(pot), skip);
+               s.d_plan.as<FftPlan>(), Tw<T>(pot, 0), Tw<T>(pot, 1), Vtab<T>(pot), gskip);
   } else {
   const bool small = fits_small && (form == 1 || form == 3);
   const bool wlines = tab && (form == 2 || form == 3);
@@ -840,23 +856,24 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
   const int pthr = small ? kSmallPlaneThreads : kPlaneThreads<T>;
   DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(pthr), smp, st, t1, s.ncol,
              s.d_col_info.as<int4>(), s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(),
-             Tw<T>(pot, 0), Tw<T>(pot, 1), Vtab<T>(pot), skip);
+             Tw<T>(pot, 0), Tw<T>(pot, 1), Vtab<T>(pot), gskip);
   }
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH((sizeof(T) == 8 ? "k_zfft_fwd.f64" : "k_zfft_fwd.f32"), kzfwd, gz, dim3(256), smz, st, t1, HX, N, s.d_col_off.as<int>(),
                      s.d_gmap.as<int2>(), s.ncol, tile, s.d_plan.as<FftPlan>() + 2, Tw<T>(pot, 2),
-                     (T)(1.0 / s.ng), (T)scale, skip);
+                     (T)(1.0 / s.ng), (T)scale, gskip);
   DKS_HIP(hipGetLastError());
 }
 
 template void apply_h<double>(dks_basis *, int, const double2 *, double2 *, int, double, double,
-                              hipStream_t, Workspace &, int, const int *);
+                              hipStream_t, Workspace &, int, const int *, const int *);
 template void apply_h<float>(dks_basis *, int, const float2 *, float2 *, int, double, double,
-                             hipStream_t, Workspace &, int, const int *);
+                             hipStream_t, Workspace &, int, const int *, const int *);
 template void apply_h_on<double>(dks_basis *, int, const double2 *, double2 *, int, double,
-                                 double, hipStream_t, const ApplyScratch &, int, const int *);
+                                 double, hipStream_t, const ApplyScratch &, int, const int *,
+                                 const int *);
 template void apply_h_on<float>(dks_basis *, int, const float2 *, float2 *, int, double, double,
-                                hipStream_t, const ApplyScratch &, int, const int *);
+                                hipStream_t, const ApplyScratch &, int, const int *, const int *);
 template void apply_scratch_bytes<double>(const dks_basis *, int, int, size_t[4], int);
 template void apply_scratch_bytes<float>(const dks_basis *, int, int, size_t[4], int);
 

@@ -81,7 +81,8 @@ struct Solver {
   Blocks<double> b64;
   Blocks<float> b32;
   DevBuf dv, dhv;   // Davidson subspace V and H V (up to davidson_dim x n rows)
-  DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, rinfo, rdinfo, off, idx, forced, rrs, part, part2, tst;
+  DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, lockmask, rinfo, rdinfo, off, idx, forced, rrs, part,
+      part2, tst;
   HostBuf h_rr, h_lam, h_res, h_act, h_vp;
   Workspace ws;   // H.X scratch of this solver's applies
 };
@@ -1075,6 +1076,7 @@ static void graph_reserve(GraphItem &g, Blocks<T> &bk) {
   sv.Wxp.ensure(sizeof(double2) * n * n);
   sv.theta.ensure(sizeof(double) * n);
   sv.norms.ensure(sizeof(double) * n);
+  sv.lockmask.ensure(sizeof(int) * n);
   sv.rinfo.ensure(sizeof(int) * 4);
   sv.rdinfo.ensure(sizeof(double) * 2);
   sv.rrs.ensure(rr_scratch_bytes(nz, n));
@@ -1091,13 +1093,17 @@ static void graph_reserve(GraphItem &g, Blocks<T> &bk) {
 // residual directions made of rounding noise in the basis, whose Gram and
 // projected matrix then lose the H-consistency of the H X recurrence and the
 // iteration breaks down (Ritz values inside the gap below the positive band).
+// `mask[j]` records the decision; the next iteration's grid transforms skip
+// the locked bands (their Y rows are zero).
 template <typename T>
 __global__ void k_graph_lock(cplx<T> *__restrict__ Y, cplx<T> *__restrict__ P,
                              cplx<T> *__restrict__ HP, const double *__restrict__ norm2, int64_t K,
-                             double tol2, const int *__restrict__ skip) {
+                             double tol2, int *__restrict__ mask, const int *__restrict__ skip) {
   if (skip && *skip) return;
   const int j = blockIdx.y;
-  if (!(norm2[j] < tol2)) return;   // active: keeps its directions
+  const bool locked = norm2[j] < tol2;
+  if (blockIdx.x == 0 && threadIdx.x == 0) mask[j] = locked ? 1 : 0;
+  if (!locked) return;   // active: keeps its directions
   const size_t o = (size_t)j * K;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -1115,7 +1121,7 @@ static void graph_lock(GraphItem &g, Blocks<T> &bk, int q, double tol, bool with
   const unsigned gx = (unsigned)std::min<int64_t>(64, (K + 255) / 256);
   DKS_LAUNCH("k_graph_lock", k_graph_lock<T>, dim3(gx, n), dim3(256), 0, g.st, bk.z(q, n),
              with_p ? bk.z(q, 2 * n) : nullptr, with_p ? bk.hz(q, 2 * n) : nullptr,
-             g.sv->norms.as<double>(), K, tol * tol, g.flags + kGfSkip);
+             g.sv->norms.as<double>(), K, tol * tol, g.sv->lockmask.as<int>(), g.flags + kGfSkip);
   DKS_HIP(hipGetLastError());
 }
 
@@ -1131,12 +1137,15 @@ static void graph_iteration(GraphItem &g, Blocks<T> &bk, int p, double tol, int 
   const int *skip = g.flags + kGfSkip;
   hipStream_t st = g.st;
   cplx<T> *Y = bk.z(p, n), *HY = bk.hz(p, n);
+  // the locked bands' Y rows are zero: their grid transforms are skipped
+  const int *lk = sv.lockmask.as<int>();
   if (x.filt) {
-    apply_h<T>(x.b, x.sys, Y, bk.W.template as<cplx<T>>(), n, x.C, 1.0, st, sv.ws, x.ncomp, skip);
+    apply_h<T>(x.b, x.sys, Y, bk.W.template as<cplx<T>>(), n, x.C, 1.0, st, sv.ws, x.ncomp, skip,
+               lk);
     apply_h<T>(x.b, x.sys, bk.W.template as<cplx<T>>(), Y, n, x.C, 1.0 / (x.Om * x.Om), st, sv.ws,
-               x.ncomp, skip);
+               x.ncomp, skip, lk);
   }
-  apply_h<T>(x.b, x.sys, Y, HY, n, 0.0, 1.0, st, sv.ws, x.ncomp, skip);
+  apply_h<T>(x.b, x.sys, Y, HY, n, 0.0, 1.0, st, sv.ws, x.ncomp, skip, lk);
   gemm_ip<T>(bk.z(p, 0), nullptr, nz, bk.z(p, 0), nullptr, nz, bk.hz(p, 0), K, sv.gS.as<double2>(),
              sv.gA.as<double2>(), nz, sv.part, st, /*hermitian=*/true, skip);
   rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, drop_tol, x.floor, nullptr,
