@@ -20,6 +20,12 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 * ``davidson_f``        -- the same filter inside a block Davidson iteration,
                            the other preconditioned solver the paper names for
                            it (Sec. 3 opening, Sec. 5).
+* ``dirac_teter``       -- the preconditioner T of Alg. 1 ("solve T Y = R"):
+                           the Teter-Payne-Allan factor that Sec. 4 employs in
+                           both LOBPCG and LOBPCG-F, applied to a spinor
+                           through the spectral projectors of the free Dirac
+                           block of each planewave (a reading: the paper does
+                           not say how the factor treats the small component).
 
 Readings where the paper is silent (each listed in the design notes):
 * complex data: the transposes of Alg. 1 are conjugate transposes;
@@ -226,6 +232,66 @@ def lobpcgf(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,
     floor = -half_gap if use_filter and half_gap is not None else -math.inf
     return block_rayleigh_ritz(apply_h, X0, n, directions, prepare=prepare, n_iter=n_iter,
                                tol=tol, n_want=n_want, max_history=max_history, floor=floor)
+
+
+def teter_factor(x: np.ndarray) -> np.ndarray:
+    """The Teter-Payne-Allan factor p / (p + 16 x^4), p = 27 + 18x + 12x^2 +
+    8x^3, of the kinetic energy ratio x (1 at x = 0, ~1/(2x) for large x)."""
+    p = 27.0 + 18.0 * x + 12.0 * x * x + 8.0 * x ** 3
+    return p / (p + 16.0 * x ** 4)
+
+
+def dirac_teter(R: np.ndarray, q: np.ndarray, c: float, ncomp: int = 4,
+                E: Optional[np.ndarray] = None, e_min: float = 1e-3) -> np.ndarray:
+    """T R for the K x m residual block R (columns = spinors, components
+    phi_up, phi_dn, chi_up, chi_dn of N planewaves each; K = ncomp N), q the
+    N x 3 wave vectors k+G (Sec. 4: the Teter preconditioner in both solvers;
+    Alg. 1: T Y = R).
+
+    At each planewave the free Dirac block (shifted by -c^2, as the operator)
+    [[0, c s.q], [c s.q, -2c^2]] has the eigenvalues e+ = sqrt(c^4 + c^2 q^2)
+    - c^2 and e- = -sqrt(c^4 + c^2 q^2) - c^2, each twice, with the spectral
+    projectors P+- = (1 +- (M + c^2)/sqrt(c^4 + c^2 q^2)) / 2.  T multiplies
+    P+ R by the Teter factor of e+ / E and P- R by that of |e-| / E, with E per
+    column the mean e+ of the residual's positive part (at least e_min).  T is
+    Hermitian positive definite (for fixed E) and keeps the spinor structure
+    of the free positive and negative states.  For ncomp = 2 (the
+    two-component operator, no small component) it is the plain Teter factor
+    of |k+G|^2 / 2.  ``E`` (optional, length m) fixes the energies.
+    """
+    N = q.shape[0]
+    m = R.shape[1]
+    Rr = R.T.reshape(m, ncomp, N)
+    q2 = np.einsum("ij,ij->i", q, q)
+    if ncomp == 2:
+        ep = 0.5 * q2
+        Pp = Rr
+        Pm = np.zeros_like(Rr)
+        em_abs = ep
+    else:
+        root = np.sqrt(c ** 4 + c * c * q2)
+        ep = c * c * q2 / (root + c * c)          # e+ without cancellation
+        em_abs = root + c * c                      # |e-|
+        qx, qy, qz = q[:, 0], q[:, 1], q[:, 2]
+
+        def sdot(u):                               # (sigma . q) u on a two-spinor
+            a, b = u[:, 0], u[:, 1]
+            return np.stack([qz * a + (qx - 1j * qy) * b, (qx + 1j * qy) * a - qz * b], axis=1)
+
+        phi, chi = Rr[:, :2], Rr[:, 2:]
+        shifted = np.concatenate([c * c * phi + c * sdot(chi), c * sdot(phi) - c * c * chi], axis=1)
+        Pp = 0.5 * (Rr + shifted / root[None, None, :])
+        Pm = Rr - Pp
+    if E is None:
+        w = np.sum(np.abs(Pp) ** 2, axis=1)        # m x N
+        den = w.sum(axis=1)
+        num = w @ ep
+        E = np.where(den > 0, num / np.where(den > 0, den, 1.0), e_min)
+        E = np.maximum(E, e_min)
+    E = np.asarray(E, dtype=float)
+    out = (Pp * teter_factor(ep[None, :] / E[:, None])[:, None, :] +
+           Pm * teter_factor(em_abs[None, :] / E[:, None])[:, None, :])
+    return out.reshape(m, ncomp * N).T
 
 
 def davidson_f(apply_h: Callable, X0: np.ndarray, n: int, C: float, Omega: float,

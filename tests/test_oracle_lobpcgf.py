@@ -184,3 +184,63 @@ def test_davidson_collapses_without_the_filter(tiny):
     filt = lobpcgf.davidson_f(lobpcgf.block_apply(op), X0, 8, C_, Om, n_iter=12, tol=1e-9,
                               use_filter=True)
     assert min(filt.min_ritz_history) > -s.c ** 2
+
+
+@pytest.mark.parametrize("c", [137.036, 3.0])
+def test_dirac_teter_scales_every_free_eigenvector(c):
+    """The preconditioner's spectral form: every eigenvector of the free Dirac
+    block (LAPACK on the oracle's dense kinetic operator, positive and
+    negative band, small cell) is scaled by the Teter factor of its |energy|
+    over E.  At c = 3 the small components are a third of the large ones, so a
+    wrong projector, sign or component order fails."""
+    import dataclasses
+    s = dataclasses.replace(sysgen.tiny_dimer(0), ecut=2.0, c=c)
+    op = dks.DKSOperator(s)
+    w, V = np.linalg.eigh(op.kinetic_dense())
+    E = 0.7
+    got = lobpcgf.dirac_teter(V, op.q, c, E=np.full(V.shape[1], E))
+    want = V * lobpcgf.teter_factor(np.abs(w) / E)[None, :]
+    # LAPACK's eigenvectors carry ~eps ||H|| / (shell gap) ~ 2e-10 of rounding
+    assert np.abs(got - want).max() < 1e-9
+
+
+def test_dirac_teter_is_hermitian_positive_and_teter_in_the_nonrelativistic_limit():
+    """T at fixed E is Hermitian positive definite; for c -> infinity a
+    large-component residual gets the scalar Teter factor of |k+G|^2 / 2E; the
+    per-column energy of a single free positive state is its own energy, so T
+    scales it by the Teter factor at x = 1 (65/81); the two-component form is
+    the plain factor."""
+    import dataclasses
+    s = dataclasses.replace(sysgen.tiny_dimer(0), ecut=2.0)
+    op = dks.DKSOperator(s)
+    N, c = op.N, s.c
+    rng = np.random.default_rng(5)
+    R = rng.standard_normal((4 * N, 3)) + 1j * rng.standard_normal((4 * N, 3))
+    E = np.array([0.4, 1.3, 2.0])
+    TR = lobpcgf.dirac_teter(R, op.q, c, E=E)
+    M = np.stack([lobpcgf.dirac_teter(np.eye(4 * N)[:, j:j + 1], op.q, c, E=E[:1]).ravel()
+                  for j in range(4 * N)], axis=1)
+    assert np.abs(M - M.conj().T).max() < 1e-14
+    assert np.linalg.eigvalsh(0.5 * (M + M.conj().T)).min() > 0
+    assert np.abs(TR[:, 0] - M @ R[:, 0]).max() < 1e-12
+    # nonrelativistic limit on the large component
+    phi = np.zeros((4 * N, 1), dtype=complex)
+    phi[:2 * N, 0] = R[:2 * N, 0]
+    out = lobpcgf.dirac_teter(phi, op.q, 1e5, E=np.array([0.9]))
+    q2 = np.einsum("ij,ij->i", op.q, op.q)
+    k = lobpcgf.teter_factor(0.5 * q2 / 0.9)
+    want = (R[:2 * N, 0].reshape(2, N) * k[None, :]).ravel()
+    assert np.abs(out[:2 * N, 0] - want).max() < 1e-8 * np.abs(want).max()
+    # one free positive state of one planewave (LAPACK on its 4 x 4 block of
+    # the dense kinetic operator): E is its energy, T scales it by 65/81
+    g = int(np.argmax(q2))
+    sel = np.arange(4) * N + g
+    w4, V4 = np.linalg.eigh(op.kinetic_dense()[np.ix_(sel, sel)])
+    v = np.zeros((4 * N, 1), dtype=complex)
+    v[sel, 0] = V4[:, 3]   # the upper (positive) pair
+    assert w4[3] > 0
+    assert np.abs(lobpcgf.dirac_teter(v, op.q, c) - v * 65.0 / 81.0).max() < 1e-12
+    # two components: the scalar factor of |k+G|^2 / 2
+    R2 = R[:2 * N, :1]
+    out2 = lobpcgf.dirac_teter(R2, op.q, c, ncomp=2, E=np.array([0.9]))
+    assert np.abs(out2[:, 0] - (R2[:, 0].reshape(2, N) * k[None, :]).ravel()).max() < 1e-14
