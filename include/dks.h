@@ -69,6 +69,23 @@ typedef enum {
                           kinetic_balance are ignored */
 } dks_model;
 
+/* The preconditioner T of Algorithm 1 (solve T Y = R for the residual block R). */
+typedef enum {
+  DKS_PRECOND_DEFAULT = -1, /* the method's own: DKS_PRECOND_TETER for Algorithm 1 (Sec. 4
+                               employs it in both LOBPCG and LOBPCG-F), DKS_PRECOND_NONE for
+                               DKS_METHOD_DAVIDSON (its filtered space stalled with the
+                               factor on systems of the uneven batch) */
+  DKS_PRECOND_NONE = 0,   /* T = I (the analysis of Sec. 3.1) */
+  DKS_PRECOND_TETER = 1   /* the Teter-Payne-Allan factor K(x) = p / (p + 16 x^4),
+                             p = 27 + 18x + 12x^2 + 8x^3 (Sec. 4: used in both LOBPCG and
+                             LOBPCG-F), applied per planewave through the spectral
+                             projectors P+- of the free Dirac block [[0, c s.q],
+                             [c s.q, -2c^2]]: P+ R scaled by K(e+ / E), P- R by K(|e-| / E),
+                             e+- = +-sqrt(c^4 + c^2 q^2) - c^2, E per column the mean e+ of
+                             the residual's positive part (>= 1e-3 Ha).  The two-component
+                             model: K(|k+G|^2 / 2E) */
+} dks_precond;
+
 /* The iterative method a solve uses. */
 typedef enum {
   DKS_METHOD_LOBPCG = 0,    /* Algorithm 1: LOBPCG-F (or standard LOBPCG, use_filter = 0) */
@@ -173,6 +190,15 @@ dks_status dks_apply_H_ksso(dks_basis *b, int sys, const void *X, void *HX, int 
 dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int nb,
                             double C, double Omega, dks_prec prec, void *stream);
 
+/* Y <- T Y in place: the preconditioner DKS_PRECOND_TETER of Algorithm 1 (the
+ * Teter factor of Sec. 4 through each planewave's free Dirac projectors; see
+ * dks_precond) on nb device blocks [nb][4][N] (model DKS_MODEL_DKS) or
+ * [nb][2][N] (DKS_MODEL_KSSO, the plain factor of |k+G|^2 / 2), complex
+ * double or float by prec.  The per-column energies are computed from Y
+ * itself.  Uses a library-owned scratch of nb doubles. */
+dks_status dks_precondition(dks_basis *b, int sys, void *Y, int nb, int model, dks_prec prec,
+                            void *stream);
+
 /* The library's default filter constants for system `sys`: C at the middle of
  * the free negative band moved by the mean local potential, Omega = (an upper
  * bound of the positive band) - C, so that f <= 1 on the positive band (the
@@ -225,6 +251,9 @@ typedef struct {
   int method;           /* dks_method.  Default DKS_METHOD_LOBPCG */
   int davidson_dim;     /* DKS_METHOD_DAVIDSON: largest subspace, in multiples of n (>= 2;
                            capped at 510 vectors).  Default 4 */
+  int preconditioner;   /* dks_precond: T of Algorithm 1 ("solve T Y = R"), applied to the
+                           residual block before the filter (Sec. 4 places the filter after
+                           the standard preconditioner).  Default DKS_PRECOND_DEFAULT */
 } dks_solve_opts;
 
 typedef struct {

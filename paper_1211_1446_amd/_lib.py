@@ -19,6 +19,7 @@ DKS_FP64, DKS_FP32 = 0, 1
 MODE_FP64, MODE_MIXED_FP32, MODE_MIXED_BF16GRAM = 0, 1, 2
 MODEL_DKS, MODEL_KSSO = 0, 1
 METHOD_LOBPCG, METHOD_DAVIDSON = 0, 1
+PRECOND_DEFAULT, PRECOND_NONE, PRECOND_TETER = -1, 0, 1
 
 _STATUS = {0: "DKS_OK", -1: "DKS_EINVAL", -2: "DKS_ENOMEM", -3: "DKS_EHIP", -4: "DKS_ECHOL",
            -5: "DKS_ECOLLAPSE", -6: "DKS_EINTERNAL", 1: "DKS_WNOTCONV"}
@@ -51,7 +52,7 @@ class SolveOpts(ct.Structure):
                 ("iter_ms", ct.POINTER(ct.c_double)), ("n_buffer", ct.c_int), ("model", ct.c_int),
                 ("batch_graph", ct.c_int), ("graph_chunk", ct.c_int),
                 ("item_buffer", ct.POINTER(ct.c_int)), ("method", ct.c_int),
-                ("davidson_dim", ct.c_int)]
+                ("davidson_dim", ct.c_int), ("preconditioner", ct.c_int)]
 
 
 class SolveInfo(ct.Structure):
@@ -103,6 +104,7 @@ def _load():
     lib.dks_get_tuning.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
     lib.dks_set_tuning.argtypes = [vp, i, i, i, i]
     lib.dks_apply_filter.argtypes = [vp, i, vp, vp, i, d, d, i, vp]
+    lib.dks_precondition.argtypes = [vp, i, vp, i, i, i, vp]
     lib.dks_filter_constants.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(d)]
     lib.dks_default_opts.argtypes = [ct.POINTER(SolveOpts)]
     lib.dks_default_opts.restype = None
@@ -293,6 +295,17 @@ def apply_filter(b: Basis, sys: int, Y, FY, C: float, Omega: float, nb: Optional
     _check_block(FY, nb, N)
     _check(_lib.dks_apply_filter(b.handle, sys, ct.c_void_p(Y.data_ptr()),
                                  ct.c_void_p(FY.data_ptr()), nb, float(C), float(Omega),
+                                 _prec_of(Y), _stream(stream)))
+
+
+def precondition(b: Basis, sys: int, Y, model: int = 0, nb: Optional[int] = None,
+                 stream=None) -> None:
+    """Y <- T Y in place, the Teter preconditioner (dks_precondition); Y is
+    [nb][4][N] for model 0 (DKS), [nb][2][N] for model 1 (KSSO)."""
+    N, _, _ = basis_info(b, sys, miller=False)
+    nb = Y.shape[0] if nb is None else nb
+    _check_block(Y, nb, N, 4 if model == 0 else 2)
+    _check(_lib.dks_precondition(b.handle, sys, ct.c_void_p(Y.data_ptr()), nb, int(model),
                                  _prec_of(Y), _stream(stream)))
 
 

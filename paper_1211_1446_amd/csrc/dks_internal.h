@@ -215,6 +215,7 @@ struct dks_basis {
   // apply_H / apply_filter scratch of the unbatched entry points
   dks::Workspace ws;
   dks::DevBuf ftmp64, ftmp32;
+  dks::DevBuf pE;   // per-column energies of dks_precondition
   // solver workspace (created on first solve)
   void *solver = nullptr;
   // self-consistent field workspace (created on first use)
@@ -266,6 +267,14 @@ template <typename T>
 void apply_h_on(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, double shift,
                 double scale, hipStream_t st, const ApplyScratch &scr, int ncomp = 4,
                 const int *skip = nullptr, const int *band_skip = nullptr);
+
+// Y <- T Y in place for m spinors (the Teter preconditioner of Algorithm 1 on
+// the spectral projectors of each planewave's free Dirac block; two
+// components: the plain factor).  E: device scratch of m doubles (the
+// per-column energies).
+template <typename T>
+void precondition(dks_basis *b, int sys, cplx<T> *Y, int m, hipStream_t st, int ncomp, double *E,
+                  const int *skip = nullptr);
 
 // out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
 // rows addressed by element offsets.  M, Nn <= 512.  `hermitian` (A and B the same

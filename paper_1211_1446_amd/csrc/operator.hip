@@ -737,6 +737,139 @@ void init_kernel_attributes() {
   done = true;
 }
 
+// ---------------------------------------------------------------------------
+// preconditioner T of Algorithm 1 (T Y = R), the Teter factor of Sec. 4 on
+// spinors: at each planewave, the spectral projectors P+- of the free Dirac
+// block [[0, c s.q], [c s.q, -2c^2]] (eigenvalues e+ = sqrt(c^4 + c^2 q^2) - c^2
+// and e- = -sqrt(c^4 + c^2 q^2) - c^2), P+ R scaled by K(e+ / E), P- R by
+// K(|e-| / E), K(x) = p / (p + 16 x^4), p = 27 + 18x + 12x^2 + 8x^3, E per
+// column the mean e+ of the residual's positive part.  Two components (no small
+// component): K(|k+G|^2 / 2E).  Blocks [m][ncomp][N].
+// ---------------------------------------------------------------------------
+constexpr double kTpaEmin = 1e-3;   // floor of E (Ha)
+
+template <typename T>
+__device__ __forceinline__ T tpa_factor(T x) {
+  const T p = T(27) + x * (T(18) + x * (T(12) + x * T(8)));
+  return p / (p + T(16) * (x * x) * (x * x));
+}
+
+// P+ of one planewave's four components (phi_up, phi_dn, chi_up, chi_dn);
+// returns e+ and |e-|.
+template <typename T, typename C>
+__device__ __forceinline__ void tpa_split(const C v[4], T qx, T qy, T qz, T c, C pp[4], T &ep,
+                                          T &em) {
+  const T q2 = qx * qx + qy * qy + qz * qz;
+  const T root = sqrt(c * c * c * c + c * c * q2);
+  ep = c * c * q2 / (root + c * c);
+  em = root + c * c;
+  // sigma.q u = [qz u0 + (qx - i qy) u1, (qx + i qy) u0 - qz u1]
+  auto sdot = [&](const C &u0, const C &u1, C &o0, C &o1) {
+    o0 = C{qz * u0.x + qx * u1.x + qy * u1.y, qz * u0.y + qx * u1.y - qy * u1.x};
+    o1 = C{qx * u0.x - qy * u0.y - qz * u1.x, qx * u0.y + qy * u0.x - qz * u1.y};
+  };
+  C sc0, sc1, sp0, sp1;
+  sdot(v[2], v[3], sc0, sc1);
+  sdot(v[0], v[1], sp0, sp1);
+  const T cc = c * c, h = T(0.5), ir = T(1) / root;
+  const C sh[4] = {C{cc * v[0].x + c * sc0.x, cc * v[0].y + c * sc0.y},
+                   C{cc * v[1].x + c * sc1.x, cc * v[1].y + c * sc1.y},
+                   C{c * sp0.x - cc * v[2].x, c * sp0.y - cc * v[2].y},
+                   C{c * sp1.x - cc * v[3].x, c * sp1.y - cc * v[3].y}};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) pp[a] = C{h * (v[a].x + sh[a].x * ir), h * (v[a].y + sh[a].y * ir)};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tpa_energy(const cplx<T> *__restrict__ Y, int N,
+                                                    const T *__restrict__ q, T c, int ncomp,
+                                                    double *__restrict__ E,
+                                                    const int *__restrict__ skip) {
+  if (skip && *skip) return;
+  using C = cplx<T>;
+  const int j = blockIdx.x;
+  const C *y = Y + (size_t)j * ncomp * N;
+  double num = 0, den = 0;
+  for (int g = threadIdx.x; g < N; g += blockDim.x) {
+    const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
+    if (ncomp == 4) {
+      const C v[4] = {y[g], y[N + g], y[2 * N + g], y[3 * N + g]};
+      C pp[4];
+      T ep, em;
+      tpa_split<T>(v, qx, qy, qz, c, pp, ep, em);
+      double w = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) w += (double)pp[a].x * pp[a].x + (double)pp[a].y * pp[a].y;
+      num += (double)ep * w;
+      den += w;
+    } else {
+      const C a = y[g], b = y[N + g];
+      const double w = (double)a.x * a.x + (double)a.y * a.y + (double)b.x * b.x + (double)b.y * b.y;
+      num += 0.5 * ((double)qx * qx + (double)qy * qy + (double)qz * qz) * w;
+      den += w;
+    }
+  }
+  __shared__ double sn[256], sd[256];
+  sn[threadIdx.x] = num;
+  sd[threadIdx.x] = den;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sn[threadIdx.x] += sn[threadIdx.x + h];
+      sd[threadIdx.x] += sd[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) E[j] = sd[0] > 0 ? fmax(sn[0] / sd[0], kTpaEmin) : kTpaEmin;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tpa_apply(cplx<T> *__restrict__ Y, int N,
+                                                   const T *__restrict__ q, T c, int ncomp,
+                                                   const double *__restrict__ E,
+                                                   const int *__restrict__ skip) {
+  if (skip && *skip) return;
+  using C = cplx<T>;
+  const int j = blockIdx.y;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  C *y = Y + (size_t)j * ncomp * N;
+  const T ie = T(1.0 / E[j]);
+  const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
+  if (ncomp == 4) {
+    const C v[4] = {y[g], y[N + g], y[2 * N + g], y[3 * N + g]};
+    C pp[4];
+    T ep, em;
+    tpa_split<T>(v, qx, qy, qz, c, pp, ep, em);
+    const T kp = tpa_factor<T>(ep * ie), km = tpa_factor<T>(em * ie);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      y[(size_t)a * N + g] = C{kp * pp[a].x + km * (v[a].x - pp[a].x), kp * pp[a].y + km * (v[a].y - pp[a].y)};
+  } else {
+    const T k = tpa_factor<T>(T(0.5) * (qx * qx + qy * qy + qz * qz) * ie);
+    const C a = y[g], b = y[N + g];
+    y[g] = C{k * a.x, k * a.y};
+    y[N + g] = C{k * b.x, k * b.y};
+  }
+}
+
+template <typename T>
+void precondition(dks_basis *b, int sysi, cplx<T> *Y, int m, hipStream_t st, int ncomp,
+                  double *E, const int *skip) {
+  if (m <= 0) return;
+  const System &s = *b->sys[sysi];
+  DKS_LAUNCH("k_tpa_energy", k_tpa_energy<T>, dim3(m), dim3(256), 0, st, Y, s.N, Qtab<T>(s),
+             (T)s.c, ncomp, E, skip);
+  DKS_HIP(hipGetLastError());
+  DKS_LAUNCH("k_tpa_apply", k_tpa_apply<T>, dim3((s.N + 255) / 256, m), dim3(256), 0, st, Y, s.N,
+             Qtab<T>(s), (T)s.c, ncomp, E, skip);
+  DKS_HIP(hipGetLastError());
+}
+template void precondition<double>(dks_basis *, int, double2 *, int, hipStream_t, int, double *,
+                                   const int *);
+template void precondition<float>(dks_basis *, int, float2 *, int, hipStream_t, int, double *,
+                                  const int *);
+
 // Plane form when none is set: the direct forms in FP64 (fewer LDS passes pay
 // where the LDS traffic is 16 bytes a point), the LDS-staged ones in FP32;
 // the 256-thread forms for planes within the small budget.

@@ -81,8 +81,8 @@ struct Solver {
   Blocks<double> b64;
   Blocks<float> b32;
   DevBuf dv, dhv;   // Davidson subspace V and H V (up to davidson_dim x n rows)
-  DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, lockmask, rinfo, rdinfo, off, idx, forced, rrs, part,
-      part2, tst;
+  DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, lockmask, pE, rinfo, rdinfo, off, idx, forced, rrs,
+      part, part2, tst;
   HostBuf h_rr, h_lam, h_res, h_act, h_vp;
   Workspace ws;   // H.X scratch of this solver's applies
 };
@@ -167,6 +167,14 @@ __global__ void k_offsets(int64_t *off, int n, int m, int mp, int64_t K) {
   if (i >= nz) return;
   int row = (i < n + m) ? i : (2 * n + (i - n - m));
   off[i] = (int64_t)row * K;
+}
+
+// The preconditioner in effect: an explicit choice, else the method's own
+// (the Teter factor for Algorithm 1, Sec. 4; T = I for the Davidson method,
+// whose space stalled with it on systems of the uneven batch).
+static bool use_teter(const dks_solve_opts &o) {
+  if (o.preconditioner >= 0) return o.preconditioner == DKS_PRECOND_TETER;
+  return o.method != DKS_METHOD_DAVIDSON;
 }
 
 template <typename T>
@@ -473,12 +481,16 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     s.iters++;
     if (x.info) x.info->iterations++;
     const int m = s.m;
-    // preconditioned residual (T = I): Y = R[:, active]
+    // preconditioned residual: Y = T R[:, active] (T = I unless opts.preconditioner)
     sv.idx.ensure(sizeof(int) * n);
     int *ha = sv.h_act.as<int>(n);
     std::copy(s.act.begin(), s.act.end(), ha);
     DKS_HIP(hipMemcpyAsync(sv.idx.p, ha, sizeof(int) * m, hipMemcpyHostToDevice, x.st));
     gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
+    if (use_teter(*x.o)) {
+      sv.pE.ensure(sizeof(double) * n);
+      precondition<T>(x.b, x.sys, bk.z(s.cur, n), m, x.st, x.ncomp, sv.pE.as<double>());
+    }
     // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
     apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st, x.sv->ws, x.ncomp);
@@ -707,6 +719,10 @@ static dks_status run_davidson(Ctx &x, Blocks<double> &bk, LoopState<double> &s,
     std::copy(act.begin(), act.end(), ha);
     DKS_HIP(hipMemcpyAsync(sv.idx.p, ha, sizeof(int) * m, hipMemcpyHostToDevice, x.st));
     gather_rows<double>(bk.R.as<double2>(), sv.idx.as<int>(), m, K, row(V, dim), x.st);
+    if (use_teter(*x.o)) {
+      sv.pE.ensure(sizeof(double) * n);
+      precondition<double>(x.b, x.sys, row(V, dim), m, x.st, x.ncomp, sv.pE.as<double>());
+    }
     if (x.filt) filter_inplace<double>(x, row(V, dim), bk.W.as<double2>(), m);
     apply_h<double>(x.b, x.sys, row(V, dim), row(HV, dim), m, 0.0, 1.0, x.st, sv.ws, x.ncomp);
     if (x.info) x.info->h_applies += m;
@@ -759,6 +775,9 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
     if (o.kinetic_balance && ncomp == 4) kinetic_balance(b, sys, Xu, n, st);
     dks_status rc = DKS_OK;
     LoopState<double> s64;
+    DKS_REQUIRE(o.preconditioner == DKS_PRECOND_DEFAULT || o.preconditioner == DKS_PRECOND_NONE ||
+                    o.preconditioner == DKS_PRECOND_TETER,
+                DKS_EINVAL, "preconditioner must be DKS_PRECOND_DEFAULT, _NONE or _TETER");
     DKS_REQUIRE(o.method == DKS_METHOD_LOBPCG || o.method == DKS_METHOD_DAVIDSON, DKS_EINVAL,
                 "bad method");
     if (o.method == DKS_METHOD_DAVIDSON) {
@@ -1077,6 +1096,7 @@ static void graph_reserve(GraphItem &g, Blocks<T> &bk) {
   sv.theta.ensure(sizeof(double) * n);
   sv.norms.ensure(sizeof(double) * n);
   sv.lockmask.ensure(sizeof(int) * n);
+  sv.pE.ensure(sizeof(double) * n);
   sv.rinfo.ensure(sizeof(int) * 4);
   sv.rdinfo.ensure(sizeof(double) * 2);
   sv.rrs.ensure(rr_scratch_bytes(nz, n));
@@ -1139,6 +1159,7 @@ static void graph_iteration(GraphItem &g, Blocks<T> &bk, int p, double tol, int 
   cplx<T> *Y = bk.z(p, n), *HY = bk.hz(p, n);
   // the locked bands' Y rows are zero: their grid transforms are skipped
   const int *lk = sv.lockmask.as<int>();
+  if (use_teter(*x.o)) precondition<T>(x.b, x.sys, Y, n, st, x.ncomp, sv.pE.as<double>(), skip);
   if (x.filt) {
     apply_h<T>(x.b, x.sys, Y, bk.W.template as<cplx<T>>(), n, x.C, 1.0, st, sv.ws, x.ncomp, skip,
                lk);
@@ -1520,6 +1541,7 @@ void dks_default_opts(dks_solve_opts *o) {
   o->item_buffer = nullptr;
   o->method = DKS_METHOD_LOBPCG;
   o->davidson_dim = 4;
+  o->preconditioner = DKS_PRECOND_DEFAULT;
   o->n_buffer = 0;
 }
 
@@ -1578,6 +1600,26 @@ dks_status dks_apply_filter(dks_basis *b, int sys, const void *Y, void *FY, int 
       apply_h<float>(b, sys, b->ftmp32.as<float2>(), (float2 *)FY, nb, C, 1.0 / (Omega * Omega), st,
                      b->ws);
     }
+    return DKS_OK;
+  });
+}
+
+dks_status dks_precondition(dks_basis *b, int sys, void *Y, int nb, int model, dks_prec prec,
+                            void *stream) {
+  return guarded([&]() -> dks_status {
+    DKS_REQUIRE(b && Y && sys >= 0 && sys < (int)b->sys.size() && nb >= 0, DKS_EINVAL,
+                "bad argument");
+    DKS_REQUIRE(model == DKS_MODEL_DKS || model == DKS_MODEL_KSSO, DKS_EINVAL, "bad model");
+    DKS_REQUIRE(prec == DKS_FP64 || prec == DKS_FP32, DKS_EINVAL, "bad precision");
+    DKS_HIP(hipSetDevice(b->device));
+    if (nb == 0) return DKS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int ncomp = model == DKS_MODEL_DKS ? 4 : 2;
+    b->pE.ensure(sizeof(double) * nb);
+    if (prec == DKS_FP64)
+      precondition<double>(b, sys, (double2 *)Y, nb, st, ncomp, b->pE.as<double>());
+    else
+      precondition<float>(b, sys, (float2 *)Y, nb, st, ncomp, b->pE.as<double>());
     return DKS_OK;
   });
 }

@@ -214,15 +214,16 @@ def test_system_27_generator_band_count(dev, mode, graph):
     assert np.max(np.abs(lam[:n] - ref[:n])) < 1e-8, np.abs(lam[:n] - ref[:n]).max()
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_graph_form_locks_converged_columns(dev, mode):
+@pytest.mark.parametrize("mode,pc", [(0, 0), (1, 0), (0, 1)])
+def test_graph_form_locks_converged_columns(dev, mode, pc):
     """System 59 of the 64-system uneven batch (N = 4169, 16 bands + 10
     buffer columns, the batch's start block) in the graph form.  Iterating
     every column, the graph form broke down on it at the fifth step (Ritz
     values inside the gap) and the item ended unconverged; with the converged
-    columns locked on the fixed shape it converges inside the graph.
-    Eigenvalues against the dense-oracle golden
-    (tests/golden/uneven_batch_seed0_sys59.json) to 1e-8 Ha."""
+    columns locked on the fixed shape it converges inside the graph (T = I,
+    the configuration that broke down).  With the Teter preconditioner it
+    may leave the graph and finish on the lanes.  Eigenvalues against the
+    dense-oracle golden (tests/golden/uneven_batch_seed0_sys59.json) to 1e-8 Ha."""
     import json
     import os
     import torch
@@ -237,14 +238,16 @@ def test_graph_form_locks_converged_columns(dev, mode):
     X0 = np.zeros((nb, 4, N), dtype=np.complex128)
     X0[:, :2] = sysgen.start_block(mil, s.lattice, s.kpts[0], nb, 159)
     X = torch.from_numpy(X0).to(dev)
-    o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, batch_graph=1)
-    print(f"[system 59 graph] mode={mode} n={n} buffer={buf} N={N}", flush=True)
+    o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, batch_graph=1,
+                        preconditioner=pc)
+    print(f"[system 59 graph] mode={mode} T={pc} n={n} buffer={buf} N={N}", flush=True)
     lams, ress, infos, rc = dk.lobpcgf_solve_batch(b, [0], [nb], [X], o, item_buffer=[buf])
     b.close()
     lam, res, info = np.asarray(lams[0]), np.asarray(ress[0]), infos[0]
     print(f"  iterations {info['iterations']}, graph exit {info['graph_exit']}, "
           f"max|r| {info['max_resnorm']:.2e}", flush=True)
     assert rc == 0 and info["converged"] == 1, info
-    assert info["graph_exit"] == 1, info
+    if pc == 0:
+        assert info["graph_exit"] == 1, info
     assert np.max(res[:n]) < 1e-8
     assert np.max(np.abs(lam[:n] - ref[:n])) < 1e-8, np.abs(lam[:n] - ref[:n]).max()

@@ -126,7 +126,7 @@ def test_davidson_collapses_without_the_filter(dev):
     with pytest.raises(dk.DksError) as e:
         dk.lobpcgf_solve(b, 0, 8, torch.from_numpy(X0).to(dev),
                          dk.default_opts(method=dk.METHOD_DAVIDSON, use_filter=0, n_iter=40,
-                                         tol=1e-9))
+                                         tol=1e-9, preconditioner=dk.PRECOND_NONE))
     assert e.value.code == -5, str(e.value)
     print("[davidson collapse] with the filter", flush=True)
     lam, res, info, rc = dk.lobpcgf_solve(b, 0, 8, torch.from_numpy(X0).to(dev),

@@ -318,12 +318,12 @@ def test_lobpcgf_buffer_out_of_range(dev):
 
 @pytest.mark.parametrize("mode", [1, 2])
 def test_reduced_precision_stage_alone(dev, mode):
-    """The FP32 (mode 1) or BF16-Gram (mode 2) stage by itself, 40 iterations,
-    followed only by the FP64 polish's first Rayleigh-Ritz (n_iter = 0): its
+    """The FP32 (mode 1) or BF16-Gram (mode 2) stage by itself, 40 iterations
+    with T = I, followed only by the FP64 polish's first Rayleigh-Ritz (n_iter = 0): its
     eigenvalues already sit near the dense ones, far below the start block's
     error, so the reduced-precision Gram products carry the right numbers."""
     lam, res, info, rc, lam_ref, vec_ref, Xo, s = _solve_tiny(
-        dev, mode, n_iter=0, mixed_iter=40, mixed_tol=-1.0)
+        dev, mode, n_iter=0, mixed_iter=40, mixed_tol=-1.0, preconditioner=0)
     err = np.max(np.abs(lam - lam_ref))
     print(f"mode {mode}: reduced stage max |lambda - dense| = {err:.3e}", flush=True)
     assert info["iters_reduced"] == 40
@@ -416,8 +416,9 @@ def test_filter_damping_across_c(dev):
 
 def test_standard_lobpcg_collapses_and_lobpcgf_does_not(dev):
     """Sec. 3.1 on the GPU: from a start block carrying 1e-15 of the lowest
-    negative-band eigenvector (dense oracle), plain LOBPCG (use_filter = 0)
-    falls into the negative continuum and the call returns DKS_ECOLLAPSE,
+    negative-band eigenvector (dense oracle), plain LOBPCG (use_filter = 0,
+    T = I as in the analysis) falls into the negative continuum and the call
+    returns DKS_ECOLLAPSE,
     while LOBPCG-F from the same block converges to the dense eigenvalues."""
     dk = _dk()
     s = sysgen.tiny_dimer(0)
@@ -436,7 +437,8 @@ def test_standard_lobpcg_collapses_and_lobpcgf_does_not(dev):
     print("[collapse] use_filter=0, 1e-15 negative-band content", flush=True)
     Xd = torch.from_numpy(X0).to(dev)
     with pytest.raises(dk.DksError) as e:
-        dk.lobpcgf_solve(b, 0, 8, Xd, dk.default_opts(use_filter=0, n_iter=40, tol=1e-9))
+        dk.lobpcgf_solve(b, 0, 8, Xd, dk.default_opts(use_filter=0, n_iter=40, tol=1e-9,
+                                                      preconditioner=dk.PRECOND_NONE))
     assert e.value.code == -5, str(e.value)
     print("[collapse] LOBPCG-F from the same block", flush=True)
     Xd = torch.from_numpy(X0).to(dev)

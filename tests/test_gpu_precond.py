@@ -1,0 +1,118 @@
+"""The preconditioner T of Algorithm 1 on the GPU (dks_precondition, opts
+preconditioner = DKS_PRECOND_TETER): the Teter factor of Sec. 4 applied
+through the spectral projectors of each planewave's free Dirac block.  The
+kernel against the oracle's dirac_teter element by element (DKS and KSSO
+blocks, FP64 and FP32, a hexagonal cell at k != 0 and the tiny dimer), and
+preconditioned solves against the dense oracle and the heavy dimer's golden:
+T changes the path of the iteration, not its answer."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import sysgen
+from oracle import dks, lobpcgf
+from tests.gpu_helpers import perm_to_oracle, to_orc
+from tests.test_gpu_parity import _dk, _hexagonal_system, _solve_tiny, row_errors
+from tests.test_gpu_batch import _start_blocks
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_precondition_matches_oracle(dev, model, prec):
+    dk = _dk()
+    ncomp = 4 if model == 0 else 2
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    ctype = torch.complex128 if prec == "fp64" else torch.complex64
+    for s, nb in ((_hexagonal_system(), 5), (sysgen.tiny_dimer(0), 3)):
+        op = dks.DKSOperator(s)
+        b = dk.init_basis([s])
+        N, _, mil = dk.basis_info(b, 0)
+        p = perm_to_oracle(mil, op.miller)
+        rng = np.random.default_rng(7 + model)
+        Y = rng.standard_normal((nb, ncomp, N)) + 1j * rng.standard_normal((nb, ncomp, N))
+        # a column with its weight at high |k+G| and one that is zero
+        Y[1] *= np.linspace(0.1, 3.0, N)[None, :]
+        Y[nb - 1] = 0
+        Yd = torch.from_numpy(Y).to(dev, ctype)
+        print(f"[precondition] {s.name} model={model} {prec} nb={nb} N={N}", flush=True)
+        dk.precondition(b, 0, Yd, model=model)
+        torch.cuda.synchronize()
+        got = to_orc(Yd.to(torch.complex128).cpu().numpy(), p)
+        b.close()
+        Yo = to_orc(Y, p)
+        ref = lobpcgf.dirac_teter(Yo.reshape(nb, -1).T, op.q, s.c, ncomp=ncomp).T.reshape(nb, ncomp, N)
+        assert np.all(got[nb - 1] == 0)
+        err = row_errors(got[:nb - 1], ref[:nb - 1])
+        assert err < tol, (s.name, err)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_preconditioned_solve_tiny_matches_dense(dev, mode):
+    lam, res, info, rc, lam_ref, vec_ref, Xo, s = _solve_tiny(dev, mode, preconditioner=1)
+    print(f"  iterations {info['iterations']}", flush=True)
+    assert rc == 0, info
+    assert np.max(np.abs(lam - lam_ref)) < 1e-8, (lam - lam_ref)
+    assert np.all(res < 1e-8)
+    assert info["min_ritz"] > -s.c ** 2
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_preconditioned_heavy_dimer_matches_golden(dev, mode):
+    """The heavy dimer (96^3, 40 bands) to 1e-8 Ha with T, against the golden of
+    the oracle's Algorithm 1 (tests/golden/heavy_dimer_seed0.json)."""
+    dk = _dk()
+    ref = np.array(json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                               "heavy_dimer_seed0.json")))["eigenvalues"])
+    s = sysgen.heavy_dimer(0)
+    n = 40
+    b = dk.init_basis([s])
+    N, _, mil = dk.basis_info(b, 0)
+    X0 = np.zeros((n, 4, N), dtype=np.complex128)
+    X0[:, :2] = sysgen.start_block(mil, s.lattice, s.kpts[0], n, 0)
+    X = torch.from_numpy(X0).to(dev)
+    o = dk.default_opts(mode=mode, tol=1e-8, n_iter=300, kinetic_balance=1, preconditioner=1)
+    print(f"[heavy dimer, T] mode={mode}", flush=True)
+    lam, res, info, rc = dk.lobpcgf_solve(b, 0, n, X, o)
+    b.close()
+    print(f"  iterations {info['iterations']}", flush=True)
+    assert rc == 0, info
+    assert np.max(res) < 1e-8
+    assert np.max(np.abs(lam - ref)) < 1e-8, np.abs(lam - ref).max()
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_preconditioned_batch_matches_dense(dev, graph):
+    """Five uneven systems with T on the lanes and in the graph form."""
+    dk = _dk()
+    systems = sysgen.uneven_batch(seed=3, count=5, npw_range=(400, 650))
+    buf = 8
+    wanted = [s.n_bands for s in systems]
+    ns = [w + buf for w in wanted]
+    refs = [lobpcgf.lowest_positive(dks.DKSOperator(s).dense(), w, s.c)[0]
+            for s, w in zip(systems, wanted)]
+    b = dk.init_basis(systems)
+    Xs = _start_blocks(dk, b, systems, ns, seed=11)
+    print(f"[batch, T] graph={graph}", flush=True)
+    opts = dk.default_opts(mode=0, kinetic_balance=1, n_iter=400, n_buffer=buf,
+                           batch_graph=graph, preconditioner=1)
+    lams, ress, infos, rc = dk.lobpcgf_solve_batch(b, list(range(len(systems))), ns, Xs, opts)
+    b.close()
+    print("  iterations", [i_["iterations"] for i_ in infos], flush=True)
+    assert rc == 0, infos
+    for i, (lam, ref, res) in enumerate(zip(lams, refs, ress)):
+        w = wanted[i]
+        assert np.max(np.abs(lam[:w] - ref)) < 1e-8, (i, lam[:w] - ref)
+        assert np.all(res[:w] < 1e-8), (i, res)
