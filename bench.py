@@ -152,15 +152,15 @@ def main():
         X4s = np.zeros((nscf, 4, N), dtype=np.complex128)
         X4s[:, :2] = phis
         scf_rec = {"workload": "heavy dimer, 24 electrons in the 40 lowest bands + 8 buffer at "
-                               "5000 K, 10 eigensolver iterations per SCF step, Anderson + Kerker, "
-                               "tol 1e-8", "models": {}}
+                               "5000 K, 5 eigensolver iterations (Teter-preconditioned) per SCF "
+                               "step, Anderson + Kerker, tol 1e-8", "models": {}}
         for tag, model, start in (("dks", dk.MODEL_DKS, X4s), ("ksso", dk.MODEL_KSSO, phis)):
             dk.set_local_potential(b, 0, v_ext)
             Xs = torch.from_numpy(np.ascontiguousarray(start)).to(dev)
             eo = dk.default_opts(model=model, kinetic_balance=1 if model == dk.MODEL_DKS else 0,
                                  use_filter=1 if model == dk.MODEL_DKS else 0, tol=1e-8, n_buffer=8,
                                  n_iter=400)
-            so = dk.scf_default_opts(n_electrons=24.0, tol=1e-8, max_scf=120, eig_iters=10)
+            so = dk.scf_default_opts(n_electrons=24.0, tol=1e-8, max_scf=120, eig_iters=5)
             torch.cuda.synchronize()
             t = time.perf_counter()
             _, occ_, info_, rc_ = dk.scf(b, 0, nscf, Xs, so, eo)
