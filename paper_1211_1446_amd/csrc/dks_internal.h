@@ -215,7 +215,7 @@ struct dks_basis {
   // apply_H / apply_filter scratch of the unbatched entry points
   dks::Workspace ws;
   dks::DevBuf ftmp64, ftmp32;
-  dks::DevBuf pE;   // per-column energies of dks_precondition
+  dks::DevBuf pE;   // partial sums of the per-column energies of dks_precondition
   // solver workspace (created on first solve)
   void *solver = nullptr;
   // self-consistent field workspace (created on first use)
@@ -270,11 +270,13 @@ void apply_h_on(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, do
 
 // Y <- T Y in place for m spinors (the Teter preconditioner of Algorithm 1 on
 // the spectral projectors of each planewave's free Dirac block; two
-// components: the plain factor).  E: device scratch of m doubles (the
-// per-column energies).
+// components: the plain factor).  part: device scratch of
+// m * kTpaMaxBlocks double2 (partial sums of the per-column energies).
+constexpr int kTpaMaxBlocks = 64;
+int tpa_blocks(int N);
 template <typename T>
-void precondition(dks_basis *b, int sys, cplx<T> *Y, int m, hipStream_t st, int ncomp, double *E,
-                  const int *skip = nullptr);
+void precondition(dks_basis *b, int sys, cplx<T> *Y, int m, hipStream_t st, int ncomp,
+                  double2 *part, const int *skip = nullptr);
 
 // out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
 // rows addressed by element offsets.  M, Nn <= 512.  `hermitian` (A and B the same

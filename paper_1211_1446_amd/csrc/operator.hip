@@ -780,17 +780,21 @@ __device__ __forceinline__ void tpa_split(const C v[4], T qx, T qy, T qz, T c, C
   for (int a = 0; a < 4; ++a) pp[a] = C{h * (v[a].x + sh[a].x * ir), h * (v[a].y + sh[a].y * ir)};
 }
 
+// Partial sums of E: block (x, j) takes planewaves x*256 + t, step
+// gridDim.x*256, of column j and writes (sum e+ |P+ y|^2, sum |P+ y|^2) to
+// part[j * gridDim.x + x]; k_tpa_apply adds the partials of its column in a
+// fixed order (the result does not depend on scheduling).
 template <typename T>
 __global__ void __launch_bounds__(256) k_tpa_energy(const cplx<T> *__restrict__ Y, int N,
                                                     const T *__restrict__ q, T c, int ncomp,
-                                                    double *__restrict__ E,
+                                                    double2 *__restrict__ part,
                                                     const int *__restrict__ skip) {
   if (skip && *skip) return;
   using C = cplx<T>;
-  const int j = blockIdx.x;
+  const int j = blockIdx.y;
   const C *y = Y + (size_t)j * ncomp * N;
   double num = 0, den = 0;
-  for (int g = threadIdx.x; g < N; g += blockDim.x) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
     const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
     if (ncomp == 4) {
       const C v[4] = {y[g], y[N + g], y[2 * N + g], y[3 * N + g]};
@@ -809,32 +813,49 @@ __global__ void __launch_bounds__(256) k_tpa_energy(const cplx<T> *__restrict__ 
       den += w;
     }
   }
-  __shared__ double sn[256], sd[256];
-  sn[threadIdx.x] = num;
-  sd[threadIdx.x] = den;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) {
-      sn[threadIdx.x] += sn[threadIdx.x + h];
-      sd[threadIdx.x] += sd[threadIdx.x + h];
-    }
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    num += __shfl_xor(num, o, 64);
+    den += __shfl_xor(den, o, 64);
   }
-  if (threadIdx.x == 0) E[j] = sd[0] > 0 ? fmax(sn[0] / sd[0], kTpaEmin) : kTpaEmin;
+  __shared__ double sn[4], sd[4];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sn[wv] = num;
+    sd[wv] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[(size_t)j * gridDim.x + blockIdx.x] = make_double2(sn[0] + sn[1] + sn[2] + sn[3],
+                                                            sd[0] + sd[1] + sd[2] + sd[3]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_tpa_apply(cplx<T> *__restrict__ Y, int N,
                                                    const T *__restrict__ q, T c, int ncomp,
-                                                   const double *__restrict__ E,
+                                                   const double2 *__restrict__ part, int nblk,
                                                    const int *__restrict__ skip) {
   if (skip && *skip) return;
   using C = cplx<T>;
   const int j = blockIdx.y;
+  __shared__ double sE;
+  if (threadIdx.x < 64) {
+    double num = 0, den = 0;
+    for (int k = threadIdx.x; k < nblk; k += 64) {
+      const double2 pk = part[(size_t)j * nblk + k];
+      num += pk.x;
+      den += pk.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      num += __shfl_xor(num, o, 64);
+      den += __shfl_xor(den, o, 64);
+    }
+    if (threadIdx.x == 0) sE = den > 0 ? fmax(num / den, kTpaEmin) : kTpaEmin;
+  }
+  __syncthreads();
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   C *y = Y + (size_t)j * ncomp * N;
-  const T ie = T(1.0 / E[j]);
+  const T ie = T(1.0 / sE);
   const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
   if (ncomp == 4) {
     const C v[4] = {y[g], y[N + g], y[2 * N + g], y[3 * N + g]};
@@ -853,21 +874,24 @@ __global__ void __launch_bounds__(256) k_tpa_apply(cplx<T> *__restrict__ Y, int 
   }
 }
 
+int tpa_blocks(int N) { return std::min(kTpaMaxBlocks, std::max(1, (N + 2047) / 2048)); }
+
 template <typename T>
 void precondition(dks_basis *b, int sysi, cplx<T> *Y, int m, hipStream_t st, int ncomp,
-                  double *E, const int *skip) {
+                  double2 *part, const int *skip) {
   if (m <= 0) return;
   const System &s = *b->sys[sysi];
-  DKS_LAUNCH("k_tpa_energy", k_tpa_energy<T>, dim3(m), dim3(256), 0, st, Y, s.N, Qtab<T>(s),
-             (T)s.c, ncomp, E, skip);
+  const int nblk = tpa_blocks(s.N);
+  DKS_LAUNCH("k_tpa_energy", k_tpa_energy<T>, dim3(nblk, m), dim3(256), 0, st, Y, s.N, Qtab<T>(s),
+             (T)s.c, ncomp, part, skip);
   DKS_HIP(hipGetLastError());
   DKS_LAUNCH("k_tpa_apply", k_tpa_apply<T>, dim3((s.N + 255) / 256, m), dim3(256), 0, st, Y, s.N,
-             Qtab<T>(s), (T)s.c, ncomp, E, skip);
+             Qtab<T>(s), (T)s.c, ncomp, part, nblk, skip);
   DKS_HIP(hipGetLastError());
 }
-template void precondition<double>(dks_basis *, int, double2 *, int, hipStream_t, int, double *,
+template void precondition<double>(dks_basis *, int, double2 *, int, hipStream_t, int, double2 *,
                                    const int *);
-template void precondition<float>(dks_basis *, int, float2 *, int, hipStream_t, int, double *,
+template void precondition<float>(dks_basis *, int, float2 *, int, hipStream_t, int, double2 *,
                                   const int *);
 
 // Plane form when none is set: the direct forms in FP64 (fewer LDS passes pay

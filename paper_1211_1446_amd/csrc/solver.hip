@@ -488,8 +488,8 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     DKS_HIP(hipMemcpyAsync(sv.idx.p, ha, sizeof(int) * m, hipMemcpyHostToDevice, x.st));
     gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
     if (use_teter(*x.o)) {
-      sv.pE.ensure(sizeof(double) * n);
-      precondition<T>(x.b, x.sys, bk.z(s.cur, n), m, x.st, x.ncomp, sv.pE.as<double>());
+      sv.pE.ensure(sizeof(double2) * n * kTpaMaxBlocks);
+      precondition<T>(x.b, x.sys, bk.z(s.cur, n), m, x.st, x.ncomp, sv.pE.as<double2>());
     }
     // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
@@ -720,8 +720,8 @@ static dks_status run_davidson(Ctx &x, Blocks<double> &bk, LoopState<double> &s,
     DKS_HIP(hipMemcpyAsync(sv.idx.p, ha, sizeof(int) * m, hipMemcpyHostToDevice, x.st));
     gather_rows<double>(bk.R.as<double2>(), sv.idx.as<int>(), m, K, row(V, dim), x.st);
     if (use_teter(*x.o)) {
-      sv.pE.ensure(sizeof(double) * n);
-      precondition<double>(x.b, x.sys, row(V, dim), m, x.st, x.ncomp, sv.pE.as<double>());
+      sv.pE.ensure(sizeof(double2) * n * kTpaMaxBlocks);
+      precondition<double>(x.b, x.sys, row(V, dim), m, x.st, x.ncomp, sv.pE.as<double2>());
     }
     if (x.filt) filter_inplace<double>(x, row(V, dim), bk.W.as<double2>(), m);
     apply_h<double>(x.b, x.sys, row(V, dim), row(HV, dim), m, 0.0, 1.0, x.st, sv.ws, x.ncomp);
@@ -1096,7 +1096,7 @@ static void graph_reserve(GraphItem &g, Blocks<T> &bk) {
   sv.theta.ensure(sizeof(double) * n);
   sv.norms.ensure(sizeof(double) * n);
   sv.lockmask.ensure(sizeof(int) * n);
-  sv.pE.ensure(sizeof(double) * n);
+  sv.pE.ensure(sizeof(double2) * n * kTpaMaxBlocks);
   sv.rinfo.ensure(sizeof(int) * 4);
   sv.rdinfo.ensure(sizeof(double) * 2);
   sv.rrs.ensure(rr_scratch_bytes(nz, n));
@@ -1159,7 +1159,7 @@ static void graph_iteration(GraphItem &g, Blocks<T> &bk, int p, double tol, int 
   cplx<T> *Y = bk.z(p, n), *HY = bk.hz(p, n);
   // the locked bands' Y rows are zero: their grid transforms are skipped
   const int *lk = sv.lockmask.as<int>();
-  if (use_teter(*x.o)) precondition<T>(x.b, x.sys, Y, n, st, x.ncomp, sv.pE.as<double>(), skip);
+  if (use_teter(*x.o)) precondition<T>(x.b, x.sys, Y, n, st, x.ncomp, sv.pE.as<double2>(), skip);
   if (x.filt) {
     apply_h<T>(x.b, x.sys, Y, bk.W.template as<cplx<T>>(), n, x.C, 1.0, st, sv.ws, x.ncomp, skip,
                lk);
@@ -1615,11 +1615,11 @@ dks_status dks_precondition(dks_basis *b, int sys, void *Y, int nb, int model, d
     if (nb == 0) return DKS_OK;
     hipStream_t st = (hipStream_t)stream;
     const int ncomp = model == DKS_MODEL_DKS ? 4 : 2;
-    b->pE.ensure(sizeof(double) * nb);
+    b->pE.ensure(sizeof(double2) * nb * kTpaMaxBlocks);
     if (prec == DKS_FP64)
-      precondition<double>(b, sys, (double2 *)Y, nb, st, ncomp, b->pE.as<double>());
+      precondition<double>(b, sys, (double2 *)Y, nb, st, ncomp, b->pE.as<double2>());
     else
-      precondition<float>(b, sys, (float2 *)Y, nb, st, ncomp, b->pE.as<double>());
+      precondition<float>(b, sys, (float2 *)Y, nb, st, ncomp, b->pE.as<double2>());
     return DKS_OK;
   });
 }
