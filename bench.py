@@ -536,7 +536,10 @@ def main():
         nkL = sL.kpts.shape[0]
         gL = golden_of("layered_crystal_seed0_k0.json")
         nwL = sL.n_bands
-        bufL = 8
+        # 40 buffer columns (n_Z = 480): 598 k-point iterations instead of 2 403 with 8, and
+        # the shortest time to solution of 8, 16, 24 and 40 (each k-point's Rayleigh-Ritz
+        # grows with n_Z, but the 16 run concurrently)
+        bufL = 40
         nL = nwL + bufL
         XsL, npwL = [], []
         for i in range(nkL):
