@@ -386,6 +386,13 @@ __device__ __forceinline__ void fwd_step1_rows_out(const typename CT<T>::c *pl, 
   X(200, 10, 20) X(240, 15, 16) X(256, 16, 16) X(288, 16, 18) X(320, 16, 20) X(360, 18, 20) \
   X(400, 20, 20)
 
+// The plane lengths whose two factors are both at most 8: a kernel that
+// dispatches only these holds the registers of its own codelets, not of the
+// 9- to 16-point ones (fewer VGPRs, more waves per SIMD).
+#define DKS_FFT_PLANE_LITE_CASES(X)                                                          \
+  X(8, 1, 8) X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(25, 5, 5) X(30, 5, 6) X(32, 4, 8)        \
+  X(36, 6, 6) X(40, 5, 8) X(48, 6, 8) X(64, 8, 8)
+
 #define DKS_FFT_CASE(N_, A_, B_)     \
   case N_:                           \
     f.template operator()<A_, B_>(); \
@@ -396,6 +403,15 @@ __device__ __forceinline__ void fwd_step1_rows_out(const typename CT<T>::c *pl, 
 __host__ __device__ constexpr bool plane_has(int n) {
   switch (n) {
     DKS_FFT_PLANE_CASES(DKS_FFT_HAS)
+    return true;
+    default:
+      return false;
+  }
+}
+// whether plane axis length n is one of the lite lengths (host and device)
+__host__ __device__ constexpr bool plane_lite_has(int n) {
+  switch (n) {
+    DKS_FFT_PLANE_LITE_CASES(DKS_FFT_HAS)
     return true;
     default:
       return false;
@@ -416,6 +432,14 @@ template <typename F>
 __device__ __forceinline__ bool dispatch_plane(int n, F &&f) {
   switch (n) {
     DKS_FFT_PLANE_CASES(DKS_FFT_CASE)
+    default:
+      return false;
+  }
+}
+template <typename F>
+__device__ __forceinline__ bool dispatch_plane_lite(int n, F &&f) {
+  switch (n) {
+    DKS_FFT_PLANE_LITE_CASES(DKS_FFT_CASE)
     default:
       return false;
   }

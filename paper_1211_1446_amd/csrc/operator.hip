@@ -216,7 +216,9 @@ size_t plane_lds_bytes(int n1, int n2) {
 // and registers stay out of the table kernel.
 // kWaveLines: the line passes of the plane are split between waves by whole
 // lines instead of between all threads by tasks (fewer workgroup barriers).
-template <typename T, bool kTab, bool kSmall = false, bool kWaveLines = false>
+// kLite: both axes have lite lengths (fft2::plane_lite_has); only their
+// codelets are compiled in (fewer registers, more waves per SIMD).
+template <typename T, bool kTab, bool kSmall = false, bool kWaveLines = false, bool kLite = false>
 __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plane(typename CT<T>::c *__restrict__ T1, int ncol,
                                                 const int4 *__restrict__ col_info,
                                                 const int *__restrict__ rows, int nrows,
@@ -246,6 +248,12 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
       for (int e = threadIdx.x; e < n1; e += blockDim.x) twx_s[e] = twx[e];
       for (int e = threadIdx.x; e < n2; e += blockDim.x) twy_s[e] = twy[e];
     }
+  };
+  auto dispatch = [](int n, auto &&f) {
+    if constexpr (kLite)
+      return fft2::dispatch_plane_lite(n, f);
+    else
+      return fft2::dispatch_plane(n, f);
   };
   C *t = T1 + ((size_t)cc * n3 + z) * ncol;
   // The column values are fetched kPre per thread at a time, all loads in
@@ -292,13 +300,13 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
       __builtin_amdgcn_wave_barrier();
     };
     const fft2::Walk Wr = fft2::walk(r1 - r0, lane, 64), Wc = fft2::walk(c1 - c0, lane, 64);
-    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+    dispatch(n2, [&]<int A, int B>() {
       fft2::inv_step1<A, B, T>(pl, Wr, Lyw, ty);
       wave_sync();
       fft2::inv_step2<A, B, T>(pl, Wr, Lyw);
     });
     __syncthreads();
-    fft2::dispatch_plane(n1, [&]<int A, int B>() {
+    dispatch(n1, [&]<int A, int B>() {
       fft2::inv_step1<A, B, T>(pl + c0, Wc, Lx, tx);
       wave_sync();
       fft2::inv2_mul_fwd2<A, B, T>(pl + c0, Wc, Lx, tx, v + c0, 1, n2);
@@ -306,7 +314,7 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
       fft2::fwd_step1<A, B, T>(pl + c0, Wc, Lx);
     });
     __syncthreads();
-    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+    dispatch(n2, [&]<int A, int B>() {
       fft2::fwd_step2<A, B, T>(pl, Wr, Lyw, ty);
       wave_sync();
       fft2::fwd_step1<A, B, T>(pl, Wr, Lyw);
@@ -316,7 +324,7 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   // inverse along a2
   const fft2::Walk Wr = fft2::walk(nrows), Wc = fft2::walk(n2);
   if constexpr (kTab) {
-    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+    dispatch(n2, [&]<int A, int B>() {
       fft2::inv_step1<A, B, T>(pl, Wr, Ly, ty);
       __syncthreads();
       fft2::inv_step2<A, B, T>(pl, Wr, Ly);
@@ -327,7 +335,7 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   __syncthreads();
   // inverse along a1, x V, forward along a1
   if constexpr (kTab) {
-    fft2::dispatch_plane(n1, [&]<int A, int B>() {
+    dispatch(n1, [&]<int A, int B>() {
       fft2::inv_step1<A, B, T>(pl, Wc, Lx, tx);
       __syncthreads();
       fft2::inv2_mul_fwd2<A, B, T>(pl, Wc, Lx, tx, v, 1, n2);
@@ -348,7 +356,7 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   __syncthreads();
   // forward along a2
   if constexpr (kTab) {
-    fft2::dispatch_plane(n2, [&]<int A, int B>() {
+    dispatch(n2, [&]<int A, int B>() {
       fft2::fwd_step2<A, B, T>(pl, Wr, Ly, ty);
       __syncthreads();
       fft2::fwd_step1<A, B, T>(pl, Wr, Ly);
@@ -389,8 +397,9 @@ size_t plane_direct_lds_bytes(int n1, int n2) {
   return plane_lds_bytes<T>(n1, n2) + sizeof(int) * (size_t)((n1 + 3) & ~3);
 }
 // kSmall: 256-thread workgroups for planes within the small LDS budget, as
-// for k_plane (plane form 5).
-template <typename T, bool kSmall>
+// for k_plane (plane form 5).  kLite: both axes have lite lengths (factors at
+// most 10); only those codelets are compiled in.
+template <typename T, bool kSmall, bool kLite = false>
 __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plane_direct(
     typename CT<T>::c *__restrict__ T1, int ncol, const int *__restrict__ ctab,
     const int *__restrict__ rowflag, const int *__restrict__ rows, int nrows,
@@ -420,6 +429,12 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
       for (int e = threadIdx.x; e < n2; e += blockDim.x) twy_s[e] = twy[e];
     }
   };
+  auto dispatch = [](int n, auto &&f) {
+    if constexpr (kLite)
+      return fft2::dispatch_plane_lite(n, f);
+    else
+      return fft2::dispatch_plane(n, f);
+  };
   const C *tx = kPlaneTwLds<T> ? twx_s : twx;
   const C *ty = kPlaneTwLds<T> ? twy_s : twy;
   C *t = T1 + ((size_t)cc * n3 + z) * ncol;
@@ -429,7 +444,7 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   const fft2::Walk Wr = fft2::walk(nrows), Wc = fft2::walk(n2);
   // inverse along a2 (step 1 from the columns, global twiddles: the LDS copy
   // is not complete before the first barrier)
-  fft2::dispatch_plane(n2, [&]<int A, int B>() {
+  dispatch(n2, [&]<int A, int B>() {
     fft2::inv_step1_rows_in<A, B, T>(pl, ld, rows, nrows, n2, ctab, t, twy);
     stage();
     __syncthreads();
@@ -437,7 +452,7 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   });
   __syncthreads();
   // inverse along a1 (sphere rows in), x V, forward along a1 (sphere rows out)
-  fft2::dispatch_plane(n1, [&]<int A, int B>() {
+  dispatch(n1, [&]<int A, int B>() {
     fft2::inv_step1_keep<A, B, T>(pl, Wc, Lx, tx, keep_s);
     __syncthreads();
     fft2::inv2_mul_fwd2<A, B, T>(pl, Wc, Lx, tx, v, 1, n2);
@@ -446,7 +461,7 @@ __global__ void __launch_bounds__((kPlaneThr<T, kSmall>), kPlaneWaves<T>) k_plan
   });
   __syncthreads();
   // forward along a2 (step 1' to the columns)
-  fft2::dispatch_plane(n2, [&]<int A, int B>() {
+  dispatch(n2, [&]<int A, int B>() {
     fft2::fwd_step2<A, B, T>(pl, Wr, Ly, ty);
     __syncthreads();
     fft2::fwd_step1_rows_out<A, B, T>(pl, ld, rows_s, nrows, n2, ctab, t);
@@ -710,6 +725,16 @@ void init_kernel_attributes() {
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  for (const void *f : {(const void *)k_plane<double, true, false, false, true>,
+                        (const void *)k_plane<float, true, false, false, true>,
+                        (const void *)k_plane<double, true, false, true, true>,
+                        (const void *)k_plane<float, true, false, true, true>})
+    DKS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  for (const void *f : {(const void *)k_plane<double, true, true, false, true>,
+                        (const void *)k_plane<float, true, true, false, true>,
+                        (const void *)k_plane<double, true, true, true, true>,
+                        (const void *)k_plane<float, true, true, true, true>})
+    DKS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<float, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane<double, true, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
@@ -731,6 +756,10 @@ void init_kernel_attributes() {
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<double, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<float, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<double, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
+  DKS_HIP(hipFuncSetAttribute((const void *)k_plane_direct<float, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallPlaneLds));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane_real<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   DKS_HIP(hipFuncSetAttribute((const void *)k_plane_real<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840));
   init_scf_kernel_attributes();
@@ -999,17 +1028,22 @@ void apply_h_on(dks_basis *b, int sysi, const cplx<T> *X, cplx<T> *HX, int nb, d
       plane_direct_lds_bytes<T>(s.grid[0], s.grid[1]) <= 163840) {
     const size_t smd = plane_direct_lds_bytes<T>(s.grid[0], s.grid[1]);
     const bool dsmall = form == 5 && smd <= kSmallPlaneLds;
-    DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"),
-               (dsmall ? k_plane_direct<T, true> : k_plane_direct<T, false>), gp,
+    const bool lite = fft2::plane_lite_has(s.grid[0]) && fft2::plane_lite_has(s.grid[1]);
+    auto kd = dsmall ? (lite ? k_plane_direct<T, true, true> : k_plane_direct<T, true>)
+                     : (lite ? k_plane_direct<T, false, true> : k_plane_direct<T, false>);
+    DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kd, gp,
                dim3(dsmall ? kSmallPlaneThreads : kPlaneThreads<T>), smd, st, t1,
                s.ncol, s.d_ctab.as<int>(), s.d_rowflag.as<int>(), s.d_rows.as<int>(), s.nrows,
                s.d_plan.as<FftPlan>(), Tw<T>(pot, 0), Tw<T>(pot, 1), Vtab<T>(pot), gskip);
   } else {
   const bool small = fits_small && (form == 1 || form == 3);
   const bool wlines = tab && (form == 2 || form == 3);
+  const bool lite = tab && fft2::plane_lite_has(s.grid[0]) && fft2::plane_lite_has(s.grid[1]);
   auto kplane = !tab ? k_plane<T, false>
-                     : small ? (wlines ? k_plane<T, true, true, true> : k_plane<T, true, true>)
-                             : (wlines ? k_plane<T, true, false, true> : k_plane<T, true>);
+                : small ? (wlines ? (lite ? k_plane<T, true, true, true, true> : k_plane<T, true, true, true>)
+                                  : (lite ? k_plane<T, true, true, false, true> : k_plane<T, true, true>))
+                        : (wlines ? (lite ? k_plane<T, true, false, true, true> : k_plane<T, true, false, true>)
+                                  : (lite ? k_plane<T, true, false, false, true> : k_plane<T, true>));
   const int pthr = small ? kSmallPlaneThreads : kPlaneThreads<T>;
   DKS_LAUNCH((sizeof(T) == 8 ? "k_plane.f64" : "k_plane.f32"), kplane, gp, dim3(pthr), smp, st, t1, s.ncol,
              s.d_col_info.as<int4>(), s.d_rows.as<int>(), s.nrows, s.d_plan.as<FftPlan>(),
