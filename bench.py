@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve runs")
     ap.add_argument("--only-scf", action="store_true",
                     help="profiling aid: only the heavy-dimer SCF loops (DKS and KSSO)")
+    ap.add_argument("--only-layered", action="store_true",
+                    help="profiling aid: only the layered crystal's batched solves and its "
+                         "all-active k-point iteration")
     ap.add_argument("--only-apply", action="store_true",
                     help="profiling aid: only K FP64 H.X applications of the 40-band block, then "
                          "one device copy of 1 GiB (the calibration kernel for HBM counters)")
@@ -140,9 +143,68 @@ def main():
     X0d = torch.from_numpy(X0).to(dev)
     stream = torch.cuda.current_stream()
 
+    def golden_of(name):
+        path = os.path.join(ROOT, "tests", "golden", name)
+        return json.load(open(path)) if os.path.exists(path) else None
+
+    # ---- the layered crystal: the 16 k-points of 120 bands (N ~ 17.0k each,
+    # 48 x 48 x 320 grid) solved to 1e-8 Ha in one batched call, FP64 and
+    # mixed; per-band errors of k-point 0 and its partner -k (k-point 15)
+    # against the oracle's golden; the all-active FP64 iteration on one k-point
+    def run_layered():
+        sL = sysgen.layered_crystal(0)
+        bL = dk.init_basis([sL])
+        nkL = sL.kpts.shape[0]
+        gL = golden_of("layered_crystal_seed0_k0.json")
+        nwL = sL.n_bands
+        # 40 buffer columns (n_Z = 480): 598 k-point iterations instead of 2 403 with 8, and
+        # the shortest time to solution of 8, 16, 24 and 40 (each k-point's Rayleigh-Ritz
+        # grows with n_Z, but the 16 run concurrently)
+        bufL = 40
+        nL = nwL + bufL
+        XsL, npwL = [], []
+        for i in range(nkL):
+            NL, _, milL = dk.basis_info(bL, i)
+            X0L = np.zeros((nL, 4, NL), dtype=np.complex128)
+            X0L[:, :2] = sysgen.start_block(milL, sL.lattice, sL.kpts[i], nL, i)
+            XsL.append(torch.from_numpy(X0L).to(dev))
+            npwL.append(NL)
+        layered = {"kpoints": nkL, "npw_per_k": npwL, "bands": nwL, "buffer_columns": bufL,
+                   "grid": list(sL.grid)}
+        for tag, mode in (("fp64", dk.MODE_FP64), ("mixed_fp32", dk.MODE_MIXED_FP32)):
+            o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=bufL)
+            Xw = [x.clone() for x in XsL]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lams, _, infos, _ = dk.lobpcgf_solve_batch(bL, list(range(nkL)), [nL] * nkL, Xw, o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            its = sum(i_["iterations"] for i_ in infos)
+            rec = {"seconds": dt, "converged": sum(int(i_["converged"]) for i_ in infos),
+                   "kpoint_iterations": its, "kpoint_iterations_per_s": its / dt,
+                   "worst_resnorm": max(i_["max_resnorm"] for i_ in infos),
+                   "iterations_per_k": [i_["iterations"] for i_ in infos]}
+            if gL:
+                ref = np.array(gL["eigenvalues"])   # the lowest len(ref) of the 120
+                for kk in (0, nkL - 1):
+                    err = np.abs(np.asarray(lams[kk][:len(ref)]) - ref)
+                    rec[f"k{kk}_max_abs_err_vs_oracle_Ha"] = float(err.max())
+                    rec[f"k{kk}_per_band_err_Ha"] = [float(x) for x in err]
+            layered[f"{tag}_to_1e-8"] = rec
+            log(f"[bench] layered crystal {tag}: 16 k to 1e-8 in {dt:.2f}s "
+                f"({rec['converged']}/16 converged, {its} k-point iterations)")
+        layered["mixed_fp32_speedup_vs_fp64"] = (layered["fp64_to_1e-8"]["seconds"] /
+                                                 layered["mixed_fp32_to_1e-8"]["seconds"])
+        it64 = np.zeros(16)
+        o64 = dk.default_opts(tol=1e-300, n_iter=4, kinetic_balance=1)
+        dk.lobpcgf_solve(bL, 0, nwL, XsL[0][:nwL].clone(), o64, iter_ms=it64)
+        layered["fp64_kpoint_iteration_ms_120_bands"] = float(np.mean(it64[1:4]))
+        bL.close()
+        return layered
+
     # ---- the SCF loop around the eigensolver (Sec. 4; Table 6 reports the wall
     # time per SCF step): 24 electrons in the 40 lowest bands (+ 8 buffer
-    # columns) at 5000 K, 10 eigensolver iterations per step, Anderson + Kerker
+    # columns) at 5000 K, 5 eigensolver iterations per step, Anderson + Kerker
     # mixing, to ||dV|| / ||V|| < 1e-8 with every wanted residual below 1e-8;
     # DKS (LOBPCG-F) and KSSO (standard LOBPCG)
     def run_scf():
@@ -183,6 +245,11 @@ def main():
 
     if args.only_scf:
         run_scf()
+        b.close()
+        return
+
+    if args.only_layered:
+        run_layered()
         b.close()
         return
 
@@ -308,10 +375,6 @@ def main():
     it32, info32 = iterations(dk.MODE_MIXED_FP32, W + K)
     step32_ms = float(np.mean(it32[W:W + K]))
     log(f"[bench] FP32 LOBPCG-F iteration: {step32_ms:.3f} ms")
-
-    def golden_of(name):
-        path = os.path.join(ROOT, "tests", "golden", name)
-        return json.load(open(path)) if os.path.exists(path) else None
 
     def solve_record(bs, nb, X0_, mode, ref=None, n_buffer=0, method=None):
         Xd_ = X0_.clone()
@@ -525,60 +588,7 @@ def main():
         log(f"[bench] same systems one after another, fp64: {batch['fp64_sequential_s']:.3f}s")
         bb.close()
 
-    # ---- the layered crystal: the 16 k-points of 120 bands (N ~ 17.0k each,
-    # 48 x 48 x 320 grid) solved to 1e-8 Ha in one batched call, FP64 and
-    # mixed; per-band errors of k-point 0 and its partner -k (k-point 15)
-    # against the oracle's golden; the all-active FP64 iteration on one k-point
-    layered = None
-    if not args.no_solve and not args.no_batch:
-        sL = sysgen.layered_crystal(0)
-        bL = dk.init_basis([sL])
-        nkL = sL.kpts.shape[0]
-        gL = golden_of("layered_crystal_seed0_k0.json")
-        nwL = sL.n_bands
-        # 40 buffer columns (n_Z = 480): 598 k-point iterations instead of 2 403 with 8, and
-        # the shortest time to solution of 8, 16, 24 and 40 (each k-point's Rayleigh-Ritz
-        # grows with n_Z, but the 16 run concurrently)
-        bufL = 40
-        nL = nwL + bufL
-        XsL, npwL = [], []
-        for i in range(nkL):
-            NL, _, milL = dk.basis_info(bL, i)
-            X0L = np.zeros((nL, 4, NL), dtype=np.complex128)
-            X0L[:, :2] = sysgen.start_block(milL, sL.lattice, sL.kpts[i], nL, i)
-            XsL.append(torch.from_numpy(X0L).to(dev))
-            npwL.append(NL)
-        layered = {"kpoints": nkL, "npw_per_k": npwL, "bands": nwL, "buffer_columns": bufL,
-                   "grid": list(sL.grid)}
-        for tag, mode in (("fp64", dk.MODE_FP64), ("mixed_fp32", dk.MODE_MIXED_FP32)):
-            o = dk.default_opts(mode=mode, tol=1e-8, n_iter=400, kinetic_balance=1, n_buffer=bufL)
-            Xw = [x.clone() for x in XsL]
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            lams, _, infos, _ = dk.lobpcgf_solve_batch(bL, list(range(nkL)), [nL] * nkL, Xw, o)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t
-            its = sum(i_["iterations"] for i_ in infos)
-            rec = {"seconds": dt, "converged": sum(int(i_["converged"]) for i_ in infos),
-                   "kpoint_iterations": its, "kpoint_iterations_per_s": its / dt,
-                   "worst_resnorm": max(i_["max_resnorm"] for i_ in infos),
-                   "iterations_per_k": [i_["iterations"] for i_ in infos]}
-            if gL:
-                ref = np.array(gL["eigenvalues"])   # the lowest len(ref) of the 120
-                for kk in (0, nkL - 1):
-                    err = np.abs(np.asarray(lams[kk][:len(ref)]) - ref)
-                    rec[f"k{kk}_max_abs_err_vs_oracle_Ha"] = float(err.max())
-                    rec[f"k{kk}_per_band_err_Ha"] = [float(x) for x in err]
-            layered[f"{tag}_to_1e-8"] = rec
-            log(f"[bench] layered crystal {tag}: 16 k to 1e-8 in {dt:.2f}s "
-                f"({rec['converged']}/16 converged, {its} k-point iterations)")
-        layered["mixed_fp32_speedup_vs_fp64"] = (layered["fp64_to_1e-8"]["seconds"] /
-                                                 layered["mixed_fp32_to_1e-8"]["seconds"])
-        it64 = np.zeros(16)
-        o64 = dk.default_opts(tol=1e-300, n_iter=4, kinetic_balance=1)
-        dk.lobpcgf_solve(bL, 0, nwL, XsL[0][:nwL].clone(), o64, iter_ms=it64)
-        layered["fp64_kpoint_iteration_ms_120_bands"] = float(np.mean(it64[1:4]))
-        bL.close()
+    layered = run_layered() if not args.no_solve and not args.no_batch else None
 
     # ---- CPU oracle on a bounded sample: one Algorithm 1 iteration on the same system
     cpu = None
