@@ -235,12 +235,14 @@ typedef struct {
                            DKS_MODEL_DKS, [n][2][N] for DKS_MODEL_KSSO.  Default DKS */
   int batch_graph;      /* dks_lobpcgf_solve_batch only.  0: every item on its own lane
                            (a stream and a host thread deciding each iteration).  1: all
-                           items in lockstep inside one captured HIP graph per chunk of
-                           graph_chunk iterations: convergence, stagnation and the
+                           items in lockstep, in groups, each group's items captured into
+                           one HIP graph of graph_chunk iterations on a stream of its own
+                           (the groups run concurrently): convergence, stagnation and the
                            iteration cap are decided on the device, finished items become
                            empty launches, the host waits once per chunk; the graph form
-                           iterates every column (no soft locking) and keeps P orthogonal
-                           to X; items that leave it unconverged (stall, a failed
+                           keeps every iteration's shape (converged columns are locked by
+                           clearing their search directions) and keeps P orthogonal to X;
+                           items that leave it unconverged (stall, a failed
                            Rayleigh-Ritz, a broken-down step) are finished on the lanes
                            from their last good block.  Algorithm 1 only (method =
                            DKS_METHOD_LOBPCG; else DKS_EINVAL).  Default 0 */

@@ -926,10 +926,10 @@ static void run_on_lanes(dks_basis *b, const std::vector<int> &items, const int 
 // Every item iterates Algorithm 1 on a fixed shape: the subspace is always
 // [X, Y, P] of 3n rows (P = 0 in the first step, whose zero columns the
 // Rayleigh-Ritz drops as dependent; the Y and P columns of converged columns
-// are zero likewise, k_graph_lock), and P is kept orthogonal to X.  Each iteration is then the same sequence of
-// launches with the same sizes, so the iterations of all items can be
-// captured once into one HIP graph (one branch per item on its own stream)
-// and replayed.  Two device kernels per iteration make the decisions the host
+// are zero likewise, k_graph_lock), and P is kept orthogonal to X.  Each
+// iteration is then the same sequence of launches with the same sizes, so the
+// iterations of a group of items can be captured once into one HIP graph on
+// the group's stream and replayed (the groups run concurrently).  Two device kernels per iteration make the decisions the host
 // makes on the lanes: k_graph_check after the Rayleigh-Ritz (failed
 // factorisation, or a Ritz value below its predecessor by more than the block
 // residual allows) and k_graph_step after the residual norms (convergence of
