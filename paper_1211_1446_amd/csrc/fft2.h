@@ -14,8 +14,10 @@
 // permutation that the potential is stored in.  Step 2, the multiplication by
 // V(r) and step 2' touch the same block and run fused in registers.
 //
-// Codelets DFT_R are unrolled at compile time from radix-2/3/4/5 kernels with
-// constant twiddles; R = 1 is the identity (single-step transforms, n = B).
+// Codelets DFT_R are unrolled at compile time from radix-2/3/4/5 kernels, with
+// constant twiddles between the factors, or none when the two factors are
+// coprime (prime-factor index maps); R = 1 is the identity (single-step
+// transforms, n = B).
 #pragma once
 
 #include "dks_internal.h"
@@ -76,6 +78,14 @@ template <int R> struct Split {
   static constexpr int Q = R / P;
 };
 
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+// the k in [0, P Q) with k = kp (mod P) and k = kq (mod Q), P and Q coprime
+constexpr int crt(int kp, int kq, int P, int Q) {
+  int k = kq;
+  while (k % P != kp) k += Q;
+  return k;
+}
+
 // y_k = sum_j v_j exp(S 2 pi i j k / R), in place
 template <int R, int S, typename T> struct Codelet {
   template <typename C> __device__ __forceinline__ static void run(C *v) {
@@ -83,6 +93,31 @@ template <int R, int S, typename T> struct Codelet {
       return;
     } else if constexpr (R == 2 || R == 3 || R == 4 || R == 5) {
       Dft<R, S, T>::run(v);
+    } else if constexpr (cgcd(Split<R>::P, Split<R>::Q) == 1) {
+      // coprime factors (Good-Thomas): with j = (Q p + P q) mod R and
+      // k = crt(kp, kq), j k = Q p kp + P q kq (mod R), so
+      // y[crt(kp, kq)] = sum_p w_P^{p kp} sum_q w_Q^{q kq} v[(Q p + P q) mod R]:
+      // two passes of short transforms and no twiddle factors in between
+      constexpr int P = Split<R>::P, Q = Split<R>::Q;
+      C t[R];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        C u[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) u[q] = v[(Q * p + P * q) % R];
+        Codelet<Q, S, T>::run(u);
+#pragma unroll
+        for (int kq = 0; kq < Q; ++kq) t[p * Q + kq] = u[kq];
+      }
+#pragma unroll
+      for (int kq = 0; kq < Q; ++kq) {
+        C u[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) u[p] = t[p * Q + kq];
+        Codelet<P, S, T>::run(u);
+#pragma unroll
+        for (int kp = 0; kp < P; ++kp) v[crt(kp, kq, P, Q)] = u[kp];
+      }
     } else {
       constexpr int P = Split<R>::P, Q = Split<R>::Q;
       C t[R];
