@@ -56,8 +56,9 @@ typedef enum {
                                  to nearest even) and accumulate hi*hi + hi*lo + lo*hi in FP32
                                  on the BF16 matrix cores (plain BF16 inputs are too coarse
                                  for the Dirac Rayleigh-Ritz).  Three BF16 products per FP32
-                                 product: measured no faster than MIXED_FP32 (the Gram
-                                 launch takes about as long), kept as the studied option */
+                                 product on the K = 32 BF16 instruction: the Gram launch is
+                                 about 1.3x faster than MIXED_FP32's, the time to solution
+                                 about the same (the Gram is a small share of it) */
 } dks_mode;
 
 /* Which operator a solve works on (the modules of the paper's Table 1). */

@@ -330,67 +330,84 @@ void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B,
 
 // ---------------------------------------------------------------------------
 // Gram products on the BF16 matrix cores with FP32 accumulation
-// (v_mfma_f32_16x16x16_bf16).  Each FP32 input is split into two BF16 numbers,
+// (v_mfma_f32_16x16x32_bf16).  Each FP32 input is split into two BF16 numbers,
 // x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to nearest even),
 // and a b is taken as hi_a hi_b + hi_a lo_b + lo_a hi_b: about 16 significant
 // bits per factor instead of 8, at three BF16 products per real product.
-// Same tiling, splitting and reduction as k_gemm_ip.
+// The split is made once per element, by the thread that stages it: LDS holds
+// four BF16 planes per row (hi and lo of the real and the imaginary part).  A
+// step stages 32 complex k values; lane l of a 16 x 16 x 32 product holds row
+// (or column) l % 16 and the eight values of slot group l / 16.  Thread t
+// fetches the pairs k = 2 p, 2 p + 1 with p = t % 4 + 4 u (u < 4: four lanes
+// read 64 contiguous bytes of a row per load) and stores them in slots
+// 8 (t % 4) + 2 u + {0, 1}; every operand is staged alike, so the k order
+// inside a step differs from memory order for all of them together and the
+// sums are those of the plain product.
+// Same output tiling, k splitting and reduction as k_gemm_ip.
 // ---------------------------------------------------------------------------
-typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+constexpr int kBfKT = 32;                   // complex k values staged per step
+constexpr int kBfPlane = kBfKT * 2;         // bytes of one BF16 plane of a row
+constexpr int kBfRow = 4 * kBfPlane + 16;   // bytes per staged row (16 B pad: rows l % 16
+                                            // of one read fall on distinct banks)
+constexpr int kBfBlocks = 512;              // split-K target (fewer partials to reduce)
 
-__device__ __forceinline__ short f32_to_bf16(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (inputs are finite)
-  return (short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f32(short h) {
-  return __uint_as_float((unsigned)(unsigned short)h << 16);
-}
-
-// hi / lo BF16 fragments of one real component
-struct Split4 {
-  s4 hi, lo;
-};
-__device__ __forceinline__ void split_bf16(float v, short &hi, short &lo) {
-  hi = f32_to_bf16(v);
-  lo = f32_to_bf16(v - bf16_to_f32(hi));
-}
-__device__ __forceinline__ f4 mfma_split(const Split4 &a, const Split4 &b, f4 c) {
-  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, c, 0, 0, 0);
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, c, 0, 0, 0);
+// Workgroup L -> (tile t, k split z).  Consecutive workgroups go to the eight
+// XCDs in turn, so the tiles of one split are given to workgroups eight apart
+// (L, L + 8, ...): they run on one XCD, whose L2 then serves the rows they
+// share.  A tail of fewer than eight splits keeps the plain order.
+__device__ __forceinline__ void bf_map(int L, int tiles, int nsplit, int &t, int &z) {
+  const int z8 = nsplit & ~7, full = z8 * tiles;
+  if (L < full) {
+    const int s = L >> 3;
+    t = s % tiles;
+    z = (s / tiles) * 8 + (L & 7);
+  } else {
+    const int r = L - full;
+    t = r % tiles;
+    z = z8 + r / tiles;
+  }
 }
 
-__global__ void __launch_bounds__(256) k_gemm_ip_bf16(const float2 *__restrict__ A,
+__device__ __forceinline__ bf8 bf_neg(bf8 x) {
+  u4 u = __builtin_bit_cast(u4, x);
+  u ^= 0x80008000u;   // flip both BF16 sign bits of each dword
+  return __builtin_bit_cast(bf8, u);
+}
+
+__global__ void __launch_bounds__(256, 2) k_gemm_ip_bf16(const float2 *__restrict__ A,
                                                       const int64_t *__restrict__ aoff, int M,
                                                       const float2 *__restrict__ B,
                                                       const int64_t *__restrict__ boff, int Nn,
                                                       const float2 *__restrict__ B2, int64_t K,
                                                       int64_t kchunk, int tm, int upper,
+                                                      int tiles, int nsplit,
                                                       double2 *__restrict__ part,
                                                       double2 *__restrict__ part2) {
-  using C = float2;
-  constexpr int LD = kIpKT + 1;
-  __shared__ C As[kIpTile * LD];
-  __shared__ C Bs[kIpTile * LD];
-  __shared__ C B2s[kIpTile * LD];
+  __shared__ __align__(16) unsigned char As[kIpTile * kBfRow];
+  __shared__ __align__(16) unsigned char Bs[kIpTile * kBfRow];
+  __shared__ __align__(16) unsigned char B2s[kIpTile * kBfRow];
   const bool two = (B2 != nullptr);
-  int ti, tj;
-  ip_tile(blockIdx.x, tm, upper != 0, ti, tj);
+  int t, z, ti, tj;
+  bf_map(blockIdx.x, tiles, nsplit, t, z);
+  ip_tile(t, tm, upper != 0, ti, tj);
   const int tm0 = ti * kIpTile, tn0 = tj * kIpTile;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t kb = (int64_t)z * kchunk;
   const int64_t ke = min(K, kb + kchunk);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int lrow = tid >> 2, lk = (tid & 3) * 4;
-  const C *arow = nullptr, *brow = nullptr, *b2row = nullptr;
-  if (tm0 + lrow < M) arow = A + (aoff ? aoff[tm0 + lrow] : (int64_t)(tm0 + lrow) * K);
-  if (tn0 + lrow < Nn) {
-    int64_t o = boff ? boff[tn0 + lrow] : (int64_t)(tn0 + lrow) * K;
-    brow = B + o;
-    if (two) b2row = B2 + o;
-  }
+  const int lrow = tid >> 2, lq = tid & 3;
+  // rows past the matrix read the tile's first row and stage zeros: every
+  // load is unconditional, its value selected (no branch around each load)
+  const bool aval = tm0 + lrow < M, bval = tn0 + lrow < Nn;
+  const int ar_ = aval ? tm0 + lrow : tm0, br_ = bval ? tn0 + lrow : tn0;
+  const float2 *arow = A + (aoff ? aoff[ar_] : (int64_t)ar_ * K);
+  const int64_t bo = boff ? boff[br_] : (int64_t)br_ * K;
+  const float2 *brow = B + bo;
+  const float2 *b2row = two ? B2 + bo : brow;
   f4 re[2][2], im[2][2], re2[2][2], im2[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -401,71 +418,107 @@ __global__ void __launch_bounds__(256) k_gemm_ip_bf16(const float2 *__restrict__
       re2[i][j] = f4{0, 0, 0, 0};
       im2[i][j] = f4{0, 0, 0, 0};
     }
-  C ra[4], rb[4], rb2[4];
-  auto fetch = [&](int64_t k0) {
+  // 16-byte loads (two complex values) where a row starts 16-byte aligned
+  // (kb and k0 are even), two 8-byte loads otherwise
+  const bool aal = ((uintptr_t)arow & 15) == 0, bal = ((uintptr_t)brow & 15) == 0,
+             b2al = ((uintptr_t)b2row & 15) == 0;
+  auto ld2 = [](const float2 *row, bool al, int64_t k) {
+    if (al) return *(const float4 *)(row + k);
+    const float2 a = row[k], b = row[k + 1];
+    return float4{a.x, a.y, b.x, b.y};
+  };
+  float4 ra[4], rb[4], rb2[4];
+  // K is even and every chunk boundary even, so a pair is in range as a whole
+  auto fetch = [&](int64_t k0) {   // k0 < ke, so k0 is a valid index
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t k = k0 + lk + u;
+      const int64_t k = k0 + 2 * (lq + 4 * u);
       const bool ok = k < ke;
-      ra[u] = (arow && ok) ? arow[k] : C{0, 0};
-      rb[u] = (brow && ok) ? brow[k] : C{0, 0};
-      if (two) rb2[u] = (b2row && ok) ? b2row[k] : C{0, 0};
+      const int64_t kk = ok ? k : k0;
+      const float4 x = ld2(arow, aal, kk), y = ld2(brow, bal, kk);
+      ra[u] = (aval && ok) ? x : float4{0, 0, 0, 0};
+      rb[u] = (bval && ok) ? y : float4{0, 0, 0, 0};
+      if (two) {
+        const float4 w = ld2(b2row, b2al, kk);
+        rb2[u] = (bval && ok) ? w : float4{0, 0, 0, 0};
+      }
     }
   };
-  // lane l's four k values of one 16 x 16 x 16 product: 4 (l / 16) + 0..3
-  auto frag = [&](const C *T_, int row, Split4 &fr, Split4 &fi) {
-    const int kq = 4 * (lane >> 4);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const C v = T_[row * LD + kq + q];
-      short h, l;
-      split_bf16(v.x, h, l);
-      fr.hi[q] = h;
-      fr.lo[q] = l;
-      split_bf16(v.y, h, l);
-      fi.hi[q] = h;
-      fi.lo[q] = l;
-    }
-  };
-  if (kb < ke) fetch(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += kIpKT) {
+  // planes at byte offsets 0 (re hi), 64 (re lo), 128 (im hi), 192 (im lo)
+  auto stage = [&](unsigned char *T_, const float4 (&v)[4]) {
+    f8 xr, xi;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      As[lrow * LD + lk + u] = ra[u];
-      Bs[lrow * LD + lk + u] = rb[u];
-      if (two) B2s[lrow * LD + lk + u] = rb2[u];
+      xr[2 * u] = v[u].x;
+      xi[2 * u] = v[u].y;
+      xr[2 * u + 1] = v[u].z;
+      xi[2 * u + 1] = v[u].w;
     }
-    __syncthreads();
-    if (k0 + kIpKT < ke) fetch(k0 + kIpKT);
-    Split4 ar[2], ai[2], ain[2], br[2], bi[2], cr[2], ci[2];
+    const bf8 rh = __builtin_convertvector(xr, bf8);
+    const bf8 rl = __builtin_convertvector(xr - __builtin_convertvector(rh, f8), bf8);
+    const bf8 ih = __builtin_convertvector(xi, bf8);
+    const bf8 il = __builtin_convertvector(xi - __builtin_convertvector(ih, f8), bf8);
+    unsigned char *p = T_ + lrow * kBfRow + lq * 16;
+    *(bf8 *)p = rh;
+    *(bf8 *)(p + kBfPlane) = rl;
+    *(bf8 *)(p + 2 * kBfPlane) = ih;
+    *(bf8 *)(p + 3 * kBfPlane) = il;
+  };
+  auto frag = [&](const unsigned char *T_, int row, bf8 (&f)[4]) {
+    const unsigned char *p = T_ + row * kBfRow + (lane >> 4) * 16;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      frag(As, wm + i * 16 + (lane & 15), ar[i], ai[i]);
-      ain[i].hi = ai[i].hi ^ (short)0x8000;   // -a_i: flip the BF16 sign bits
-      ain[i].lo = ai[i].lo ^ (short)0x8000;
-      frag(Bs, wn + i * 16 + (lane & 15), br[i], bi[i]);
-      if (two) frag(B2s, wn + i * 16 + (lane & 15), cr[i], ci[i]);
-    }
+    for (int q = 0; q < 4; ++q) f[q] = *(const bf8 *)(p + q * kBfPlane);
+  };
+  // acc += x y over the step, x = xh + xl and y = yh + yl: small terms first
+  auto prod = [&](f4 (&acc)[2][2], const bf8 (&x)[2][4], int px, const bf8 (&y)[2][4], int py) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        // conj(a) b: re += ar br + ai bi, im += ar bi - ai br
-        re[i][j] = mfma_split(ar[i], br[j], re[i][j]);
-        im[i][j] = mfma_split(ar[i], bi[j], im[i][j]);
-        re[i][j] = mfma_split(ai[i], bi[j], re[i][j]);
-        im[i][j] = mfma_split(ain[i], br[j], im[i][j]);
-        if (two) {
-          re2[i][j] = mfma_split(ar[i], cr[j], re2[i][j]);
-          im2[i][j] = mfma_split(ar[i], ci[j], im2[i][j]);
-          re2[i][j] = mfma_split(ai[i], ci[j], re2[i][j]);
-          im2[i][j] = mfma_split(ain[i], cr[j], im2[i][j]);
-        }
-      }
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[i][px + 1], y[j][py], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[i][px], y[j][py + 1], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[i][px], y[j][py], acc[i][j], 0, 0, 0);
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kBfKT) {
+    stage(As, ra);
+    stage(Bs, rb);
+    if (two) stage(B2s, rb2);
+    __syncthreads();
+    if (k0 + kBfKT < ke) fetch(k0 + kBfKT);
+    // a[i] = [re hi, re lo, im hi, im lo], an[i] = [-im hi, -im lo] (slots 2, 3 unused)
+    bf8 a[2][4], an[2][4], b[2][4], c[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      frag(As, wm + i * 16 + (lane & 15), a[i]);
+      an[i][0] = bf_neg(a[i][2]);
+      an[i][1] = bf_neg(a[i][3]);
+      frag(Bs, wn + i * 16 + (lane & 15), b[i]);
+      if (two) frag(B2s, wn + i * 16 + (lane & 15), c[i]);
+    }
+    // conj(a) b: re += ar br + ai bi, im += ar bi - ai br
+    prod(re, a, 0, b, 0);
+    prod(im, a, 0, b, 2);
+    prod(re, a, 2, b, 2);
+    prod(im, an, 0, b, 0);
+    if (two) {
+      prod(re2, a, 0, c, 0);
+      prod(im2, a, 0, c, 2);
+      prod(re2, a, 2, c, 2);
+      prod(im2, an, 0, c, 0);
+    }
     __syncthreads();
   }
-  double2 *p1 = part + (size_t)blockIdx.z * M * Nn;
-  double2 *p2 = two ? part2 + (size_t)blockIdx.z * M * Nn : nullptr;
+  double2 *p1 = part + (size_t)z * M * Nn;
+  double2 *p2 = two ? part2 + (size_t)z * M * Nn : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -486,16 +539,17 @@ void gemm_ip_bf16(const float2 *A, const int64_t *aoff, int M, const float2 *B, 
                   int Nn, const float2 *B2, int64_t K, double2 *out, double2 *out2, int ldo,
                   DevBuf &part, hipStream_t st, bool hermitian) {
   if (M <= 0 || Nn <= 0) return;
-  const IpShape g = ip_shape(M, Nn, K, hermitian, 0);
+  DKS_REQUIRE(K % 2 == 0, DKS_EINVAL, "BF16 Gram product: the row length must be even");
+  const IpShape g = ip_shape(M, Nn, K, hermitian, kBfBlocks);
   const int tm = g.tm, tiles = g.tiles;
   const bool upper = g.upper;
   const int64_t nsplit = g.nsplit, kchunk = g.kchunk;
-  part.ensure(sizeof(double2) * gemm_ip_part_elems(M, Nn, K, B2 != nullptr, hermitian));
+  part.ensure(sizeof(double2) * gemm_ip_part_elems(M, Nn, K, B2 != nullptr, hermitian, kBfBlocks));
   double2 *p1 = part.as<double2>();
   double2 *p2 = B2 ? p1 + (size_t)nsplit * M * Nn : nullptr;
-  dim3 grid(tiles, 1, (unsigned)nsplit);
+  dim3 grid((unsigned)(tiles * nsplit));
   DKS_LAUNCH("k_gemm_ip.gram.bf16", k_gemm_ip_bf16, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn,
-             B2, K, kchunk, tm, (int)upper, p1, p2);
+             B2, K, kchunk, tm, (int)upper, tiles, (int)nsplit, p1, p2);
   DKS_HIP(hipGetLastError());
   reduce_parts(p1, p2, (int)nsplit, M, Nn, upper, out, out2, ldo, st);
 }

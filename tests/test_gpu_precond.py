@@ -59,7 +59,7 @@ def test_precondition_matches_oracle(dev, model, prec):
         assert err < tol, (s.name, err)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_preconditioned_solve_tiny_matches_dense(dev, mode):
     lam, res, info, rc, lam_ref, vec_ref, Xo, s = _solve_tiny(dev, mode, preconditioner=1)
     print(f"  iterations {info['iterations']}", flush=True)
@@ -69,7 +69,7 @@ def test_preconditioned_solve_tiny_matches_dense(dev, mode):
     assert info["min_ritz"] > -s.c ** 2
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_preconditioned_heavy_dimer_matches_golden(dev, mode):
     """The heavy dimer (96^3, 40 bands) to 1e-8 Ha with T, against the golden of
     the oracle's Algorithm 1 (tests/golden/heavy_dimer_seed0.json)."""
