@@ -54,7 +54,11 @@ __device__ __forceinline__ void ip_tile(int x, int tm, bool upper, int &ti, int 
 // kTwo: B2 is given (the Gram pair S and A); without it the second set of
 // accumulators and its LDS tile are not there, which lets a single product
 // (projector coefficients, P against X) run at more waves per SIMD.
-template <typename T, bool kTwo>
+// kR48 (single products with M <= 48: 36 projectors, P against X of up to 48
+// columns): a 48 x 64 output tile, each wave 48 rows x 16 columns, so that no
+// 16 x 16 block lies wholly past the 48th row; 64-row tiles spend 28 of 64
+// rows on padding at M = 36.
+template <typename T, bool kTwo, bool kR48 = false>
 __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__restrict__ A,
                                                  const int64_t *__restrict__ aoff, int M,
                                                  const typename CT<T>::c *__restrict__ B,
@@ -68,23 +72,26 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
   using C = typename CT<T>::c;
   using MF = Mfma<T>;
   using acc_t = typename MF::acc;
+  static_assert(!(kTwo && kR48), "the 48-row tile is for single products");
   constexpr int LD = kIpKT + 1;
-  __shared__ C As[kIpTile * LD];
+  constexpr int TM = kR48 ? 48 : kIpTile;   // output tile rows
+  constexpr int NI = kR48 ? 3 : 2, NJ = kR48 ? 1 : 2;   // 16 x 16 blocks per wave
+  __shared__ C As[TM * LD];
   __shared__ C Bs[kIpTile * LD];
   __shared__ C B2s[kTwo ? kIpTile * LD : 1];
   constexpr bool two = kTwo;
   int ti, tj;
   ip_tile(blockIdx.x, tm, upper != 0, ti, tj);
-  const int tm0 = ti * kIpTile, tn0 = tj * kIpTile;
+  const int tm0 = ti * TM, tn0 = tj * kIpTile;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = min(K, kb + kchunk);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = kR48 ? 0 : (wave >> 1) * 32, wn = kR48 ? wave * 16 : (wave & 1) * 32;
   // loader mapping: 4 threads per row, 4 consecutive complex each
   const int lrow = tid >> 2, lk = (tid & 3) * 4;
   const C *arow = nullptr, *brow = nullptr, *b2row = nullptr;
-  if (tm0 + lrow < M) arow = A + (aoff ? aoff[tm0 + lrow] : (int64_t)(tm0 + lrow) * K);
+  if (lrow < TM && tm0 + lrow < M) arow = A + (aoff ? aoff[tm0 + lrow] : (int64_t)(tm0 + lrow) * K);
   if (tn0 + lrow < Nn) {
     int64_t o = boff ? boff[tn0 + lrow] : (int64_t)(tn0 + lrow) * K;
     brow = B + o;
@@ -96,13 +103,13 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
   // FP64 accumulator sets halve the occupancy and cost more than they save.
   constexpr bool gauss = sizeof(T) == 4;
   constexpr int NT = gauss ? 3 : 2;
-  acc_t t[NT][2][2], u[NT][2][2];
+  acc_t t[NT][NI][NJ], u[NT][NI][NJ];
 #pragma unroll
   for (int q = 0; q < NT; ++q)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) t[q][i][j] = u[q][i][j] = acc_t{0, 0, 0, 0};
+      for (int j = 0; j < NJ; ++j) t[q][i][j] = u[q][i][j] = acc_t{0, 0, 0, 0};
   // the next k step is fetched into registers while the current one is multiplied
   C ra[4], rb[4], rb2[4];
   auto fetch = [&](int64_t k0) {
@@ -119,7 +126,7 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
   for (int64_t k0 = kb; k0 < ke; k0 += kIpKT) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      As[lrow * LD + lk + u] = ra[u];
+      if (!kR48 || lrow < TM) As[lrow * LD + lk + u] = ra[u];
       Bs[lrow * LD + lk + u] = rb[u];
       if (two) B2s[lrow * LD + lk + u] = rb2[u];
     }
@@ -128,25 +135,27 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
 #pragma unroll
     for (int s = 0; s < kIpKT / 4; ++s) {
       const int kk = s * 4 + (lane >> 4);
-      C a[2], bb[2], b2[2];
+      C a[NI], bb[NJ], b2[NJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = As[(wm + i * 16 + (lane & 15)) * LD + kk];
-        bb[i] = Bs[(wn + i * 16 + (lane & 15)) * LD + kk];
-        if (two) b2[i] = B2s[(wn + i * 16 + (lane & 15)) * LD + kk];
+      for (int i = 0; i < NI; ++i) a[i] = As[(wm + i * 16 + (lane & 15)) * LD + kk];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        bb[j] = Bs[(wn + j * 16 + (lane & 15)) * LD + kk];
+        if (two) b2[j] = B2s[(wn + j * 16 + (lane & 15)) * LD + kk];
       }
       if constexpr (gauss) {
-        T ad[2], bs[2], b2s[2];
+        T ad[NI], bs[NJ], b2s[NJ];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          ad[i] = a[i].x - a[i].y;
-          bs[i] = bb[i].x + bb[i].y;
-          if (two) b2s[i] = b2[i].x + b2[i].y;
+        for (int i = 0; i < NI; ++i) ad[i] = a[i].x - a[i].y;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          bs[j] = bb[j].x + bb[j].y;
+          if (two) b2s[j] = b2[j].x + b2[j].y;
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < NJ; ++j) {
             t[0][i][j] = MF::mma(a[i].x, bb[j].x, t[0][i][j]);
             t[1][i][j] = MF::mma(a[i].y, bb[j].y, t[1][i][j]);
             t[NT - 1][i][j] = MF::mma(ad[i], bs[j], t[NT - 1][i][j]);
@@ -160,9 +169,9 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
         // re += ar br + ai bi, im += ar bi - ai br; the .x products of all
         // tiles first so that no accumulator is reused back to back
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < NJ; ++j) {
             t[0][i][j] = MF::mma(a[i].x, bb[j].x, t[0][i][j]);
             t[1][i][j] = MF::mma(a[i].x, bb[j].y, t[1][i][j]);
             if (two) {
@@ -171,9 +180,9 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
             }
           }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < NJ; ++j) {
             t[0][i][j] = MF::mma(a[i].y, bb[j].y, t[0][i][j]);
             t[1][i][j] = MF::mma(-a[i].y, bb[j].x, t[1][i][j]);
             if (two) {
@@ -188,15 +197,15 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
   double2 *p1 = part + (size_t)blockIdx.z * M * Nn;
   double2 *p2 = two ? part2 + (size_t)blockIdx.z * M * Nn : nullptr;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int r = tm0 + wm + i * 16 + MF::row(lane, v);
         int c = tn0 + wn + j * 16 + (lane & 15);
         if (r < M && c < Nn) {
-          auto val = [&](acc_t (&w)[NT][2][2]) {
+          auto val = [&](acc_t (&w)[NT][NI][NJ]) {
             const double x0 = w[0][i][j][v], x1 = w[1][i][j][v];
             if constexpr (gauss) {
               const double x2 = w[NT - 1][i][j][v];
@@ -321,7 +330,8 @@ void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B,
   dim3 grid(tiles, 1, (unsigned)nsplit);
   const char *name = upper ? (sizeof(T) == 8 ? "k_gemm_ip.gram.f64" : "k_gemm_ip.gram.f32")
                            : (sizeof(T) == 8 ? "k_gemm_ip.f64" : "k_gemm_ip.f32");
-  auto kern = B2 ? k_gemm_ip<T, true> : k_gemm_ip<T, false>;
+  // single products of at most 48 rows: one 48-row tile (tm = 1 as for 64 rows)
+  auto kern = B2 ? k_gemm_ip<T, true> : (M <= 48 ? k_gemm_ip<T, false, true> : k_gemm_ip<T, false>);
   DKS_LAUNCH(name, kern, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk, tm,
              (int)upper, p1, p2, skip);
   DKS_HIP(hipGetLastError());
