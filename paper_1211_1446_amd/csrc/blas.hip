@@ -51,6 +51,23 @@ __device__ __forceinline__ void ip_tile(int x, int tm, bool upper, int &ti, int 
   tj = ti + x;
 }
 
+// Workgroup L -> (tile t, k split z).  Consecutive workgroups go to the eight
+// XCDs in turn, so the tiles of one split are given to workgroups eight apart
+// (L, L + 8, ...): they run on one XCD, whose L2 then serves the rows they
+// share.  A tail of fewer than eight splits keeps the plain order.
+__device__ __forceinline__ void split_map(int L, int tiles, int nsplit, int &t, int &z) {
+  const int z8 = nsplit & ~7, full = z8 * tiles;
+  if (L < full) {
+    const int s = L >> 3;
+    t = s % tiles;
+    z = (s / tiles) * 8 + (L & 7);
+  } else {
+    const int r = L - full;
+    t = r % tiles;
+    z = z8 + r / tiles;
+  }
+}
+
 // kTwo: B2 is given (the Gram pair S and A); without it the second set of
 // accumulators and its LDS tile are not there, which lets a single product
 // (projector coefficients, P against X) run at more waves per SIMD.
@@ -65,6 +82,7 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
                                                  const int64_t *__restrict__ boff, int Nn,
                                                  const typename CT<T>::c *__restrict__ B2,
                                                  int64_t K, int64_t kchunk, int tm, int upper,
+                                                 int tiles, int nsplit,
                                                  double2 *__restrict__ part,
                                                  double2 *__restrict__ part2,
                                                  const int *__restrict__ skip) {
@@ -80,10 +98,11 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
   __shared__ C Bs[kIpTile * LD];
   __shared__ C B2s[kTwo ? kIpTile * LD : 1];
   constexpr bool two = kTwo;
-  int ti, tj;
-  ip_tile(blockIdx.x, tm, upper != 0, ti, tj);
+  int t_, z, ti, tj;
+  split_map(blockIdx.x, tiles, nsplit, t_, z);
+  ip_tile(t_, tm, upper != 0, ti, tj);
   const int tm0 = ti * TM, tn0 = tj * kIpTile;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t kb = (int64_t)z * kchunk;
   const int64_t ke = min(K, kb + kchunk);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -194,8 +213,8 @@ __global__ void __launch_bounds__(256) k_gemm_ip(const typename CT<T>::c *__rest
     }
     __syncthreads();
   }
-  double2 *p1 = part + (size_t)blockIdx.z * M * Nn;
-  double2 *p2 = two ? part2 + (size_t)blockIdx.z * M * Nn : nullptr;
+  double2 *p1 = part + (size_t)z * M * Nn;
+  double2 *p2 = two ? part2 + (size_t)z * M * Nn : nullptr;
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -327,13 +346,13 @@ void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B,
   const int64_t nsplit = g.nsplit, kchunk = g.kchunk;
   double2 *p1 = part;
   double2 *p2 = B2 ? p1 + (size_t)nsplit * M * Nn : nullptr;
-  dim3 grid(tiles, 1, (unsigned)nsplit);
+  dim3 grid((unsigned)(tiles * nsplit));
   const char *name = upper ? (sizeof(T) == 8 ? "k_gemm_ip.gram.f64" : "k_gemm_ip.gram.f32")
                            : (sizeof(T) == 8 ? "k_gemm_ip.f64" : "k_gemm_ip.f32");
   // single products of at most 48 rows: one 48-row tile (tm = 1 as for 64 rows)
   auto kern = B2 ? k_gemm_ip<T, true> : (M <= 48 ? k_gemm_ip<T, false, true> : k_gemm_ip<T, false>);
   DKS_LAUNCH(name, kern, grid, dim3(256), 0, st, A, aoff, M, B, boff, Nn, B2, K, kchunk, tm,
-             (int)upper, p1, p2, skip);
+             (int)upper, tiles, (int)nsplit, p1, p2, skip);
   DKS_HIP(hipGetLastError());
   reduce_parts(p1, p2, (int)nsplit, M, Nn, upper, out, out2, ldo, st, skip);
 }
@@ -353,7 +372,7 @@ void gemm_ip_raw(const cplx<T> *A, const int64_t *aoff, int M, const cplx<T> *B,
 // 8 (t % 4) + 2 u + {0, 1}; every operand is staged alike, so the k order
 // inside a step differs from memory order for all of them together and the
 // sums are those of the plain product.
-// Same output tiling, k splitting and reduction as k_gemm_ip.
+// Same output tiling, k splitting, workgroup order and reduction as k_gemm_ip.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f8 __attribute__((ext_vector_type(8)));
@@ -363,23 +382,6 @@ constexpr int kBfPlane = kBfKT * 2;         // bytes of one BF16 plane of a row
 constexpr int kBfRow = 4 * kBfPlane + 16;   // bytes per staged row (16 B pad: rows l % 16
                                             // of one read fall on distinct banks)
 constexpr int kBfBlocks = 512;              // split-K target (fewer partials to reduce)
-
-// Workgroup L -> (tile t, k split z).  Consecutive workgroups go to the eight
-// XCDs in turn, so the tiles of one split are given to workgroups eight apart
-// (L, L + 8, ...): they run on one XCD, whose L2 then serves the rows they
-// share.  A tail of fewer than eight splits keeps the plain order.
-__device__ __forceinline__ void bf_map(int L, int tiles, int nsplit, int &t, int &z) {
-  const int z8 = nsplit & ~7, full = z8 * tiles;
-  if (L < full) {
-    const int s = L >> 3;
-    t = s % tiles;
-    z = (s / tiles) * 8 + (L & 7);
-  } else {
-    const int r = L - full;
-    t = r % tiles;
-    z = z8 + r / tiles;
-  }
-}
 
 __device__ __forceinline__ bf8 bf_neg(bf8 x) {
   u4 u = __builtin_bit_cast(u4, x);
@@ -401,7 +403,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm_ip_bf16(const float2 *__restric
   __shared__ __align__(16) unsigned char B2s[kIpTile * kBfRow];
   const bool two = (B2 != nullptr);
   int t, z, ti, tj;
-  bf_map(blockIdx.x, tiles, nsplit, t, z);
+  split_map(blockIdx.x, tiles, nsplit, t, z);
   ip_tile(t, tm, upper != 0, ti, tj);
   const int tm0 = ti * kIpTile, tn0 = tj * kIpTile;
   const int64_t kb = (int64_t)z * kchunk;
