@@ -83,8 +83,16 @@ struct Solver {
   DevBuf dv, dhv;   // Davidson subspace V and H V (up to davidson_dim x n rows)
   DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, lockmask, pE, rinfo, rdinfo, off, idx, forced, rrs,
       part, part2, tst;
+  DevBuf rrout;   // Rayleigh-Ritz result laid out as its host copy h_rr
   HostBuf h_rr, h_lam, h_res, h_act, h_vp;
   Workspace ws;   // H.X scratch of this solver's applies
+  hipEvent_t rr_ev = nullptr;   // the Rayleigh-Ritz result has reached the host
+  Solver() = default;
+  Solver(const Solver &) = delete;
+  Solver &operator=(const Solver &) = delete;
+  ~Solver() {
+    if (rr_ev) (void)hipEventDestroy(rr_ev);
+  }
 };
 
 // Lanes of dks_lobpcgf_solve_batch: a solver workspace and a stream each,
@@ -233,7 +241,36 @@ template <typename T> struct LoopState {
   int iters = 0;
   double min_piv = 1.0;   // smallest Cholesky pivot of the last Rayleigh-Ritz basis
   int dropped = 0;   // directions the last Rayleigh-Ritz removed as dependent
+  bool xhx_queued = false;   // the last Rayleigh-Ritz queued X, H X of the next step
 };
+
+// X_new = Z V[:, :n], HX_new = HZ V into the other half of the double buffer.
+template <typename T>
+static void queue_xhx(Ctx &x, Blocks<T> &bk, int cur, int nz, int n, const double2 *Vz) {
+  Solver &sv = *x.sv;
+  const int nxt = 1 - cur;
+  gemm_up2<T>(bk.Z[cur].template as<cplx<T>>(), bk.HZ[cur].template as<cplx<T>>(),
+              sv.off.as<int64_t>(), nz, Vz, n, n, bk.K, bk.z(nxt, 0), bk.hz(nxt, 0), bk.K, 0.0,
+              x.st);
+}
+
+// The Rayleigh-Ritz result in one device buffer laid out as its host copy:
+// [info 4 x int | dinfo 2 x double | theta n | V nz x n] in double2 units, so
+// that one copy brings it over.
+struct RRView {
+  int *info;
+  double *dinfo, *theta;
+  double2 *V;
+};
+static size_t rr_count(int nz, int n) { return 2 + (size_t)(n + 1) / 2 + (size_t)nz * n; }
+static RRView rr_view(double2 *base, int n) {
+  RRView v;
+  v.info = reinterpret_cast<int *>(base);
+  v.dinfo = reinterpret_cast<double *>(base + 1);
+  v.theta = reinterpret_cast<double *>(base + 2);
+  v.V = base + 2 + (n + 1) / 2;
+  return v;
+}
 
 // Rayleigh-Ritz on Z_cur rows described by (n, m, mp); returns false when
 // fewer than n directions survive even without P.
@@ -268,18 +305,17 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
                  bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(),
                  sv.gA.as<double2>(), nz, sv.part, x.st, /*hermitian=*/true);
     }
-    sv.Vz.ensure(sizeof(double2) * nz * n);
-    sv.theta.ensure(sizeof(double) * n);
-    sv.rinfo.ensure(sizeof(int) * 4);
-    sv.rdinfo.ensure(sizeof(double) * 2);
+    const size_t nrr = rr_count(nz, n);
+    sv.rrout.ensure(sizeof(double2) * nrr);
+    const RRView d = rr_view(sv.rrout.as<double2>(), n);
     const bool stamps = log_enabled();
     if (stamps) sv.tst.ensure(sizeof(long long) * kRRStamps);
     // BF16-split Gram products carry relative errors of a few 1e-6: directions
     // whose scaled overlap pivot is not well above that are dropped
     const double dtol = (sizeof(T) == 4 && x.bf16_gram) ? std::max(drop_tol, kBf16DropTol) : drop_tol;
-    rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, dtol, x.floor, nullptr,
-                  sv.Vz.as<double2>(), sv.theta.as<double>(), sv.rinfo.as<int>(),
-                  sv.rdinfo.as<double>(), sv.rrs, x.st, stamps ? sv.tst.as<long long>() : nullptr);
+    rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, dtol, x.floor, nullptr, d.V,
+                  d.theta, d.info, d.dinfo, sv.rrs, x.st,
+                  stamps ? sv.tst.as<long long>() : nullptr);
     if (stamps) {
       // reduction phases: scaling, Cholesky, L^-1, products + Hermitian part,
       // tridiagonal reduction (stamps 0-5 of k_rr_reduce)
@@ -290,18 +326,23 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
       for (int k = 1; k < 6; ++k) std::fprintf(stderr, "%s%.1f", k > 1 ? ", " : "", (ts[k] - ts[k - 1]) / 100.0);
       std::fprintf(stderr, "]}\n");
     }
-    // status, Ritz values and vectors in one round trip: [info 4 x int |
-    // dinfo 2 x double | theta n | V nz x n]
-    double2 *hr = sv.h_rr.as<double2>(2 + (size_t)n + (size_t)nz * n);
-    int *info = reinterpret_cast<int *>(hr);
-    double *dinfo = reinterpret_cast<double *>(hr + 1);
-    double *hth = reinterpret_cast<double *>(hr + 2);
-    double2 *hvz = hr + 2 + (n + 1) / 2;
-    DKS_HIP(hipMemcpyAsync(info, sv.rinfo.p, sizeof(int) * 4, hipMemcpyDeviceToHost, x.st));
-    DKS_HIP(hipMemcpyAsync(dinfo, sv.rdinfo.p, sizeof(double) * 2, hipMemcpyDeviceToHost, x.st));
-    DKS_HIP(hipMemcpyAsync(hth, sv.theta.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
-    DKS_HIP(hipMemcpyAsync(hvz, sv.Vz.p, sizeof(double2) * nz * n, hipMemcpyDeviceToHost, x.st));
-    DKS_HIP(hipStreamSynchronize(x.st));
+    // status, Ritz values and vectors in one copy
+    double2 *hr = sv.h_rr.as<double2>(nrr);
+    const RRView h = rr_view(hr, n);
+    int *info = h.info;
+    double *dinfo = h.dinfo;
+    double *hth = h.theta;
+    double2 *hvz = h.V;
+    DKS_HIP(hipMemcpyAsync(hr, sv.rrout.p, sizeof(double2) * nrr, hipMemcpyDeviceToHost, x.st));
+    // X and H X of the next step (Z V[:, :n], HZ V) are queued before the host
+    // waits for the copies, so that the device works while the host reads the
+    // result.  They go to the half of the double buffer that the step does not
+    // read; after a failed Rayleigh-Ritz the retry queues them again.
+    if (!sv.rr_ev) DKS_HIP(hipEventCreateWithFlags(&sv.rr_ev, hipEventDisableTiming));
+    DKS_HIP(hipEventRecord(sv.rr_ev, x.st));
+    queue_xhx<T>(x, bk, s.cur, nz, n, d.V);
+    s.xhx_queued = true;
+    DKS_HIP(hipEventSynchronize(sv.rr_ev));
     if (log_enabled())
       std::fprintf(stderr,
                    "{\"prec\": %d, \"nz\": %d, \"n\": %d, \"m\": %d, \"mp\": %d, \"kept\": %d, "
@@ -334,9 +375,9 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
   Solver &sv = *x.sv;
   const int nz = n + s.m + s.mp;
   const int nxt = 1 - s.cur;
-  gemm_up2<T>(bk.Z[s.cur].template as<cplx<T>>(), bk.HZ[s.cur].template as<cplx<T>>(),
-              sv.off.as<int64_t>(), nz, sv.Vz.as<double2>(), n, n, bk.K, bk.z(nxt, 0),
-              bk.hz(nxt, 0), bk.K, 0.0, x.st);
+  if (!s.xhx_queued)
+    queue_xhx<T>(x, bk, s.cur, nz, n, rr_view(sv.rrout.as<double2>(), n).V);
+  s.xhx_queued = false;
   sv.lam.ensure(sizeof(double) * n);
   double *hl = sv.h_lam.as<double>(n);
   std::copy(s.lam.begin(), s.lam.end(), hl);
@@ -415,6 +456,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   s.m = 0;
   s.mp = 0;
   s.converged = false;
+  s.xhx_queued = false;
   // initial filtering of the start block
   if (filt)
     for (int k = 0; k < n_init; ++k) filter_inplace<T>(x, bk.z(0, 0), bk.W.template as<cplx<T>>(), n);
