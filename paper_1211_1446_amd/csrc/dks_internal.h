@@ -360,5 +360,14 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
                    DevBuf &scratch, hipStream_t st, long long *tstamp = nullptr,
                    const int *skip = nullptr);
+// The same in two parts, for a caller that has S before A: rayleigh_ritz_s
+// (scaling, Cholesky with dropping, L^-1: S only) and, on the same scratch,
+// rayleigh_ritz_a (the scaled A and everything after); the second must be
+// ordered after the first.
+void rayleigh_ritz_s(const double2 *S, int nz, int nkeep, double drop_tol, const int *forced_drop,
+                     int *info, double *dinfo, DevBuf &scratch, hipStream_t st);
+void rayleigh_ritz_a(const double2 *A, int nz, int nkeep, double floor_val, const int *forced_drop,
+                     double2 *V, double *theta, int *info, double *dinfo, DevBuf &scratch,
+                     hipStream_t st);
 
 }  // namespace dks

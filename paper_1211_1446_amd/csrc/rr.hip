@@ -24,6 +24,11 @@
 //      group of lanes while all reflectors are applied.
 // Triangular factors and the Hermitian working matrix are packed lower
 // triangles in LDS when n_Z <= 120, else full rows in the global scratch area.
+// A caller that has S before A runs steps 1-3 without A (rayleigh_ritz_s:
+// k_rr_reduce phase 2) on a stream of its own, and the rest after A is there
+// (rayleigh_ritz_a: k_rr_scale_a forms D A D, then steps 3-7 as above).  The
+// unbatched solver does so: S = Z^H Z is complete once Y is filtered, and the
+// one-workgroup S phase then runs beside the application of H to Y.
 #include <algorithm>
 #include <cfloat>
 #include <mutex>
@@ -822,9 +827,11 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     double drop_tol, const int *__restrict__ forced, int *__restrict__ info,
     double *__restrict__ dinfo, RRScratch W, long long *__restrict__ tstamp,
     const int *__restrict__ skip) {
-  // a finished system of a graph-captured batch: status 3 makes every later
+  // phase 0: scaling, Cholesky and L^-1 (and the scaled A); phase 2: the same
+  // without A, which k_rr_scale_a forms once A is there; phase 1: the rest.
+  // A finished system of a graph-captured batch: status 3 makes every later
   // Rayleigh-Ritz kernel of the call return at once
-  if (phase == 0 && skip && *skip) {
+  if (phase != 1 && skip && *skip) {
     if (threadIdx.x == 0) {
       info[0] = 0;
       info[1] = 3;
@@ -839,7 +846,7 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
   do {                  \
     if (tstamp && threadIdx.x == 0) tstamp[k] = wall_clock64(); \
   } while (0)
-  if (phase == 0) DKS_RR_STAMP(0);
+  if (phase != 1) DKS_RR_STAMP(0);
   // ---- LDS arena (sized by nz): partial sums, per-index arrays, then the
   // packed triangle or the GEMM tiles
   const int na = (nz + 1) & ~1;
@@ -914,8 +921,10 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
     for (int j = tid & 63; j < nz; j += 64) {
       const size_t e = (size_t)i * nz + j;
       const double f = di * dsc[j];
-      const double2 a1 = Ain[e], a2 = Ain[(size_t)j * nz + i];
-      Am[e] = make_double2(0.5 * f * (a1.x + a2.x), 0.5 * f * (a1.y - a2.y));
+      if (phase == 0) {
+        const double2 a1 = Ain[e], a2 = Ain[(size_t)j * nz + i];
+        Am[e] = make_double2(0.5 * f * (a1.x + a2.x), 0.5 * f * (a1.y - a2.y));
+      }
       if (j <= i) {
         const double2 s1 = Sin[e], s2 = Sin[(size_t)j * nz + i];
         const double2 h = make_double2(0.5 * f * (s1.x + s2.x), 0.5 * f * (s1.y - s2.y));
@@ -974,6 +983,22 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_reduce(
   DKS_RR_STAMP(3);
 
 #undef DKS_RR_STAMP
+}
+
+// ---- 1b. the scaled Hermitian part of A, D (A + A^H) D / 2, for a Rayleigh-Ritz
+// whose S phase ran without A (phase 2); one wave per row, D from that phase
+__global__ void __launch_bounds__(256) k_rr_scale_a(const double2 *__restrict__ Ain, int nz,
+                                                    const int *__restrict__ info, RRScratch W) {
+  if (info[1]) return;   // the S phase found too few independent columns
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nz) return;
+  const double di = W.dsc[i];
+  for (int j = threadIdx.x & 63; j < nz; j += 64) {
+    const size_t e = (size_t)i * nz + j;
+    const double f = di * W.dsc[j];
+    const double2 a1 = Ain[e], a2 = Ain[(size_t)j * nz + i];
+    W.Am[e] = make_double2(0.5 * f * (a1.x + a2.x), 0.5 * f * (a1.y - a2.y));
+  }
 }
 
 // ---- 3b. the two products of C = Li (D A D)_kept Li^H, one 64 x 64 output tile
@@ -1380,13 +1405,49 @@ static size_t rr_vec_lds_bytes(int nz) {
 
 size_t rr_scratch_bytes(int nz, int nkeep) { return RRScratch::bytes(nz, nkeep); }
 
+static void rr_set_attributes();
+static void rr_finish(const double2 *A, int nz, int nkeep, double floor_val,
+                      const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
+                      const RRScratch &W, hipStream_t st, long long *tstamp, const int *skip,
+                      bool scale_a);
+
 void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double drop_tol,
                    double floor_val, const int *forced_drop, double2 *V, double *theta, int *info,
                    double *dinfo, DevBuf &scratch, hipStream_t st, long long *tstamp,
                    const int *skip) {
   DKS_REQUIRE(nz > 0 && nz <= kRRMax && nkeep > 0 && nkeep <= nz, DKS_EINVAL,
               "Rayleigh-Ritz size out of range (subspace dimension must be <= 512)");
-  // once per process, also when batch lanes arrive here together
+  rr_set_attributes();
+  scratch.ensure(RRScratch::bytes(nz, nkeep));
+  const RRScratch W = RRScratch::at(scratch.p, nz, nkeep);
+  DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 0, A, S,
+             nz, nkeep, drop_tol, forced_drop, info, dinfo, W, tstamp, skip);
+  DKS_HIP(hipGetLastError());
+  rr_finish(A, nz, nkeep, floor_val, forced_drop, V, theta, info, dinfo, W, st, tstamp, skip, false);
+}
+
+void rayleigh_ritz_s(const double2 *S, int nz, int nkeep, double drop_tol, const int *forced_drop,
+                     int *info, double *dinfo, DevBuf &scratch, hipStream_t st) {
+  DKS_REQUIRE(nz > 0 && nz <= kRRMax && nkeep > 0 && nkeep <= nz, DKS_EINVAL,
+              "Rayleigh-Ritz size out of range (subspace dimension must be <= 512)");
+  rr_set_attributes();
+  scratch.ensure(RRScratch::bytes(nz, nkeep));
+  const RRScratch W = RRScratch::at(scratch.p, nz, nkeep);
+  DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 2,
+             nullptr, S, nz, nkeep, drop_tol, forced_drop, info, dinfo, W, nullptr, nullptr);
+  DKS_HIP(hipGetLastError());
+}
+
+void rayleigh_ritz_a(const double2 *A, int nz, int nkeep, double floor_val, const int *forced_drop,
+                     double2 *V, double *theta, int *info, double *dinfo, DevBuf &scratch,
+                     hipStream_t st) {
+  const RRScratch W = RRScratch::at(scratch.p, nz, nkeep);
+  rr_finish(A, nz, nkeep, floor_val, forced_drop, V, theta, info, dinfo, W, st, nullptr, nullptr,
+            true);
+}
+
+// kernel attributes, once per process (also when batch lanes arrive together)
+static void rr_set_attributes() {
   static std::once_flag attr;
   hipError_t attr_rc = hipSuccess;
   std::call_once(attr, [&] {
@@ -1404,11 +1465,20 @@ void rayleigh_ritz(const double2 *A, const double2 *S, int nz, int nkeep, double
     }
   });
   DKS_HIP(attr_rc);
-  scratch.ensure(RRScratch::bytes(nz, nkeep));
-  const RRScratch W = RRScratch::at(scratch.p, nz, nkeep);
-  DKS_LAUNCH("k_rr_reduce", k_rr_reduce, dim3(1), dim3(kRRThreads), rr_lds_bytes(nz), st, 0, A, S,
-             nz, nkeep, drop_tol, forced_drop, info, dinfo, W, tstamp, skip);
-  DKS_HIP(hipGetLastError());
+}
+
+// everything after the S phase: [the scaled A,] the two products, the
+// tridiagonal reduction, eigenvalues, eigenvectors
+static void rr_finish(const double2 *A, int nz, int nkeep, double floor_val,
+                      const int *forced_drop, double2 *V, double *theta, int *info, double *dinfo,
+                      const RRScratch &W, hipStream_t st, long long *tstamp, const int *skip,
+                      bool scale_a) {
+  const double2 *S = nullptr;   // phase 1 reads neither input matrix
+  const double drop_tol = 0.0;
+  if (scale_a) {
+    DKS_LAUNCH("k_rr_scale_a", k_rr_scale_a, dim3((nz + 3) / 4), dim3(256), 0, st, A, nz, info, W);
+    DKS_HIP(hipGetLastError());
+  }
   const unsigned tiles = (unsigned)((nz + kGT - 1) / kGT);
   for (int which = 1; which <= 2; ++which) {
     DKS_LAUNCH("k_rr_gemm", k_rr_gemm, dim3(tiles, tiles), dim3(kRRThreads), 0, st, which, nz, info, W);

@@ -87,11 +87,18 @@ struct Solver {
   HostBuf h_rr, h_lam, h_res, h_act, h_vp;
   Workspace ws;   // H.X scratch of this solver's applies
   hipEvent_t rr_ev = nullptr;   // the Rayleigh-Ritz result has reached the host
+  // second stream (default priority) for the S phase of the Rayleigh-Ritz,
+  // which runs beside the application of H to Y; its two events
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_s = nullptr, ev_p0 = nullptr;
   Solver() = default;
   Solver(const Solver &) = delete;
   Solver &operator=(const Solver &) = delete;
   ~Solver() {
     if (rr_ev) (void)hipEventDestroy(rr_ev);
+    if (ev_s) (void)hipEventDestroy(ev_s);
+    if (ev_p0) (void)hipEventDestroy(ev_p0);
+    if (st2) (void)hipStreamDestroy(st2);
   }
 };
 
@@ -166,6 +173,7 @@ struct Ctx {
   int iter_slot = 0, iter_cap = 0;   // entries written to / capacity of opts.iter_ms
   double floor = -1e300;              // Ritz values below are discarded (mid-gap -c^2 with F)
   bool bf16_gram = false;             // reduced-precision stage: Gram products from BF16 inputs
+  bool split_rr = false;              // S half of the Rayleigh-Ritz beside H Y (unbatched solves)
 };
 
 // Row offsets of Z = [rows 0..n) U [n, n+m) U [2n, 2n+mp) of a 3n-row block.
@@ -242,6 +250,7 @@ template <typename T> struct LoopState {
   double min_piv = 1.0;   // smallest Cholesky pivot of the last Rayleigh-Ritz basis
   int dropped = 0;   // directions the last Rayleigh-Ritz removed as dependent
   bool xhx_queued = false;   // the last Rayleigh-Ritz queued X, H X of the next step
+  int s_nz = 0;              // subspace size of an S half queued ahead of H Y (0: none)
 };
 
 // X_new = Z V[:, :n], HX_new = HZ V into the other half of the double buffer.
@@ -272,6 +281,37 @@ static RRView rr_view(double2 *base, int n) {
   return v;
 }
 
+// The S half of the next Rayleigh-Ritz, queued before H Y: Z = [X, Y, P] is
+// complete once Y is filtered, and S = Z^H Z with its scaling, Cholesky and
+// L^-1 needs nothing else.  The S product runs on the solver's stream; the
+// one-workgroup S phase runs on the second stream, beside the application of
+// H to Y, and ritz() waits for it before the A half.
+template <typename T>
+static void queue_s_half(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol) {
+  Solver &sv = *x.sv;
+  const int nz = n + s.m + s.mp;
+  sv.off.ensure(sizeof(int64_t) * 3 * n);
+  DKS_LAUNCH("k_offsets", k_offsets, dim3((nz + 255) / 256), dim3(256), 0, x.st, sv.off.as<int64_t>(),
+             n, s.m, s.mp, bk.K);
+  DKS_HIP(hipGetLastError());
+  sv.gS.ensure(sizeof(double2) * nz * nz);
+  sv.gA.ensure(sizeof(double2) * nz * nz);
+  gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+             bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
+             sv.gS.as<double2>(), nullptr, nz, sv.part, x.st, /*hermitian=*/true);
+  if (!sv.st2) DKS_HIP(hipStreamCreateWithFlags(&sv.st2, hipStreamNonBlocking));
+  if (!sv.ev_s) DKS_HIP(hipEventCreateWithFlags(&sv.ev_s, hipEventDisableTiming));
+  if (!sv.ev_p0) DKS_HIP(hipEventCreateWithFlags(&sv.ev_p0, hipEventDisableTiming));
+  const size_t nrr = rr_count(nz, n);
+  sv.rrout.ensure(sizeof(double2) * nrr);
+  const RRView d = rr_view(sv.rrout.as<double2>(), n);
+  DKS_HIP(hipEventRecord(sv.ev_s, x.st));
+  DKS_HIP(hipStreamWaitEvent(sv.st2, sv.ev_s, 0));
+  rayleigh_ritz_s(sv.gS.as<double2>(), nz, n, drop_tol, nullptr, d.info, d.dinfo, sv.rrs, sv.st2);
+  DKS_HIP(hipEventRecord(sv.ev_p0, sv.st2));
+  s.s_nz = nz;
+}
+
 // Rayleigh-Ritz on Z_cur rows described by (n, m, mp); returns false when
 // fewer than n directions survive even without P.
 template <typename T>
@@ -281,41 +321,56 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
   int mp = s.mp;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int nz = n + s.m + mp;
-    sv.off.ensure(sizeof(int64_t) * 3 * n);
-    DKS_LAUNCH("k_offsets", k_offsets, dim3((nz + 255) / 256), dim3(256), 0, x.st, sv.off.as<int64_t>(),
-                       n, s.m, mp, bk.K);
-    DKS_HIP(hipGetLastError());
-    sv.gS.ensure(sizeof(double2) * nz * nz);
-    sv.gA.ensure(sizeof(double2) * nz * nz);
-    if constexpr (std::is_same<T, float>::value) {
-      if (x.bf16_gram) {
-        gemm_ip_bf16(bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz,
-                     bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz,
-                     bk.HZ[s.cur].template as<float2>(), bk.K, sv.gS.as<double2>(),
+    // S = Z^H Z and the S phase were queued ahead of H Y (queue_s_half)
+    const bool s_ready = attempt == 0 && s.s_nz == nz;
+    s.s_nz = 0;
+    if (s_ready) {
+      gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+                 bk.HZ[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
+                 sv.gA.as<double2>(), nullptr, nz, sv.part, x.st, /*hermitian=*/true);
+    } else {
+      sv.off.ensure(sizeof(int64_t) * 3 * n);
+      DKS_LAUNCH("k_offsets", k_offsets, dim3((nz + 255) / 256), dim3(256), 0, x.st, sv.off.as<int64_t>(),
+                         n, s.m, mp, bk.K);
+      DKS_HIP(hipGetLastError());
+      sv.gS.ensure(sizeof(double2) * nz * nz);
+      sv.gA.ensure(sizeof(double2) * nz * nz);
+      if constexpr (std::is_same<T, float>::value) {
+        if (x.bf16_gram) {
+          gemm_ip_bf16(bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz,
+                       bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz,
+                       bk.HZ[s.cur].template as<float2>(), bk.K, sv.gS.as<double2>(),
+                       sv.gA.as<double2>(), nz, sv.part, x.st, /*hermitian=*/true);
+        } else {
+          gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+                     bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+                     bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(),
                      sv.gA.as<double2>(), nz, sv.part, x.st, /*hermitian=*/true);
+        }
       } else {
         gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
                    bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
                    bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(),
                    sv.gA.as<double2>(), nz, sv.part, x.st, /*hermitian=*/true);
       }
-    } else {
-      gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
-                 bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
-                 bk.HZ[s.cur].template as<cplx<T>>(), bk.K, sv.gS.as<double2>(),
-                 sv.gA.as<double2>(), nz, sv.part, x.st, /*hermitian=*/true);
     }
     const size_t nrr = rr_count(nz, n);
     sv.rrout.ensure(sizeof(double2) * nrr);
     const RRView d = rr_view(sv.rrout.as<double2>(), n);
-    const bool stamps = log_enabled();
+    const bool stamps = log_enabled() && !s_ready;
     if (stamps) sv.tst.ensure(sizeof(long long) * kRRStamps);
     // BF16-split Gram products carry relative errors of a few 1e-6: directions
     // whose scaled overlap pivot is not well above that are dropped
     const double dtol = (sizeof(T) == 4 && x.bf16_gram) ? std::max(drop_tol, kBf16DropTol) : drop_tol;
-    rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, dtol, x.floor, nullptr, d.V,
-                  d.theta, d.info, d.dinfo, sv.rrs, x.st,
-                  stamps ? sv.tst.as<long long>() : nullptr);
+    if (s_ready) {
+      DKS_HIP(hipStreamWaitEvent(x.st, sv.ev_p0, 0));
+      rayleigh_ritz_a(sv.gA.as<double2>(), nz, n, x.floor, nullptr, d.V, d.theta, d.info, d.dinfo,
+                      sv.rrs, x.st);
+    } else {
+      rayleigh_ritz(sv.gA.as<double2>(), sv.gS.as<double2>(), nz, n, dtol, x.floor, nullptr, d.V,
+                    d.theta, d.info, d.dinfo, sv.rrs, x.st,
+                    stamps ? sv.tst.as<long long>() : nullptr);
+    }
     if (stamps) {
       // reduction phases: scaling, Cholesky, L^-1, products + Hermitian part,
       // tridiagonal reduction (stamps 0-5 of k_rr_reduce)
@@ -457,6 +512,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
   s.mp = 0;
   s.converged = false;
   s.xhx_queued = false;
+  s.s_nz = 0;
   // initial filtering of the start block
   if (filt)
     for (int k = 0; k < n_init; ++k) filter_inplace<T>(x, bk.z(0, 0), bk.W.template as<cplx<T>>(), n);
@@ -535,6 +591,8 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     }
     // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
+    if (x.split_rr && !(sizeof(T) == 4 && x.bf16_gram) && !log_enabled())
+      queue_s_half<T>(x, bk, s, n, drop_tol);
     apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st, x.sv->ws, x.ncomp);
     if (x.info) x.info->h_applies += m;
     // Rayleigh-Ritz on Z = [X, Y, P]
@@ -778,7 +836,8 @@ static dks_status run_davidson(Ctx &x, Blocks<double> &bk, LoopState<double> &s,
 // status and, for a nonzero one, its message.  Throws dks::Error on failures.
 static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *lambda,
                             double *resnorms, const dks_solve_opts &o, dks_solve_info *info,
-                            hipStream_t st, Solver *sv, std::string &msg) {
+                            hipStream_t st, Solver *sv, std::string &msg,
+                            bool split_rr = false) {
   {
     const System &s = *b->sys[sys];
     DKS_REQUIRE(o.model == DKS_MODEL_DKS || o.model == DKS_MODEL_KSSO, DKS_EINVAL, "bad model");
@@ -800,6 +859,7 @@ static dks_status solve_one(dks_basis *b, int sys, int n, double2 *Xu, double *l
     x.N = s.N;
     x.ncomp = ncomp;
     x.K = ncomp * (int64_t)s.N;
+    x.split_rr = split_rr;
     // the KSSO operator is solved by standard LOBPCG (the paper's comparison):
     // no filter, no kinetic balance, and (no negative band) the breakdown guard on
     x.filt = o.use_filter != 0 && ncomp == 4;
@@ -1676,7 +1736,8 @@ dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lamb
     DKS_HIP(hipSetDevice(b->device));
     std::string msg;
     const dks_status rc = solve_one(b, sys, n, (double2 *)X, lambda, resnorms, o, info,
-                                    (hipStream_t)stream, &solvers_of(b)->main, msg);
+                                    (hipStream_t)stream, &solvers_of(b)->main, msg,
+                                    /*split_rr=*/true);
     if (rc != DKS_OK) set_error(msg);
     return rc;
   });
