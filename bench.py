@@ -346,8 +346,11 @@ def main():
                             (dk.MODE_MIXED_FP32, "f32", FP32_PEAK_TFLOPS),
                             (dk.MODE_MIXED_BF16GRAM, "bf16", BF16_PEAK_TFLOPS)):
         a, c = profiled(mode, 2), profiled(mode, 8)
+        # the Gram pair S = Z^H Z, A = Z^H H Z: one fused launch (BF16-split), or
+        # S and A as launches of their own (the unbatched solver forms S before
+        # H Y): its flops are per iteration and shared among the launches seen
         per_it = {
-            f"k_gemm_ip.gram.{sfx}": (1, 8.0 * 2 * ip_pairs(nz) * K4),
+            f"k_gemm_ip.gram.{sfx}": (None, 8.0 * 2 * ip_pairs(nz) * K4),
             # X and H X (m = n_Z rows), P and H P (2n rows): one paired launch each
             f"k_gemm_up.{sfx}": (2, 8.0 * K4 * n * (2 * nz + 2 * (2 * n)) / 2),
             f"k_gemm_ip.{sfx}": (3, 8.0 * nproj * 4 * n * N),
@@ -361,6 +364,8 @@ def main():
             if cnt <= 0 or tot <= 0:
                 continue
             ms = tot / cnt
+            if launches is None:
+                flops = flops / (cnt / 6.0)
             tf = flops / (ms * 1e-3) / 1e12
             kp = peak if sfx != "bf16" or "gram" in kname else FP32_PEAK_TFLOPS
             mk[kname] = {"avg_ms": ms, "launches_per_iteration": cnt / 6.0,
