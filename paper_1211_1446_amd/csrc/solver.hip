@@ -84,6 +84,7 @@ struct Solver {
   DevBuf gS, gA, Vz, Vp, Wxp, theta, lam, norms, lockmask, pE, rinfo, rdinfo, off, idx, forced, rrs,
       part, part2, tst;
   DevBuf rrout;   // Rayleigh-Ritz result laid out as its host copy h_rr
+  DevBuf part_s;  // split-K partial sums of S formed on the second stream
   HostBuf h_rr, h_lam, h_res, h_act, h_vp;
   Workspace ws;   // H.X scratch of this solver's applies
   hipEvent_t rr_ev = nullptr;   // the Rayleigh-Ritz result has reached the host
@@ -283,9 +284,9 @@ static RRView rr_view(double2 *base, int n) {
 
 // The S half of the next Rayleigh-Ritz, queued before H Y: Z = [X, Y, P] is
 // complete once Y is filtered, and S = Z^H Z with its scaling, Cholesky and
-// L^-1 needs nothing else.  The S product runs on the solver's stream; the
-// one-workgroup S phase runs on the second stream, beside the application of
-// H to Y, and ritz() waits for it before the A half.
+// L^-1 needs nothing else.  The S product (with partial sums of its own) and
+// the one-workgroup S phase run on the second stream, beside the application
+// of H to Y, and ritz() waits for them before the A half.
 template <typename T>
 static void queue_s_half(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol) {
   Solver &sv = *x.sv;
@@ -296,9 +297,7 @@ static void queue_s_half(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double d
   DKS_HIP(hipGetLastError());
   sv.gS.ensure(sizeof(double2) * nz * nz);
   sv.gA.ensure(sizeof(double2) * nz * nz);
-  gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
-             bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
-             sv.gS.as<double2>(), nullptr, nz, sv.part, x.st, /*hermitian=*/true);
+  sv.part_s.ensure(sizeof(double2) * gemm_ip_part_elems(nz, nz, bk.K, false, true));
   if (!sv.st2) DKS_HIP(hipStreamCreateWithFlags(&sv.st2, hipStreamNonBlocking));
   if (!sv.ev_s) DKS_HIP(hipEventCreateWithFlags(&sv.ev_s, hipEventDisableTiming));
   if (!sv.ev_p0) DKS_HIP(hipEventCreateWithFlags(&sv.ev_p0, hipEventDisableTiming));
@@ -307,6 +306,9 @@ static void queue_s_half(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double d
   const RRView d = rr_view(sv.rrout.as<double2>(), n);
   DKS_HIP(hipEventRecord(sv.ev_s, x.st));
   DKS_HIP(hipStreamWaitEvent(sv.st2, sv.ev_s, 0));
+  gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+             bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
+             sv.gS.as<double2>(), nullptr, nz, sv.part_s, sv.st2, /*hermitian=*/true);
   rayleigh_ritz_s(sv.gS.as<double2>(), nz, n, drop_tol, nullptr, d.info, d.dinfo, sv.rrs, sv.st2);
   DKS_HIP(hipEventRecord(sv.ev_p0, sv.st2));
   s.s_nz = nz;
