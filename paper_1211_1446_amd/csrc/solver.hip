@@ -306,10 +306,23 @@ static void queue_s_half(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double d
   const RRView d = rr_view(sv.rrout.as<double2>(), n);
   DKS_HIP(hipEventRecord(sv.ev_s, x.st));
   DKS_HIP(hipStreamWaitEvent(sv.st2, sv.ev_s, 0));
-  gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
-             bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
-             sv.gS.as<double2>(), nullptr, nz, sv.part_s, sv.st2, /*hermitian=*/true);
-  rayleigh_ritz_s(sv.gS.as<double2>(), nz, n, drop_tol, nullptr, d.info, d.dinfo, sv.rrs, sv.st2);
+  double dtol = drop_tol;
+  bool bf16 = false;
+  if constexpr (std::is_same<T, float>::value) {
+    if (x.bf16_gram) {
+      // the BF16-split product, and its wider drop tolerance (see ritz)
+      gemm_ip_bf16(bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz,
+                   bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
+                   sv.gS.as<double2>(), nullptr, nz, sv.part_s, sv.st2, /*hermitian=*/true);
+      dtol = std::max(drop_tol, kBf16DropTol);
+      bf16 = true;
+    }
+  }
+  if (!bf16)
+    gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+               bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
+               sv.gS.as<double2>(), nullptr, nz, sv.part_s, sv.st2, /*hermitian=*/true);
+  rayleigh_ritz_s(sv.gS.as<double2>(), nz, n, dtol, nullptr, d.info, d.dinfo, sv.rrs, sv.st2);
   DKS_HIP(hipEventRecord(sv.ev_p0, sv.st2));
   s.s_nz = nz;
 }
@@ -327,9 +340,19 @@ static bool ritz(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, double drop_tol,
     const bool s_ready = attempt == 0 && s.s_nz == nz;
     s.s_nz = 0;
     if (s_ready) {
-      gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
-                 bk.HZ[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
-                 sv.gA.as<double2>(), nullptr, nz, sv.part, x.st, /*hermitian=*/true);
+      bool bf16 = false;
+      if constexpr (std::is_same<T, float>::value) {
+        if (x.bf16_gram) {
+          gemm_ip_bf16(bk.Z[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz,
+                       bk.HZ[s.cur].template as<float2>(), sv.off.as<int64_t>(), nz, nullptr,
+                       bk.K, sv.gA.as<double2>(), nullptr, nz, sv.part, x.st, /*hermitian=*/true);
+          bf16 = true;
+        }
+      }
+      if (!bf16)
+        gemm_ip<T>(bk.Z[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz,
+                   bk.HZ[s.cur].template as<cplx<T>>(), sv.off.as<int64_t>(), nz, nullptr, bk.K,
+                   sv.gA.as<double2>(), nullptr, nz, sv.part, x.st, /*hermitian=*/true);
     } else {
       sv.off.ensure(sizeof(int64_t) * 3 * n);
       DKS_LAUNCH("k_offsets", k_offsets, dim3((nz + 255) / 256), dim3(256), 0, x.st, sv.off.as<int64_t>(),
@@ -593,7 +616,7 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     }
     // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
-    if (x.split_rr && !(sizeof(T) == 4 && x.bf16_gram) && !log_enabled())
+    if (x.split_rr && !log_enabled())
       queue_s_half<T>(x, bk, s, n, drop_tol);
     apply_h<T>(x.b, x.sys, bk.z(s.cur, n), bk.hz(s.cur, n), m, 0.0, 1.0, x.st, x.sv->ws, x.ncomp);
     if (x.info) x.info->h_applies += m;
