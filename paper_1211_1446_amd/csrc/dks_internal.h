@@ -271,12 +271,15 @@ void apply_h_on(dks_basis *b, int sys, const cplx<T> *X, cplx<T> *HX, int nb, do
 // Y <- T Y in place for m spinors (the Teter preconditioner of Algorithm 1 on
 // the spectral projectors of each planewave's free Dirac block; two
 // components: the plain factor).  part: device scratch of
-// m * kTpaMaxBlocks double2 (partial sums of the per-column energies).
+// m * kTpaMaxBlocks double2 (partial sums of the per-column energies).  With
+// `src` (and `idx`, device, m rows): Y row j <- T src row idx[j], the gather
+// of the active residuals folded in (src must not overlap Y).
 constexpr int kTpaMaxBlocks = 64;
 int tpa_blocks(int N);
 template <typename T>
 void precondition(dks_basis *b, int sys, cplx<T> *Y, int m, hipStream_t st, int ncomp,
-                  double2 *part, const int *skip = nullptr);
+                  double2 *part, const int *skip = nullptr, const cplx<T> *src = nullptr,
+                  const int *idx = nullptr);
 
 // out[i][j] = sum_k conj(A_i[k]) B_j[k] (+ the same with B2 into out2), FP64 result,
 // rows addressed by element offsets.  M, Nn <= 512.  `hermitian` (A and B the same

@@ -817,11 +817,12 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_tpa_energy(const cplx<T> *__restrict__ Y, int N,
                                                     const T *__restrict__ q, T c, int ncomp,
                                                     double2 *__restrict__ part,
-                                                    const int *__restrict__ skip) {
+                                                    const int *__restrict__ skip,
+                                                    const int *__restrict__ idx) {
   if (skip && *skip) return;
   using C = cplx<T>;
   const int j = blockIdx.y;
-  const C *y = Y + (size_t)j * ncomp * N;
+  const C *y = Y + (size_t)(idx ? idx[j] : j) * ncomp * N;
   double num = 0, den = 0;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
     const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
@@ -859,10 +860,12 @@ __global__ void __launch_bounds__(256) k_tpa_energy(const cplx<T> *__restrict__ 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_tpa_apply(cplx<T> *__restrict__ Y, int N,
+// Src row idx[j] (or j) in, Y row j out: the two coincide in place
+__global__ void __launch_bounds__(256) k_tpa_apply(const cplx<T> *Src, cplx<T> *Y, int N,
                                                    const T *__restrict__ q, T c, int ncomp,
                                                    const double2 *__restrict__ part, int nblk,
-                                                   const int *__restrict__ skip) {
+                                                   const int *__restrict__ skip,
+                                                   const int *__restrict__ idx) {
   if (skip && *skip) return;
   using C = cplx<T>;
   const int j = blockIdx.y;
@@ -884,10 +887,11 @@ __global__ void __launch_bounds__(256) k_tpa_apply(cplx<T> *__restrict__ Y, int 
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   C *y = Y + (size_t)j * ncomp * N;
+  const C *src = Src + (size_t)(idx ? idx[j] : j) * ncomp * N;
   const T ie = T(1.0 / sE);
   const T qx = q[g], qy = q[N + g], qz = q[2 * N + g];
   if (ncomp == 4) {
-    const C v[4] = {y[g], y[N + g], y[2 * N + g], y[3 * N + g]};
+    const C v[4] = {src[g], src[N + g], src[2 * N + g], src[3 * N + g]};
     C pp[4];
     T ep, em;
     tpa_split<T>(v, qx, qy, qz, c, pp, ep, em);
@@ -897,7 +901,7 @@ __global__ void __launch_bounds__(256) k_tpa_apply(cplx<T> *__restrict__ Y, int 
       y[(size_t)a * N + g] = C{kp * pp[a].x + km * (v[a].x - pp[a].x), kp * pp[a].y + km * (v[a].y - pp[a].y)};
   } else {
     const T k = tpa_factor<T>(T(0.5) * (qx * qx + qy * qy + qz * qz) * ie);
-    const C a = y[g], b = y[N + g];
+    const C a = src[g], b = src[N + g];
     y[g] = C{k * a.x, k * a.y};
     y[N + g] = C{k * b.x, k * b.y};
   }
@@ -907,21 +911,25 @@ int tpa_blocks(int N) { return std::min(kTpaMaxBlocks, std::max(1, (N + 2047) / 
 
 template <typename T>
 void precondition(dks_basis *b, int sysi, cplx<T> *Y, int m, hipStream_t st, int ncomp,
-                  double2 *part, const int *skip) {
+                  double2 *part, const int *skip, const cplx<T> *src, const int *idx) {
   if (m <= 0) return;
   const System &s = *b->sys[sysi];
   const int nblk = tpa_blocks(s.N);
-  DKS_LAUNCH("k_tpa_energy", k_tpa_energy<T>, dim3(nblk, m), dim3(256), 0, st, Y, s.N, Qtab<T>(s),
-             (T)s.c, ncomp, part, skip);
+  if (!src) {
+    src = Y;
+    idx = nullptr;
+  }
+  DKS_LAUNCH("k_tpa_energy", k_tpa_energy<T>, dim3(nblk, m), dim3(256), 0, st, src, s.N,
+             Qtab<T>(s), (T)s.c, ncomp, part, skip, idx);
   DKS_HIP(hipGetLastError());
-  DKS_LAUNCH("k_tpa_apply", k_tpa_apply<T>, dim3((s.N + 255) / 256, m), dim3(256), 0, st, Y, s.N,
-             Qtab<T>(s), (T)s.c, ncomp, part, nblk, skip);
+  DKS_LAUNCH("k_tpa_apply", k_tpa_apply<T>, dim3((s.N + 255) / 256, m), dim3(256), 0, st, src, Y,
+             s.N, Qtab<T>(s), (T)s.c, ncomp, part, nblk, skip, idx);
   DKS_HIP(hipGetLastError());
 }
 template void precondition<double>(dks_basis *, int, double2 *, int, hipStream_t, int, double2 *,
-                                   const int *);
+                                   const int *, const double2 *, const int *);
 template void precondition<float>(dks_basis *, int, float2 *, int, hipStream_t, int, double2 *,
-                                  const int *);
+                                  const int *, const float2 *, const int *);
 
 // Plane form when none is set: the direct forms in FP64 (fewer LDS passes pay
 // where the LDS traffic is 16 bytes a point), the LDS-staged ones in FP32;

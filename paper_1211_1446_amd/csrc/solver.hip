@@ -609,10 +609,13 @@ static dks_status run_stage(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, int n
     int *ha = sv.h_act.as<int>(n);
     std::copy(s.act.begin(), s.act.end(), ha);
     DKS_HIP(hipMemcpyAsync(sv.idx.p, ha, sizeof(int) * m, hipMemcpyHostToDevice, x.st));
-    gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
     if (use_teter(*x.o)) {
+      // T reads the active rows of R itself (no separate gather)
       sv.pE.ensure(sizeof(double2) * n * kTpaMaxBlocks);
-      precondition<T>(x.b, x.sys, bk.z(s.cur, n), m, x.st, x.ncomp, sv.pE.as<double2>());
+      precondition<T>(x.b, x.sys, bk.z(s.cur, n), m, x.st, x.ncomp, sv.pE.as<double2>(), nullptr,
+                      bk.R.template as<cplx<T>>(), sv.idx.as<int>());
+    } else {
+      gather_rows<T>(bk.R.template as<cplx<T>>(), sv.idx.as<int>(), m, bk.K, bk.z(s.cur, n), x.st);
     }
     // the filtering step: Y = f(H) Y
     if (filt) filter_inplace<T>(x, bk.z(s.cur, n), bk.W.template as<cplx<T>>(), m);
