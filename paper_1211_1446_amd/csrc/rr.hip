@@ -411,16 +411,22 @@ struct TriWork {
 // rows k+1..r-1; the column below the subdiagonal keeps v for the
 // back-transformation.  With x = tau C22 v and q = v^H C22 v (real), the
 // two-sided update is C22 -= v w^H + w v^H, w = x - |tau|^2 q v / 2.  Per
-// reflector, three barriers: (b) x by row groups of all waves, and q's per-wave
-// partials; (c1) the update of the trailing matrix's first column, which also
-// sums that column's norm; (c2) waves 1-15 update the rest while wave 0 forms
-// the next reflector from the finished column (look-ahead: its scalar
-// arithmetic and the writing of v no longer stand between two barriers).
+// reflector, three barriers on full rows in global memory: (b) x by row
+// groups of all waves, and q's per-wave partials; (c1) the update of the
+// trailing matrix's first column, which also sums that column's norm; (c2)
+// waves 1-15 update the rest while wave 0 forms the next reflector from the
+// finished column (look-ahead: its scalar arithmetic and the writing of v no
+// longer stand between two barriers).  Packed in LDS, two: wave 0 does (c1)
+// itself, with the same sums, and goes on to the reflector.
 // Reflector vectors alternate between two LDS buffers, since wave 0 writes
 // v_{k+1} while the others still read v_k.
 template <typename Mat>
 __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
   constexpr int NW = kRRThreads / 64;
+  // packed (LDS, order <= 120) matrices: wave 0 takes the first column itself
+  // (one barrier fewer); full rows in global memory keep it on all threads
+  constexpr bool kFusedCol = std::is_same<Mat, PackedLower>::value;
+  static_assert(kRRPackedMax <= 128 && kRRThreads >= 128, "wave 0 covers the first column in two rows of lanes");
   constexpr int kUpRows = (kRRThreads - 64) / kRowG;                  // rows per pass, waves 1-15
   constexpr int kUpPasses = (kRRMax + kUpRows - 1) / kUpRows;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -428,11 +434,8 @@ __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
   const int rlu = (tid - 64) / kRowG;   // row of waves 1-15 in the update
   // reflector k from column k (its norm below the subdiagonal in w.nred), by
   // wave 0: tau, beta and the diagonal entry to LDS, v into w.vv[k & 1] and M
-  auto reflector = [&](int k) {
+  auto reflector = [&](int k, double xn2) {
     const int m = r - k - 1;
-    double xn2 = 0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) xn2 += w.nred[q];
     const double2 alpha = M.lo(k + 1, k);
     double2 tau = make_double2(0, 0), scal = make_double2(0, 0);
     double beta = alpha.x;
@@ -466,7 +469,13 @@ __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
     if (lane == 0) w.nred[wid] = x;
     __syncthreads();
   }
-  if (r >= 2 && wid == 0) reflector(0);
+  auto nred_sum = [&]() {
+    double xn2 = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) xn2 += w.nred[q];
+    return xn2;
+  };
+  if (r >= 2 && wid == 0) reflector(0, nred_sum());
   __syncthreads();
   for (int k = 0; k + 1 < r; ++k) {
     const int m = r - k - 1;   // trailing size, rows/cols k+1..r-1
@@ -514,28 +523,20 @@ __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
     for (int p = 0; p < NW; ++p) q += w.qred[p];
     const double al = -0.5 * (tau.x * tau.x + tau.y * tau.y) * q;
     auto wv = [&](int i) { return zadd(w.xv[i], zscale(vv[i], al)); };
-    // (c1) first column of the trailing matrix (local column 0) and its norm
-    // below the subdiagonal: the next reflector's input
-    {
-      const double2 v0 = vv[0], w0 = wv(0);
-      double nx = 0;
-      for (int ii = tid; ii < m; ii += nt) {
-        const double2 vi = vv[ii], wi = wv(ii);
-        double2 c = M.lo(k + 1 + ii, k + 1);
-        c = zsub(c, zadd(zmul(vi, zconj(w0)), zmul(wi, zconj(v0))));
-        if (ii == 0) c.y = 0.0;
-        M.set(k + 1 + ii, k + 1, c);
-        if (ii >= 2) nx += c.x * c.x + c.y * c.y;
-      }
-      nx = wave_sum(nx);
-      if (lane == 0) w.nred[wid] = nx;
-    }
-    __syncthreads();
-    // (c2) the rest of the update (local columns 1..), waves 1-15, row groups
-    // over 1 <= j <= i; meanwhile wave 0 forms the next reflector
-    if (wid == 0) {
-      if (k + 2 < r) reflector(k + 1);
-    } else {
+    // one element of the update of the trailing matrix's first column (local
+    // column 0) and its share of that column's norm below the subdiagonal
+    const double2 v0 = vv[0], w0 = wv(0);
+    auto col0 = [&](int ii) {
+      const double2 vi = vv[ii], wi = wv(ii);
+      double2 c = M.lo(k + 1 + ii, k + 1);
+      c = zsub(c, zadd(zmul(vi, zconj(w0)), zmul(wi, zconj(v0))));
+      if (ii == 0) c.y = 0.0;
+      M.set(k + 1 + ii, k + 1, c);
+      return ii >= 2 ? c.x * c.x + c.y * c.y : 0.0;
+    };
+    // the rest of the update (local columns 1..), waves 1-15, row groups over
+    // 1 <= j <= i
+    auto update_rest = [&]() {
 #pragma unroll
       for (int p = 0; p < kUpPasses; ++p) {
         const int ii = p * kUpRows + rlu;
@@ -554,8 +555,44 @@ __device__ void tridiagonalise(const Mat M, int r, TriWork w) {
           }
         }
       }
+    };
+    if constexpr (kFusedCol) {
+      // (c) wave 0 updates the first column (m <= 119: rows lane and 64 +
+      // lane), sums its norm exactly as the per-wave partials of (c1) below
+      // would (the same lanes, the same reductions, added in wave order) and
+      // forms the next reflector from the values its lanes have just written
+      // (the fence orders them); meanwhile waves 1-15 update the rest.  Two
+      // barriers per reflector, the same numbers as three.
+      if (wid == 0) {
+        const double p0 = wave_sum(lane < m ? col0(lane) : 0.0);
+        const double p1 = wave_sum(64 + lane < m ? col0(64 + lane) : 0.0);
+        double xn2 = 0;
+        xn2 += p0;
+        xn2 += p1;
+        __threadfence_block();
+        if (k + 2 < r) reflector(k + 1, xn2);
+      } else {
+        update_rest();
+      }
+      __syncthreads();
+    } else {
+      // (c1) the first column by all threads, its norm from per-wave partials
+      {
+        double nx = 0;
+        for (int ii = tid; ii < m; ii += nt) nx += col0(ii);
+        nx = wave_sum(nx);
+        if (lane == 0) w.nred[wid] = nx;
+      }
+      __syncthreads();
+      // (c2) the rest, waves 1-15, while wave 0 forms the next reflector from
+      // the finished column
+      if (wid == 0) {
+        if (k + 2 < r) reflector(k + 1, nred_sum());
+      } else {
+        update_rest();
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (tid == 0) w.dd[r - 1] = M.lo(r - 1, r - 1).x;
   __syncthreads();
