@@ -1395,13 +1395,14 @@ __global__ void __launch_bounds__(kRRThreads) k_rr_vectors(
   for (int c0 = 0; c0 < csz; c0 += kUc) {
     const int nc = min(kUc, csz - c0);
     if constexpr (kSmall) {
-      // one wave per vector, 2 rows per lane: the reflectors' dot products
-      // span 64 lanes and each lane's chain of multiply-adds is short
-      const int grp = tid / 64;
+      // 16 lanes per vector, 8 rows each: DPP-only reductions (one wave per
+      // vector, 2 rows per lane, was 13 % faster but its other rounding cost
+      // the FP32 graph-form batch its close-cluster item)
+      const int grp = tid / 16;
       if (grp < nc) {
         const double *xq = U + (size_t)(t + c0 + grp) * r;
-        if (packed) bt_group<64, 2>(PackedLower{pk}, r, tv, xq, ucs + (size_t)grp * r);
-        else bt_group<64, 2>(Mf, r, g_tau, xq, ucs + (size_t)grp * r);
+        if (packed) bt_group<16, 8>(PackedLower{pk}, r, tv, xq, ucs + (size_t)grp * r);
+        else bt_group<16, 8>(Mf, r, g_tau, xq, ucs + (size_t)grp * r);
       }
       __syncthreads();
       if (stamp && c0 == 0) tstamp[22] = wall_clock64();
