@@ -284,8 +284,12 @@ void dks_default_opts(dks_solve_opts *o);
  * `sys`.  X: device complex128 block [n][4][N]; in: the start block X0, out: the
  * eigenvectors (unit 2-norm).  lambda: host array of n eigenvalues (ascending,
  * shifted by -c^2).  resnorms: optional host array of n final residual norms.
- * info: optional.  Synchronous on `stream`.  The library allocates its workspace
- * (about 13 blocks of n bands) on first use and keeps it for reuse.
+ * info: optional.  Synchronous on `stream`.  Inside the call the Gram product
+ * S = Z^H Z and its Cholesky run on a second stream of the library, ordered
+ * with `stream` by events, beside the application of H to the filtered block;
+ * every such operation has finished when the call returns.  The library
+ * allocates its workspace (about 13 blocks of n bands) on first use and keeps
+ * it for reuse.  Calls that overlap on one basis race.
  * Returns DKS_WNOTCONV if n_iter was reached, DKS_ECOLLAPSE if a Ritz value fell
  * below -c^2, DKS_ECHOL if the start block is numerically rank deficient. */
 dks_status dks_lobpcgf_solve(dks_basis *b, int sys, int n, void *X, double *lambda,
