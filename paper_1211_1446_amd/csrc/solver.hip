@@ -467,7 +467,10 @@ static void update(Ctx &x, Blocks<T> &bk, LoopState<T> &s, int n, const std::vec
               sv.norms.as<double>(), sv.part2, x.st);
   double *hres = sv.h_res.as<double>(n);
   DKS_HIP(hipMemcpyAsync(hres, sv.norms.p, sizeof(double) * n, hipMemcpyDeviceToHost, x.st));
-  DKS_HIP(hipStreamSynchronize(x.st));
+  // wait on an event of the copy (a spinning wait) rather than the stream
+  if (!sv.rr_ev) DKS_HIP(hipEventCreateWithFlags(&sv.rr_ev, hipEventDisableTiming));
+  DKS_HIP(hipEventRecord(sv.rr_ev, x.st));
+  DKS_HIP(hipEventSynchronize(sv.rr_ev));
   s.res.assign(hres, hres + n);
   for (auto &r : s.res) r = std::sqrt(std::max(r, 0.0));
   if (log_enabled()) {
